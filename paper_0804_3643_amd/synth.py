@@ -1,0 +1,298 @@
+"""Seeded synthetic protein banks standing in for the paper's PIR / SWISS-PROT banks.
+
+This module only generates inputs. It holds none of the search method's
+arithmetic (no seed keys, no scoring, no extension); both the CPU oracle and the
+GPU path consume what it produces.
+
+Storage format of a bank (the "padded layout")
+---------------------------------------------
+``codes`` is one ``uint8`` array: a run of ``PAD_LEN`` pad codes (value
+``PAD_CODE`` = 20), sequence 0, another pad run, sequence 1, ..., the last
+sequence and a final pad run.  Residues are coded 0..19 in the order
+``ALPHABET``.  ``seq_start`` is ``int64[n+1]``: ``seq_start[i]`` is the offset of
+the first residue of sequence ``i`` and ``seq_start[n] == len(codes)``, so the
+length of sequence ``i`` is ``seq_start[i+1] - seq_start[i] - PAD_LEN``.
+
+Workload recipe (the paper's banks, Annex 1, are not available)
+---------------------------------------------------------------
+* lengths: ``clamp(round(exp(mu + sigma*Z)), 50, 1000)`` with ``sigma = 0.6`` and
+  ``mu = ln 300 - sigma^2/2`` (unclamped mean 300);
+* residues: i.i.d. from the BLOSUM62 background composition;
+* planted homologs: a bank1 sequence is mutated (per position with probability
+  ``1 - identity``, the new residue ``b != a`` drawn with probability
+  proportional to ``f_b exp(lambda s_ab)``, the BLOSUM62 target frequencies),
+  with indels at rate 0.02 per position (half insertions of background
+  residues, half deletions, length ``min(Geom(1/2), 5)``), and the result
+  replaces a bank2 sequence;
+* low-complexity repeats (skewed configuration): 5% of the sequences of each
+  bank receive one run of length U[100, 400] (clamped to the sequence) drawn
+  uniformly from one of three small alphabets of 2, 3 and 4 letters; the pool is
+  drawn once per seed.
+
+Random streams: ``numpy.random.SeedSequence(651300 + cfg).spawn(6)`` gives the
+independent streams (lengths, residues, plant choice, mutation, indels,
+repeats).
+"""
+from __future__ import annotations
+
+import dataclasses
+import hashlib
+import math
+
+import numpy as np
+
+ALPHABET = "ACDEFGHIKLMNPQRSTVWY"
+PAD_CODE = 20
+PAD_LEN = 20
+
+# BLOSUM62 background amino-acid frequencies (Henikoff & Henikoff 1992), in
+# ALPHABET order.  Used here only to draw residues and homolog substitutions.
+_BG = {
+    "A": .074, "R": .052, "N": .045, "D": .054, "C": .025, "Q": .034, "E": .054,
+    "G": .074, "H": .026, "I": .068, "L": .099, "K": .058, "M": .025, "F": .047,
+    "P": .039, "S": .057, "T": .051, "W": .013, "Y": .032, "V": .073,
+}
+BACKGROUND = np.array([_BG[c] for c in ALPHABET], dtype=np.float64)
+
+# BLOSUM62 in the NCBI row order ARNDCQEGHILKMFPSTWYV; this generator's own copy,
+# used only to draw realistic substitutions in planted homologs.
+_B62_ORDER = "ARNDCQEGHILKMFPSTWYV"
+_B62_ROWS = """
+ 4 -1 -2 -2  0 -1 -1  0 -2 -1 -1 -1 -1 -2 -1  1  0 -3 -2  0
+-1  5  0 -2 -3  1  0 -2  0 -3 -2  2 -1 -3 -2 -1 -1 -3 -2 -3
+-2  0  6  1 -3  0  0  0  1 -3 -3  0 -2 -3 -2  1  0 -4 -2 -3
+-2 -2  1  6 -3  0  2 -1 -1 -3 -4 -1 -3 -3 -1  0 -1 -4 -3 -3
+ 0 -3 -3 -3  9 -3 -4 -3 -3 -1 -1 -3 -1 -2 -3 -1 -1 -2 -2 -1
+-1  1  0  0 -3  5  2 -2  0 -3 -2  1  0 -3 -1  0 -1 -2 -1 -2
+-1  0  0  2 -4  2  5 -2  0 -3 -3  1 -2 -3 -1  0 -1 -3 -2 -2
+ 0 -2  0 -1 -3 -2 -2  6 -2 -4 -4 -2 -3 -3 -2  0 -2 -2 -3 -3
+-2  0  1 -1 -3  0  0 -2  8 -3 -3 -1 -2 -1 -2 -1 -2 -2  2 -3
+-1 -3 -3 -3 -1 -3 -3 -4 -3  4  2 -3  1  0 -3 -2 -1 -3 -1  3
+-1 -2 -3 -4 -1 -2 -3 -4 -3  2  4 -2  2  0 -3 -2 -1 -2 -1  1
+-1  2  0 -1 -3  1  1 -2 -1 -3 -2  5 -1 -3 -1  0 -1 -3 -2 -2
+-1 -1 -2 -3 -1  0 -2 -3 -2  1  2 -1  5  0 -2 -1 -1 -1 -1  1
+-2 -3 -3 -3 -2 -3 -3 -3 -1  0  0 -3  0  6 -4 -2 -2  1  3 -1
+-1 -2 -2 -1 -3 -1 -1 -2 -2 -3 -3 -1 -2 -4  7 -1 -1 -4 -3 -2
+ 1 -1  1  0 -1  0  0  0 -1 -2 -2  0 -1 -2 -1  4  1 -3 -2 -2
+ 0 -1  0 -1 -1 -1 -1 -2 -2 -1 -1 -1 -1 -2 -1  1  5 -2 -2  0
+-3 -3 -4 -4 -2 -2 -3 -2 -2 -3 -2 -3 -1  1 -4 -3 -2 11  2 -3
+-2 -2 -2 -3 -2 -1 -2 -3  2 -1 -1 -2 -1  3 -3 -2 -2  2  7 -1
+ 0 -3 -3 -3 -1 -2 -2 -3 -3  3  1 -2  1 -1 -2 -2  0 -3 -1  4
+"""
+
+
+def _b62_in_alphabet_order() -> np.ndarray:
+    raw = np.array([[int(x) for x in r.split()] for r in _B62_ROWS.strip().splitlines()])
+    perm = [_B62_ORDER.index(c) for c in ALPHABET]
+    return raw[np.ix_(perm, perm)]
+
+
+def _substitution_probs() -> np.ndarray:
+    """Row-stochastic matrix P[a, b] (b != a) proportional to f_b exp(lam s_ab)."""
+    s = _b62_in_alphabet_order().astype(np.float64)
+    ff = np.outer(BACKGROUND, BACKGROUND)
+    lo, hi = 0.05, 2.0  # bisection on sum f_a f_b exp(lam s_ab) = 1
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if (ff * np.exp(mid * s)).sum() > 1.0:
+            hi = mid
+        else:
+            lo = mid
+    q = ff * np.exp(lo * s)
+    np.fill_diagonal(q, 0.0)
+    return q / q.sum(axis=1, keepdims=True)
+
+
+@dataclasses.dataclass
+class Bank:
+    codes: np.ndarray      # uint8, padded layout
+    seq_start: np.ndarray  # int64[n+1]
+
+    @property
+    def n_seqs(self) -> int:
+        return int(self.seq_start.shape[0] - 1)
+
+    @property
+    def lengths(self) -> np.ndarray:
+        return (np.diff(self.seq_start) - PAD_LEN).astype(np.int64)
+
+    @property
+    def n_residues(self) -> int:
+        return int(self.lengths.sum())
+
+    def seq(self, i: int) -> np.ndarray:
+        s = int(self.seq_start[i])
+        return self.codes[s:s + int(self.lengths[i])]
+
+    def sha256(self) -> str:
+        h = hashlib.sha256()
+        h.update(self.codes.tobytes())
+        h.update(self.seq_start.tobytes())
+        return h.hexdigest()
+
+    @staticmethod
+    def from_seqs(seqs) -> "Bank":
+        lens = np.array([len(s) for s in seqs], dtype=np.int64)
+        n = len(seqs)
+        seq_start = np.empty(n + 1, dtype=np.int64)
+        seq_start[0] = PAD_LEN
+        if n:
+            seq_start[1:] = PAD_LEN + np.cumsum(lens + PAD_LEN)
+        codes = np.full(int(seq_start[-1]), PAD_CODE, dtype=np.uint8)
+        for i, s in enumerate(seqs):
+            codes[seq_start[i]:seq_start[i] + lens[i]] = np.asarray(s, dtype=np.uint8)
+        return Bank(codes, seq_start)
+
+    @staticmethod
+    def from_strings(strs) -> "Bank":
+        return Bank.from_seqs([encode(s) for s in strs])
+
+
+def encode(s: str) -> np.ndarray:
+    lut = {c: i for i, c in enumerate(ALPHABET)}
+    return np.array([lut[c] for c in s.upper()], dtype=np.uint8)
+
+
+def decode(codes) -> str:
+    return "".join(ALPHABET[int(c)] for c in codes)
+
+
+@dataclasses.dataclass
+class Plant:
+    src: int            # bank1 sequence index
+    dst: int            # bank2 sequence index it replaced
+    target_identity: float
+    identity: float     # realised identity over aligned (non-indel) columns
+    colmap: np.ndarray  # int32, per homolog position: source position or -1 (insertion)
+
+
+@dataclasses.dataclass
+class Workload:
+    cfg: int
+    bank1: Bank
+    bank2: Bank
+    plants: list
+    description: str
+
+
+@dataclasses.dataclass(frozen=True)
+class ConfigSpec:
+    n1: int
+    n2: int
+    n_plants: int
+    identity: tuple          # (lo, hi); lo == hi means fixed
+    repeats: bool
+    description: str
+
+
+CONFIGS = {
+    0: ConfigSpec(200, 2_000, 20, (0.40, 0.40), False,
+                  "PLAST-P tiny: 200 x 2,000 proteins, 20 planted homologs at 40% identity"),
+    1: ConfigSpec(10_000, 100_000, 500, (0.30, 0.60), False,
+                  "PLAST-P: 10,000 x 100,000 proteins, 500 planted homologs at 30-60% identity"),
+    2: ConfigSpec(20_000, 300_000, 0, (0.40, 0.40), True,
+                  "PLAST-P skewed: 20,000 x 300,000 proteins, 5% carry 2-4-letter repeats"),
+}
+
+_SIGMA = 0.6
+_MU = math.log(300.0) - _SIGMA ** 2 / 2
+INDEL_RATE = 0.02
+
+
+def _lengths(rng, n):
+    z = rng.standard_normal(n)
+    return np.clip(np.rint(np.exp(_MU + _SIGMA * z)), 50, 1000).astype(np.int64)
+
+
+def _mutate(src: np.ndarray, identity: float, rng_mut, rng_indel, subst):
+    out, colmap = [], []
+    n = len(src)
+    mutate = rng_mut.random(n) >= identity
+    u = rng_mut.random(n)
+    cum = np.cumsum(subst, axis=1)
+    indel_at = rng_indel.random(n) < INDEL_RATE
+    p = 0
+    while p < n:
+        if indel_at[p]:
+            length = min(int(rng_indel.geometric(0.5)), 5)
+            if rng_indel.random() < 0.5:  # insertion before position p
+                ins = rng_indel.choice(20, size=length, p=BACKGROUND)
+                out.extend(int(x) for x in ins)
+                colmap.extend([-1] * length)
+                indel_at[p] = False        # then emit position p normally
+                continue
+            p += length                    # deletion of `length` source positions
+            continue
+        a = int(src[p])
+        if mutate[p]:
+            b = int(min(np.searchsorted(cum[a], u[p] * cum[a, -1], side="right"), 19))
+            if b == a:  # guard against rounding at the cumulative edge
+                b = (a + 1) % 20
+            out.append(b)
+        else:
+            out.append(a)
+        colmap.append(p)
+        p += 1
+    out = np.array(out, dtype=np.uint8)
+    colmap = np.array(colmap, dtype=np.int32)
+    aligned = colmap >= 0
+    ident = float(np.mean(out[aligned] == src[colmap[aligned]])) if aligned.any() else 0.0
+    return out, colmap, ident
+
+
+def _add_repeats(seqs, rng, pool):
+    n = len(seqs)
+    chosen = rng.choice(n, size=max(1, int(round(0.05 * n))), replace=False)
+    for i in np.sort(chosen):
+        s = seqs[i]
+        L = min(int(rng.integers(100, 401)), len(s))
+        off = int(rng.integers(0, len(s) - L + 1))
+        alpha = pool[int(rng.integers(0, len(pool)))]
+        s[off:off + L] = rng.choice(alpha, size=L)
+    return chosen
+
+
+def _split(flat, lens):
+    offs = np.concatenate([[0], np.cumsum(lens)])
+    return [flat[offs[i]:offs[i + 1]].copy() for i in range(len(lens))]
+
+
+def make_workload(cfg: int, plants: bool = True, scale: float = 1.0) -> Workload:
+    """Build configuration ``cfg`` deterministically.
+
+    ``plants=False`` skips homolog planting (used to calibrate thresholds on
+    purely random banks).  ``scale`` shrinks both banks proportionally (for
+    quick tests); the random streams are the same.
+    """
+    spec = CONFIGS[cfg]
+    n1 = max(1, int(round(spec.n1 * scale)))
+    n2 = max(1, int(round(spec.n2 * scale)))
+    ss = np.random.SeedSequence(651300 + cfg).spawn(6)
+    r_len, r_res, r_plant, r_mut, r_indel, r_rep = [np.random.Generator(np.random.PCG64(s)) for s in ss]
+    lens = _lengths(r_len, n1 + n2)
+    flat = r_res.choice(20, size=int(lens.sum()), p=BACKGROUND).astype(np.uint8)
+    seqs = _split(flat, lens)
+    s1, s2 = seqs[:n1], seqs[n1:]
+    if spec.repeats:
+        pool = [r_rep.choice(20, size=k, replace=False) for k in (2, 3, 4)]
+        _add_repeats(s1, r_rep, pool)
+        _add_repeats(s2, r_rep, pool)
+    planted = []
+    n_pl = min(spec.n_plants, n1, n2) if plants else 0
+    if n_pl:
+        subst = _substitution_probs()
+        src = r_plant.choice(n1, size=n_pl, replace=False)
+        dst = r_plant.choice(n2, size=n_pl, replace=False)
+        lo, hi = spec.identity
+        ids = np.full(n_pl, lo) if lo == hi else r_plant.uniform(lo, hi, size=n_pl)
+        for k in range(n_pl):
+            hom, colmap, ident = _mutate(s1[src[k]], float(ids[k]), r_mut, r_indel, subst)
+            s2[dst[k]] = hom
+            planted.append(Plant(int(src[k]), int(dst[k]), float(ids[k]), ident, colmap))
+    return Workload(cfg, Bank.from_seqs(s1), Bank.from_seqs(s2), planted, spec.description)
+
+
+def random_bank(rng, n, lo=1, hi=60, alphabet_size=20) -> Bank:
+    """Small random bank for tests: ``n`` sequences of length U[lo, hi]."""
+    lens = rng.integers(lo, hi + 1, size=n)
+    return Bank.from_seqs([rng.integers(0, alphabet_size, size=int(L)).astype(np.uint8) for L in lens])

@@ -1,0 +1,374 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself:
+published constants, the paper's worked examples, closed forms, brute-force
+enumeration on tiny inputs, symmetry and planted ground truth."""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import coracle as C
+from oracle import plast_oracle as O
+from paper_0804_3643_amd import params, synth
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _golden_lines(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return [l.split() for l in f if l.strip() and not l.startswith("#")]
+
+
+# ----------------------------------------------------------------------------- BLOSUM62
+
+def test_blosum62_shape_and_published_facts():
+    M = O.BLOSUM62
+    A = O.ALPHABET
+    assert M.shape == (20, 20)
+    assert (M == M.T).all()
+    g = {l[0]: l[1:] for l in _golden_lines("blosum62_karlin_altschul.txt") if l[0] != "robinson"}
+    assert M.max() == int(g["max_entry"][2]) == M[A.index("W"), A.index("W")]
+    assert M[A.index("C"), A.index("C")] == int(g["entry"][2])
+    assert M.min() == int(g["min_entry"][0])
+    assert np.diag(M).min() >= 4  # identical letters always score positively
+
+
+def test_blosum62_karlin_altschul_lambda_and_entropy():
+    """Solving sum p_a p_b exp(lambda s_ab) = 1 with the Robinson frequencies must
+    give the published ungapped lambda and H; one wrong cell moves them."""
+    rows = _golden_lines("blosum62_karlin_altschul.txt")
+    rob = {l[1]: float(l[2]) for l in rows if l[0] == "robinson"}
+    p = np.array([rob[c] for c in O.ALPHABET])
+    p /= p.sum()
+    pp = np.outer(p, p)
+    M = O.BLOSUM62.astype(np.float64)
+    assert (pp * M).sum() < 0  # negative expected score, required for local statistics
+    lo, hi = 0.01, 2.0
+    for _ in range(100):
+        mid = (lo + hi) / 2
+        if (pp * np.exp(mid * M)).sum() > 1:
+            hi = mid
+        else:
+            lo = mid
+    lam = lo
+    H = lam * (pp * M * np.exp(lam * M)).sum()
+    g = {l[0]: float(l[1]) for l in rows if l[0] in ("lambda", "H")}
+    assert abs(lam - g["lambda"]) < 6e-5
+    assert abs(H - g["H"]) < 6e-5
+
+
+def test_blosum62_matches_generator_transcription():
+    """Two transcriptions typed in different layouts (lower triangle in code
+    order here, full NCBI-order rows in the generator) agree cell by cell."""
+    assert (synth._b62_in_alphabet_order() == O.BLOSUM62).all()
+
+
+# ----------------------------------------------------------------------------- seed key
+
+def _key(word):
+    c = synth.encode(word)
+    return int(O.seed_key(c[0], c[1], c[2], c[3]))
+
+
+def test_seed_key_paper_examples():
+    for line in _golden_lines("seed_examples.txt"):
+        keys = [_key(w) for w in line[1:]]
+        if line[0] == "same":
+            assert len(set(keys)) == 1, line
+        else:
+            assert len(set(keys)) == len(keys), line
+
+
+def test_seed_key_image_is_8800_and_partitions():
+    w = np.array(list(itertools.product(range(20), repeat=4)))
+    k = O.seed_key(w[:, 0], w[:, 1], w[:, 2], w[:, 3])
+    assert k.min() == 0 and k.max() == O.NKEYS - 1
+    assert len(np.unique(k)) == 8800
+    # class tables partition the alphabet
+    assert sorted("".join(O.SEED_POS2)) == sorted(O.ALPHABET)
+    assert sorted("".join(O.SEED_POS3)) == sorted(O.ALPHABET)
+    assert len(O.SEED_POS2) == 2 and len(O.SEED_POS3) == 11
+    # equal keys <=> equal letters at 1 and 4 and equal classes at 2 and 3
+    rng = np.random.default_rng(1)
+    a = w[rng.integers(0, len(w), 20000)]
+    b = w[rng.integers(0, len(w), 20000)]
+    b[:5000, 0], b[:5000, 3] = a[:5000, 0], a[:5000, 3]
+    ka = O.seed_key(a[:, 0], a[:, 1], a[:, 2], a[:, 3])
+    kb = O.seed_key(b[:, 0], b[:, 1], b[:, 2], b[:, 3])
+
+    def cls(letter, table):
+        return next(i for i, s in enumerate(table) if O.ALPHABET[letter] in s)
+    same = np.array([x[0] == y[0] and x[3] == y[3] and cls(x[1], O.SEED_POS2) == cls(y[1], O.SEED_POS2)
+                     and cls(x[2], O.SEED_POS3) == cls(y[2], O.SEED_POS3) for x, y in zip(a, b)])
+    assert ((ka == kb) == same).all()
+    assert same.sum() > 100
+
+
+# ----------------------------------------------------------------------------- index
+
+def _tiny_banks(seed, n1=4, n2=5, lo=0, hi=40, alpha=20):
+    rng = np.random.default_rng(seed)
+    return synth.random_bank(rng, n1, lo, hi, alpha), synth.random_bank(rng, n2, lo, hi, alpha)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_index_csr_invariants_and_brute_force(seed):
+    b1, _ = _tiny_banks(seed, n1=30, lo=0, hi=60, alpha=4 if seed % 2 else 20)
+    key_off, occ_seq, occ_pos = O.build_index(b1)
+    seqs = O.sequences(b1)
+    n_words = sum(max(0, len(s) - 3) for s in seqs)
+    assert key_off[0] == 0 and key_off[-1] == n_words and (np.diff(key_off) >= 0).all()
+    # brute force: dictionary of key -> sorted (seq, pos)
+    ref = {}
+    for s, a in enumerate(seqs):
+        for p in range(len(a) - 3):
+            ref.setdefault(_key(synth.decode(a[p:p + 4])), []).append((s, p))
+    for k in range(O.NKEYS):
+        got = list(zip(occ_seq[key_off[k]:key_off[k + 1]].tolist(), occ_pos[key_off[k]:key_off[k + 1]].tolist()))
+        assert got == sorted(ref.get(k, []))
+    # the C oracle builds the same CSR
+    ck = C.build_index(b1)
+    assert all((x == y).all() for x, y in zip(ck, (key_off, occ_seq, occ_pos)))
+
+
+def test_n_extensions_equals_pair_count():
+    b1, b2 = _tiny_banks(11, n1=6, n2=7, alpha=3)
+    i1, i2 = O.build_index(b1), O.build_index(b2)
+    A, B = O.sequences(b1), O.sequences(b2)
+    brute = 0
+    for a in A:
+        for p1 in range(len(a) - 3):
+            for b in B:
+                for p2 in range(len(b) - 3):
+                    brute += _key(synth.decode(a[p1:p1 + 4])) == _key(synth.decode(b[p2:p2 + 4]))
+    assert O.n_extensions(i1, i2) == brute > 0
+
+
+# ----------------------------------------------------------------------------- ungapped score
+
+def _segment_max(a, p1, b, p2, nbr=O.NBR, right=O.RIGHT):
+    """Closed form: best sum over diagonal segments [p-l, p+r) touching the seed
+    start, 0 <= l <= min(nbr, p1, p2), 0 <= r <= min(right, remaining)."""
+    lmax = min(nbr, p1, p2)
+    rmax = min(right, len(a) - p1, len(b) - p2)
+    best = None
+    for l in range(lmax + 1):
+        for r in range(rmax + 1):
+            s = sum(int(O.BLOSUM62[a[p1 + t], b[p2 + t]]) for t in range(-l, r))
+            best = s if best is None else max(best, s)
+    return best
+
+
+def test_score_equals_segment_enumeration():
+    rng = np.random.default_rng(7)
+    for _ in range(300):
+        la, lb = rng.integers(4, 60, size=2)
+        a = rng.integers(0, 20, la)
+        b = rng.integers(0, 20, lb)
+        p1, p2 = int(rng.integers(0, la - 3)), int(rng.integers(0, lb - 3))
+        assert O.ungapped_score(a, p1, b, p2) == _segment_max(a, p1, b, p2)
+
+
+def test_score_self_hit_closed_form():
+    """Same sequence, same position: every term is a diagonal entry (>= 4), so the
+    score is the sum of M[x, x] over the whole clipped window."""
+    rng = np.random.default_rng(3)
+    for _ in range(200):
+        L = int(rng.integers(4, 80))
+        a = rng.integers(0, 20, L)
+        p = int(rng.integers(0, L - 3))
+        lo, hi = max(0, p - 20), min(L, p + 24)
+        assert O.ungapped_score(a, p, a, p) == int(np.diag(O.BLOSUM62)[a[lo:hi]].sum())
+
+
+def test_poly_a_closed_form():
+    """Poly-A versus poly-A: every pair is a candidate and scores
+    4 * (min(20, p1, p2) + min(24, |a| - p1, |b| - p2))."""
+    A4 = int(O.BLOSUM62[0, 0])
+    assert A4 == 4
+    bank1 = synth.Bank.from_strings(["A" * 30, "A" * 7])
+    bank2 = synth.Bank.from_strings(["A" * 45, "A" * 4, "A" * 26])
+    hits = O.ungapped_hits(bank1, bank2, 0)
+    exp = []
+    for s1, a in enumerate(O.sequences(bank1)):
+        for p1 in range(len(a) - 3):
+            for s2, b in enumerate(O.sequences(bank2)):
+                for p2 in range(len(b) - 3):
+                    exp.append((s1, p1, s2, p2, 4 * (min(20, p1, p2) + min(24, len(a) - p1, len(b) - p2))))
+    assert np.array_equal(hits, O.canonical(np.array(exp)))
+
+
+def _brute_force_hits(bank1, bank2, s1):
+    out = []
+    A, B = O.sequences(bank1), O.sequences(bank2)
+    for i, a in enumerate(A):
+        for p1 in range(len(a) - 3):
+            ka = _key(synth.decode(a[p1:p1 + 4]))
+            for j, b in enumerate(B):
+                for p2 in range(len(b) - 3):
+                    if ka != _key(synth.decode(b[p2:p2 + 4])):
+                        continue
+                    sc = _segment_max(a, p1, b, p2)
+                    if sc >= s1:
+                        out.append((i, p1, j, p2, sc))
+    return O.canonical(np.array(out, dtype=np.int64).reshape(-1, 5))
+
+
+@pytest.mark.parametrize("seed,s1", [(0, 15), (1, 25), (2, 4), (3, 38)])
+def test_hit_list_equals_all_diagonal_brute_force(seed, s1):
+    b1, b2 = _tiny_banks(100 + seed, n1=3, n2=4, lo=0, hi=45, alpha=5)
+    ref = _brute_force_hits(b1, b2, s1)
+    assert np.array_equal(O.ungapped_hits(b1, b2, s1), ref)
+    assert np.array_equal(C.ungapped_hits(b1, b2, s1, nthreads=3)[0], ref)
+    if s1 <= 4:
+        assert len(ref) == O.n_extensions(O.build_index(b1), O.build_index(b2)) > 0
+
+
+def test_threshold_at_most_4_keeps_every_candidate(cfg0_random):
+    """The score is >= 4 (first seed letters are identical), so S1 <= 4 makes the
+    hit list exactly the candidate-pair list."""
+    w = cfg0_random
+    h, n_ext = C.ungapped_hits(w.bank1, w.bank2, 4)
+    assert len(h) == n_ext
+    assert h[:, 4].min() >= 4
+
+
+def test_swap_symmetry(cfg0):
+    h12, _ = C.ungapped_hits(cfg0.bank1, cfg0.bank2, params.S1)
+    h21, _ = C.ungapped_hits(cfg0.bank2, cfg0.bank1, params.S1)
+    assert np.array_equal(h12, O.canonical(h21[:, [2, 3, 0, 1, 4]]))
+
+
+def test_numpy_and_c_oracles_agree_on_config0(cfg0):
+    hp = O.ungapped_hits(cfg0.bank1, cfg0.bank2, params.S1)
+    hc, n_ext = C.ungapped_hits(cfg0.bank1, cfg0.bank2, params.S1)
+    assert np.array_equal(hp, hc)
+    assert n_ext == O.n_extensions(O.build_index(cfg0.bank1), O.build_index(cfg0.bank2))
+    # scalar definition on a sample of rows
+    A, B = O.sequences(cfg0.bank1), O.sequences(cfg0.bank2)
+    for r in hp[:: max(1, len(hp) // 200)]:
+        assert O.ungapped_score(A[r[0]], int(r[1]), B[r[2]], int(r[3])) == r[4]
+
+
+def test_planted_homologs_are_recovered(cfg0):
+    h, _ = C.ungapped_hits(cfg0.bank1, cfg0.bank2, params.S1)
+    found = {(int(a), int(b)) for a, b in h[:, [0, 2]]}
+    rec = np.mean([(p.src, p.dst) in found for p in cfg0.plants])
+    assert rec >= 0.95
+
+
+def test_selectivity_near_paper(cfg0_random):
+    """Soft target: about 0.19% of candidate pairs pass on random banks."""
+    h, n_ext = C.ungapped_hits(cfg0_random.bank1, cfg0_random.bank2, params.S1)
+    assert 0.0010 < len(h) / n_ext <= 0.00186
+
+
+def test_thresholds_match_calibration_record():
+    with open(os.path.join(GOLDEN, "thresholds.json")) as f:
+        rec = json.load(f)
+    assert rec["s1"] == params.S1 and rec["s2"] == params.S2
+
+
+@pytest.mark.slow
+def test_thresholds_recalibrate():
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("cal", os.path.join(GOLDEN, "calibrate_thresholds.py"))
+    cal = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(cal)
+    res = cal.calibrate()
+    assert (res["s1"], res["s2"]) == (params.S1, params.S2)
+
+
+# ----------------------------------------------------------------------------- gapped filter
+
+def _brute_gapped(x, y, band, go, ge):
+    """Enumerate every monotone path from (0, 0) inside the band; score is the
+    sum of substitutions minus (go + k*ge) per maximal run of k same-direction
+    gap moves; the best over all paths (all path prefixes are paths) and 0."""
+    best = 0
+    stack = [(0, 0, 0, None)]  # i, j, score, last move
+    while stack:
+        i, j, s, last = stack.pop()
+        best = max(best, s)
+        for mv, di, dj in (("M", 1, 1), ("X", 1, 0), ("Y", 0, 1)):
+            ni, nj = i + di, j + dj
+            if ni > len(x) or nj > len(y) or abs(ni - nj) > band:
+                continue
+            if mv == "M":
+                ns = s + int(O.BLOSUM62[x[i], y[j]])
+            else:
+                ns = s - ge - (0 if last == mv else go)
+            stack.append((ni, nj, ns, mv))
+    return best
+
+
+def test_gapped_side_equals_path_enumeration():
+    rng = np.random.default_rng(5)
+    for case in range(150):
+        lx, ly = int(rng.integers(0, 6)), int(rng.integers(0, 6))
+        x = rng.integers(0, 20 if case % 3 else 3, lx)
+        y = rng.integers(0, 20 if case % 3 else 3, ly)
+        band = int(rng.integers(0, 4))
+        go, ge = [(11, 1), (1, 1), (0, 2), (3, 0)][case % 4]
+        assert O.gapped_side(x, y, band, go, ge) == _brute_gapped(x, y, band, go, ge), (x, y, band, go, ge)
+
+
+def test_gapped_no_gaps_reduces_to_ungapped_prefix():
+    rng = np.random.default_rng(6)
+    for _ in range(100):
+        x = rng.integers(0, 20, int(rng.integers(0, 30)))
+        y = rng.integers(0, 20, int(rng.integers(0, 30)))
+        n = min(len(x), len(y))
+        pref = np.concatenate([[0], np.cumsum(O.BLOSUM62[x[:n], y[:n]])])
+        assert O.gapped_side(x, y, 16, None, 1) == int(pref.max())
+
+
+def test_gapped_poly_a_and_swap_symmetry():
+    for lx in range(0, 12):
+        for ly in range(0, 12):
+            x = np.zeros(lx, dtype=np.int64)
+            y = np.zeros(ly, dtype=np.int64)
+            assert O.gapped_side(x, y, 16, 11, 1) == 4 * min(lx, ly)
+    rng = np.random.default_rng(9)
+    for _ in range(50):
+        x = rng.integers(0, 20, int(rng.integers(0, 40)))
+        y = rng.integers(0, 20, int(rng.integers(0, 40)))
+        assert O.gapped_side(x, y, 5, 11, 1) == O.gapped_side(y, x, 5, 11, 1)
+
+
+def test_gapped_vectorised_and_c_match_scalar(cfg0):
+    h, _ = C.ungapped_hits(cfg0.bank1, cfg0.bank2, params.S1)
+    sample = h[:: max(1, len(h) // 60)]
+    A, B = O.sequences(cfg0.bank1), O.sequences(cfg0.bank2)
+    scal = np.array([O.gapped_score(A[r[0]], int(r[1]), B[r[2]], int(r[3])) for r in sample])
+    assert np.array_equal(O.gapped_scores(cfg0.bank1, cfg0.bank2, sample), scal)
+    assert np.array_equal(C.gapped_scores(cfg0.bank1, cfg0.bank2, sample), scal)
+    # an ungapped hit's gapped score is at least its best one-sided diagonal prefix
+    assert (scal >= 0).all()
+
+
+def test_gapped_dominates_ungapped_on_same_windows(cfg0):
+    """With windows covering the ungapped ones, the gapped score can only be
+    larger: the ungapped segment is one of the allowed alignments."""
+    h, _ = C.ungapped_hits(cfg0.bank1, cfg0.bank2, params.S1)
+    g = C.gapped_scores(cfg0.bank1, cfg0.bank2, h)
+    assert (g >= h[:, 4]).all()
+
+
+# ----------------------------------------------------------------------------- generator
+
+def test_generator_deterministic_and_identity():
+    w1 = synth.make_workload(0)
+    w2 = synth.make_workload(0)
+    assert w1.bank1.sha256() == w2.bank1.sha256() and w1.bank2.sha256() == w2.bank2.sha256()
+    ids = np.array([p.identity for p in w1.plants])
+    tgt = np.array([p.target_identity for p in w1.plants])
+    assert abs((ids - tgt).mean()) < 0.03
+    for p in w1.plants:
+        n = (p.colmap >= 0).sum()
+        sd = np.sqrt(p.target_identity * (1 - p.target_identity) / n)
+        assert abs(p.identity - p.target_identity) < 5 * sd + 1e-9
+    L = np.concatenate([w1.bank1.lengths, w1.bank2.lengths])
+    assert 50 <= L.min() and L.max() <= 1000 + 5 * 10  # homologs may grow by insertions
+    assert 270 < L.mean() < 320
