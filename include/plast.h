@@ -1,0 +1,175 @@
+/*
+ * plast.h -- C ABI of the MI355X (gfx950) PLAST-P bank-versus-bank hot path.
+ *
+ * Method: Nguyen & Lavenier, "Fine-grained parallelization of similarity search
+ * between protein sequences", INRIA RR-6513 (2008).  Two protein banks are
+ * indexed by a 4-letter subset seed (Sec. 3.3.1); for every seed key, every pair
+ * of an occurrence in bank 1 and an occurrence in bank 2 gets a one-hit ungapped
+ * extension on bounded neighbourhoods (Sec. 3.2, Sec. 3.3.3; score composition
+ * of the GPU kernel in Annex 4) and survivors go through a small banded gapped
+ * filter (Sec. 3.3.4 stage 3.1, Sec. 5.2.2).
+ *
+ * Conventions shared by every entry point
+ *   - Device pointers ("d_") are HIP device memory owned by the caller; the
+ *     library never allocates, frees or retains device memory.  Host pointers
+ *     ("h_") are ordinary host memory.
+ *   - Every call returns a status (PLAST_OK or a negative PLAST_E_* code);
+ *     nothing throws or aborts across the ABI.  plast_strerror() maps a code to
+ *     a static string, plast_last_error() returns a thread-local detail message
+ *     for the last failing call on the calling thread.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Calls that return
+ *     counts to the host synchronise that stream before returning; the others
+ *     only enqueue work.
+ *   - Residue codes are 0..19 in the order ACDEFGHIKLMNPQRSTVWY.
+ */
+#ifndef PLAST_H
+#define PLAST_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PLAST_NKEYS 8800   /* 20 x 2 x 11 x 20 subset-seed keys (Sec. 3.3.1) */
+#define PLAST_SEED_LEN 4
+#define PLAST_PAD_CODE 20  /* code of the separator between sequences */
+#define PLAST_PAD_LEN 20   /* separator run length of the padded bank layout */
+#define PLAST_NBR 20       /* neighbourhood letters scanned beyond each seed end */
+
+enum {
+  PLAST_OK = 0,
+  PLAST_E_ARG = -1,        /* null pointer, negative size, unsupported parameter */
+  PLAST_E_ALPHABET = -2,   /* a residue code > 19, or a separator that is not 20 */
+  PLAST_E_CAPACITY = -3,   /* hit buffer too small; required size reported */
+  PLAST_E_WORKSPACE = -4,  /* workspace / index buffer smaller than the query said */
+  PLAST_E_HIP = -5,        /* a HIP runtime call failed (detail in plast_last_error) */
+  PLAST_E_LAYOUT = -6      /* seq_start is not a valid padded layout */
+};
+
+enum { PLAST_PLAIN = 0, PLAST_BATCHED = 1 };
+
+/* One ungapped hit: sequence ids (0-based) and the 0-based position of the first
+ * seed letter in each sequence, plus the exact integer score (20 bytes). */
+typedef struct {
+  int32_t seq1, pos1, seq2, pos2, score;
+} plast_hit_t;
+
+/* Read-only view of a built index (filled by plast_build_index).  All pointers
+ * are device pointers into caller memory: the bank passed in and the index
+ * buffer.  The view borrows them; it does not own anything. */
+typedef struct {
+  const uint8_t* codes;      /* the bank, padded layout, n_padded bytes */
+  const int64_t* seq_start;  /* n_seqs + 1 offsets */
+  int32_t n_seqs;
+  int64_t n_padded;
+  const int64_t* key_off;    /* PLAST_NKEYS + 1: occurrences of key k are [key_off[k], key_off[k+1]) */
+  const int32_t* occ;        /* n_words: offset in codes of the first seed letter */
+  const int32_t* occ_seq;    /* n_words: sequence id of that occurrence */
+  const uint8_t* scan_codes; /* internal copy of codes scaled for table addressing, with tail slack */
+  int64_t n_words;           /* host copy of key_off[PLAST_NKEYS] */
+} plast_index_t;
+
+typedef struct {
+  int32_t nbr;             /* must be PLAST_NBR (20) */
+  int32_t s1;              /* a pair is a hit iff score >= s1 */
+  const int8_t* matrix;    /* host, 20x20 row-major in code order; NULL = BLOSUM62 */
+} plast_ungapped_params_t;
+
+typedef struct {
+  int32_t window;          /* letters per side, 1..64 (64 in the reference configuration) */
+  int32_t band;            /* cells (i, j) with |i - j| <= band, 0..16 */
+  int32_t gap_open;        /* a gap of length k costs gap_open + k * gap_extend */
+  int32_t gap_extend;
+  int32_t s2;              /* pass iff gapped score >= s2 */
+  const int8_t* matrix;    /* host, 20x20 row-major in code order; NULL = BLOSUM62 */
+} plast_gapped_params_t;
+
+/*
+ * Sizes for plast_build_index.
+ * n_padded: length of the padded bank; n_seqs: number of sequences.
+ * *index_bytes receives the size of the index buffer (it holds key_off, occ,
+ * occ_seq and scan_codes and must outlive every view built into it);
+ * *ws_bytes the size of the scratch workspace used only during the build.
+ */
+int plast_index_bytes(int64_t n_padded, int32_t n_seqs, size_t* index_bytes, size_t* ws_bytes);
+
+/*
+ * Stage 0, bank indexing (Sec. 3.3.1): the subset-seed key of every 4-letter
+ * word that lies inside one sequence, then a stable counting sort by key, so
+ * that inside a key occurrences are ascending by (sequence, position).
+ *
+ * Padded layout of the bank (d_codes, n_padded bytes; d_seq_start, n_seqs + 1
+ * int64): a run of PLAST_PAD_LEN codes PLAST_PAD_CODE, sequence 0, a run, ...,
+ * the last sequence, a final run.  d_seq_start[i] is the offset of the first
+ * residue of sequence i, d_seq_start[n_seqs] == n_padded; sequence i has length
+ * d_seq_start[i+1] - d_seq_start[i] - PLAST_PAD_LEN (0 allowed).  n_padded must
+ * be < 2^31 - 64.
+ * Errors: PLAST_E_ARG (null pointer, bad sizes), PLAST_E_WORKSPACE (buffers
+ * smaller than plast_index_bytes), PLAST_E_LAYOUT (seq_start inconsistent),
+ * PLAST_E_ALPHABET (residue code > 19 or separator code != 20),
+ * PLAST_E_HIP.  Synchronises `stream` (to validate and to report n_words).
+ * On success *out is a view into d_codes, d_seq_start and d_index.
+ */
+int plast_build_index(const uint8_t* d_codes, const int64_t* d_seq_start, int32_t n_seqs, int64_t n_padded,
+                      void* d_index, size_t index_bytes, void* d_ws, size_t ws_bytes, plast_index_t* out,
+                      void* stream);
+
+/*
+ * Workspace size for plast_ungapped_extend in `mode` (PLAST_PLAIN or
+ * PLAST_BATCHED) for these two indexes.  Reads both key tables back to the host
+ * (synchronises `stream`).  *n_ext (may be NULL) receives the number of
+ * candidate pairs, sum over keys of n1(k) * n2(k).
+ */
+int plast_ungapped_workspace_bytes(const plast_index_t* a, const plast_index_t* b, int32_t mode, size_t* bytes,
+                                   int64_t* n_ext, void* stream);
+
+/*
+ * Stage 2, ungapped extension (Sec. 3.2 generic algorithm, Sec. 3.3.3) with hit
+ * compaction.  For every key and every pair (i in bank a, j in bank b) of its
+ * occurrences the score is best-right + best-left: the best prefix sum (0
+ * included) of substitution scores scanning rightward from the first seed
+ * letters over at most PLAST_SEED_LEN + nbr letters, plus the best prefix sum
+ * scanning leftward from the letters before them over at most nbr letters;
+ * both scans stop at sequence ends.  Pairs with score >= s1 are written to
+ * d_hits in unspecified order.
+ *
+ * mode PLAST_PLAIN launches one grid per key with candidate pairs, in key order;
+ * PLAST_BATCHED builds a device work list and runs one persistent work-queue
+ * kernel.  Both produce the same set of hits.
+ * d_ws/ws_bytes: scratch of at least plast_ungapped_workspace_bytes.
+ * d_hits/capacity: output array of `capacity` records.
+ * *h_n_hits always receives the number of hits (even when it exceeds capacity);
+ * *h_n_ext (may be NULL) the number of pairs scored.
+ * Errors: PLAST_E_ARG, PLAST_E_WORKSPACE, PLAST_E_HIP; PLAST_E_CAPACITY when
+ * *h_n_hits > capacity (d_hits then holds an unspecified subset; call again
+ * with a larger buffer).  Synchronises `stream`.
+ */
+int plast_ungapped_extend(const plast_index_t* a, const plast_index_t* b, const plast_ungapped_params_t* p,
+                          int32_t mode, void* d_ws, size_t ws_bytes, plast_hit_t* d_hits, int64_t capacity,
+                          int64_t* h_n_hits, int64_t* h_n_ext, void* stream);
+
+/*
+ * Stage 3.1, small gapped filter (Sec. 3.3.4; Sec. 5.2.2: one extension on each
+ * side of the seed).  For every hit, an anchored banded affine-gap alignment of
+ * a[pos1 ..) against b[pos2 ..) and another of a[pos1-1], a[pos1-2], ...
+ * against b[pos2-1], b[pos2-2], ..., each over at most `window` letters per
+ * sequence and clipped at sequence ends; cells (i, j) exist iff |i - j| <= band;
+ * each side's score is max(0, best cell).  d_gscore[h] = right + left,
+ * d_pass[h] = (d_gscore[h] >= s2).  Hits are read from d_hits[0 .. n_hits).
+ * A record whose sequence ids or positions lie outside the banks gets
+ * d_gscore = -1 and d_pass = 0 (nothing is read for it).
+ * Errors: PLAST_E_ARG (bad parameters), PLAST_E_HIP.  Enqueues only; does not
+ * synchronise.
+ */
+int plast_gapped_filter(const plast_index_t* a, const plast_index_t* b, const plast_hit_t* d_hits, int64_t n_hits,
+                        const plast_gapped_params_t* g, int32_t* d_gscore, uint8_t* d_pass, void* stream);
+
+const char* plast_strerror(int code);
+const char* plast_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PLAST_H */

@@ -1,0 +1,246 @@
+"""Thin ctypes binding of ``libplast_hip.so`` (C ABI in ``include/plast.h``).
+
+Argument marshalling only: device memory comes from torch tensors, the stream is
+torch's current stream, and every step of the search runs in the HIP library.
+Importing this module fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libplast_hip.so")
+
+NKEYS = 8800
+PAD_CODE = 20
+PAD_LEN = 20
+NBR = 20
+PLAIN, BATCHED = 0, 1
+MODES = {"plain": PLAIN, "batched": BATCHED}
+
+OK, E_ARG, E_ALPHABET, E_CAPACITY, E_WORKSPACE, E_HIP, E_LAYOUT = 0, -1, -2, -3, -4, -5, -6
+
+EXPORTS = ("plast_index_bytes", "plast_build_index", "plast_ungapped_workspace_bytes", "plast_ungapped_extend",
+           "plast_gapped_filter", "plast_strerror", "plast_last_error")
+
+
+class PlastError(RuntimeError):
+    def __init__(self, code, where, detail):
+        super().__init__("%s failed: %s (%d)%s" % (where, _strerror(code), code, (": " + detail) if detail else ""))
+        self.code = code
+
+
+class IndexView(ctypes.Structure):
+    _fields_ = [("codes", ctypes.c_void_p), ("seq_start", ctypes.c_void_p), ("n_seqs", ctypes.c_int32),
+                ("n_padded", ctypes.c_int64), ("key_off", ctypes.c_void_p), ("occ", ctypes.c_void_p),
+                ("occ_seq", ctypes.c_void_p), ("scan_codes", ctypes.c_void_p), ("n_words", ctypes.c_int64)]
+
+
+class UngappedParams(ctypes.Structure):
+    _fields_ = [("nbr", ctypes.c_int32), ("s1", ctypes.c_int32), ("matrix", ctypes.c_void_p)]
+
+
+class GappedParams(ctypes.Structure):
+    _fields_ = [("window", ctypes.c_int32), ("band", ctypes.c_int32), ("gap_open", ctypes.c_int32),
+                ("gap_extend", ctypes.c_int32), ("s2", ctypes.c_int32), ("matrix", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load():
+    """Load the in-tree library (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libplast_hip.so is not built (run __graft_entry__.build() or "
+                              "python paper_0804_3643_amd/build.py); there is no CPU fallback")
+        lib = ctypes.CDLL(LIB_PATH)
+        P, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+        lib.plast_index_bytes.argtypes = [i64, i32, ctypes.POINTER(sz), ctypes.POINTER(sz)]
+        lib.plast_build_index.argtypes = [P, P, i32, i64, P, sz, P, sz, ctypes.POINTER(IndexView), P]
+        lib.plast_ungapped_workspace_bytes.argtypes = [ctypes.POINTER(IndexView), ctypes.POINTER(IndexView), i32,
+                                                       ctypes.POINTER(sz), ctypes.POINTER(i64), P]
+        lib.plast_ungapped_extend.argtypes = [ctypes.POINTER(IndexView), ctypes.POINTER(IndexView),
+                                              ctypes.POINTER(UngappedParams), i32, P, sz, P, i64,
+                                              ctypes.POINTER(i64), ctypes.POINTER(i64), P]
+        lib.plast_gapped_filter.argtypes = [ctypes.POINTER(IndexView), ctypes.POINTER(IndexView), P, i64,
+                                            ctypes.POINTER(GappedParams), P, P, P]
+        for f in ("plast_index_bytes", "plast_build_index", "plast_ungapped_workspace_bytes",
+                  "plast_ungapped_extend", "plast_gapped_filter"):
+            getattr(lib, f).restype = ctypes.c_int
+        lib.plast_strerror.argtypes = [ctypes.c_int]
+        lib.plast_strerror.restype = ctypes.c_char_p
+        lib.plast_last_error.argtypes = []
+        lib.plast_last_error.restype = ctypes.c_char_p
+        _lib = lib
+    return _lib
+
+
+def _strerror(code):
+    return load().plast_strerror(code).decode()
+
+
+def _check(rc, where):
+    if rc != OK:
+        raise PlastError(rc, where, load().plast_last_error().decode())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else ctypes.c_void_p(0)
+
+
+def _alloc(nbytes, device):
+    # 256-byte alignment is required by the library; torch's caching allocator
+    # returns blocks aligned to at least 512 bytes.
+    t = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+    assert t.data_ptr() % 256 == 0
+    return t
+
+
+class BankIndex:
+    """A bank resident on the device plus its built index (owns the tensors)."""
+
+    def __init__(self, codes, seq_start, index_buf, view):
+        self.codes = codes
+        self.seq_start = seq_start
+        self.index_buf = index_buf
+        self.view = view
+
+    @property
+    def n_words(self):
+        return int(self.view.n_words)
+
+    @property
+    def n_seqs(self):
+        return int(self.view.n_seqs)
+
+    def key_off(self):
+        return _view_tensor(self.index_buf, self.view.key_off, NKEYS + 1, torch.int64)
+
+    def occ(self):
+        return _view_tensor(self.index_buf, self.view.occ, self.n_words, torch.int32)
+
+    def occ_seq(self):
+        return _view_tensor(self.index_buf, self.view.occ_seq, self.n_words, torch.int32)
+
+
+def _view_tensor(buf, ptr, n, dtype):
+    off = int(ptr) - buf.data_ptr()
+    esz = torch.empty(0, dtype=dtype).element_size()
+    return buf[off:off + n * esz].view(dtype)
+
+
+def bank_to_device(bank, device="cuda"):
+    """Copy a bank in the padded layout (numpy ``codes``/``seq_start``) to the device."""
+    codes = torch.from_numpy(np.ascontiguousarray(bank.codes, dtype=np.uint8)).to(device)
+    seq_start = torch.from_numpy(np.ascontiguousarray(bank.seq_start, dtype=np.int64)).to(device)
+    return codes, seq_start
+
+
+def index_bytes(n_padded, n_seqs):
+    ib, wb = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    _check(load().plast_index_bytes(int(n_padded), int(n_seqs), ctypes.byref(ib), ctypes.byref(wb)),
+           "plast_index_bytes")
+    return ib.value, wb.value
+
+
+def build_index(codes, seq_start, stream=None, workspace=None):
+    """Stage 0 on the device: ``codes`` uint8 and ``seq_start`` int64 CUDA tensors."""
+    assert codes.is_cuda and codes.dtype == torch.uint8 and seq_start.dtype == torch.int64
+    n_seqs = seq_start.numel() - 1
+    n_padded = codes.numel()
+    ib, wb = index_bytes(n_padded, n_seqs)
+    buf = _alloc(ib, codes.device)
+    ws = workspace if workspace is not None and workspace.numel() >= wb else _alloc(wb, codes.device)
+    view = IndexView()
+    _check(load().plast_build_index(_ptr(codes), _ptr(seq_start), n_seqs, n_padded, _ptr(buf), buf.numel(),
+                                    _ptr(ws), ws.numel(), ctypes.byref(view), _stream(stream)),
+           "plast_build_index")
+    return BankIndex(codes, seq_start, buf, view)
+
+
+def _matrix_ptr(matrix):
+    if matrix is None:
+        return None, ctypes.c_void_p(0)
+    m = np.ascontiguousarray(np.asarray(matrix, dtype=np.int8).reshape(20, 20))
+    return m, ctypes.c_void_p(m.ctypes.data)
+
+
+def ungapped_workspace_bytes(ia, ib, mode="batched", stream=None):
+    sz, n_ext = ctypes.c_size_t(0), ctypes.c_int64(0)
+    _check(load().plast_ungapped_workspace_bytes(ctypes.byref(ia.view), ctypes.byref(ib.view), MODES[mode],
+                                                 ctypes.byref(sz), ctypes.byref(n_ext), _stream(stream)),
+           "plast_ungapped_workspace_bytes")
+    return sz.value, n_ext.value
+
+
+class Extender:
+    """Reusable ungapped-extension call: holds the workspace and the hit buffer
+    so that repeated calls (benchmark steps) allocate nothing."""
+
+    def __init__(self, ia, ib, s1, mode="batched", capacity=None, matrix=None, stream=None):
+        self.ia, self.ib, self.mode = ia, ib, MODES[mode]
+        wsb, self.n_ext_expected = ungapped_workspace_bytes(ia, ib, mode, stream)
+        self.ws = _alloc(wsb, ia.codes.device)
+        if capacity is None:
+            capacity = int(self.n_ext_expected * 0.004) + 4096
+        self.hits = torch.empty((int(capacity), 5), dtype=torch.int32, device=ia.codes.device)
+        self._mat, mp = _matrix_ptr(matrix)
+        self.params = UngappedParams(NBR, int(s1), mp)
+        self.stream = stream
+
+    def run(self):
+        n_hits, n_ext = ctypes.c_int64(0), ctypes.c_int64(0)
+        while True:
+            rc = load().plast_ungapped_extend(ctypes.byref(self.ia.view), ctypes.byref(self.ib.view),
+                                              ctypes.byref(self.params), self.mode, _ptr(self.ws), self.ws.numel(),
+                                              _ptr(self.hits), self.hits.shape[0], ctypes.byref(n_hits),
+                                              ctypes.byref(n_ext), _stream(self.stream))
+            if rc == E_CAPACITY:
+                self.hits = torch.empty((int(n_hits.value * 1.1) + 1024, 5), dtype=torch.int32,
+                                        device=self.ia.codes.device)
+                continue
+            _check(rc, "plast_ungapped_extend")
+            return self.hits[:n_hits.value], n_ext.value
+
+
+def ungapped_extend(ia, ib, s1, mode="batched", capacity=None, matrix=None, stream=None):
+    """Stage 2: returns (hits int32[n, 5] device tensor in unspecified order, n_ext)."""
+    return Extender(ia, ib, s1, mode, capacity, matrix, stream).run()
+
+
+def gapped_filter(ia, ib, hits, s2, window=64, band=16, gap_open=11, gap_extend=1, matrix=None, stream=None,
+                  out=None):
+    """Stage 3.1: returns (gscore int32[n], pass uint8[n]) device tensors."""
+    n = hits.shape[0]
+    dev = ia.codes.device
+    if out is None:
+        gs = torch.empty(n, dtype=torch.int32, device=dev)
+        ps = torch.empty(n, dtype=torch.uint8, device=dev)
+    else:
+        gs, ps = out[0][:n], out[1][:n]
+    m, mp = _matrix_ptr(matrix)
+    g = GappedParams(int(window), int(band), int(gap_open), int(gap_extend), int(s2), mp)
+    hp = hits if hits.is_contiguous() else hits.contiguous()
+    _check(load().plast_gapped_filter(ctypes.byref(ia.view), ctypes.byref(ib.view), _ptr(hp), n, ctypes.byref(g),
+                                      _ptr(gs), _ptr(ps), _stream(stream)), "plast_gapped_filter")
+    del m
+    return gs, ps
+
+
+def canonical_hits(hits):
+    """Host copy of a hit tensor sorted lexicographically (seq1, pos1, seq2, pos2, score)."""
+    h = hits.detach().to("cpu").numpy().astype(np.int64).reshape(-1, 5)
+    if len(h) == 0:
+        return h
+    return h[np.lexsort(h.T[::-1])]

@@ -1,0 +1,175 @@
+// C ABI entry points, argument validation, error reporting and the library's
+// tables (BLOSUM62 and the subset-seed classes).
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "plast_internal.h"
+
+namespace plast {
+
+const char kNcbiOrder[21] = "ARNDCQEGHILKMFPSTWYV";
+
+// BLOSUM62, Henikoff & Henikoff (1992), NCBI row/column order.
+const int8_t kBlosum62Ncbi[20][20] = {
+    /* A */ {4, -1, -2, -2, 0, -1, -1, 0, -2, -1, -1, -1, -1, -2, -1, 1, 0, -3, -2, 0},
+    /* R */ {-1, 5, 0, -2, -3, 1, 0, -2, 0, -3, -2, 2, -1, -3, -2, -1, -1, -3, -2, -3},
+    /* N */ {-2, 0, 6, 1, -3, 0, 0, 0, 1, -3, -3, 0, -2, -3, -2, 1, 0, -4, -2, -3},
+    /* D */ {-2, -2, 1, 6, -3, 0, 2, -1, -1, -3, -4, -1, -3, -3, -1, 0, -1, -4, -3, -3},
+    /* C */ {0, -3, -3, -3, 9, -3, -4, -3, -3, -1, -1, -3, -1, -2, -3, -1, -1, -2, -2, -1},
+    /* Q */ {-1, 1, 0, 0, -3, 5, 2, -2, 0, -3, -2, 1, 0, -3, -1, 0, -1, -2, -1, -2},
+    /* E */ {-1, 0, 0, 2, -4, 2, 5, -2, 0, -3, -3, 1, -2, -3, -1, 0, -1, -3, -2, -2},
+    /* G */ {0, -2, 0, -1, -3, -2, -2, 6, -2, -4, -4, -2, -3, -3, -2, 0, -2, -2, -3, -3},
+    /* H */ {-2, 0, 1, -1, -3, 0, 0, -2, 8, -3, -3, -1, -2, -1, -2, -1, -2, -2, 2, -3},
+    /* I */ {-1, -3, -3, -3, -1, -3, -3, -4, -3, 4, 2, -3, 1, 0, -3, -2, -1, -3, -1, 3},
+    /* L */ {-1, -2, -3, -4, -1, -2, -3, -4, -3, 2, 4, -2, 2, 0, -3, -2, -1, -2, -1, 1},
+    /* K */ {-1, 2, 0, -1, -3, 1, 1, -2, -1, -3, -2, 5, -1, -3, -1, 0, -1, -3, -2, -2},
+    /* M */ {-1, -1, -2, -3, -1, 0, -2, -3, -2, 1, 2, -1, 5, 0, -2, -1, -1, -1, -1, 1},
+    /* F */ {-2, -3, -3, -3, -2, -3, -3, -3, -1, 0, 0, -3, 0, 6, -4, -2, -2, 1, 3, -1},
+    /* P */ {-1, -2, -2, -1, -3, -1, -1, -2, -2, -3, -3, -1, -2, -4, 7, -1, -1, -4, -3, -2},
+    /* S */ {1, -1, 1, 0, -1, 0, 0, 0, -1, -2, -2, 0, -1, -2, -1, 4, 1, -3, -2, -2},
+    /* T */ {0, -1, 0, -1, -1, -1, -1, -2, -2, -1, -1, -1, -1, -2, -1, 1, 5, -2, -2, 0},
+    /* W */ {-3, -3, -4, -4, -2, -2, -3, -2, -2, -3, -2, -3, -1, 1, -4, -3, -2, 11, 2, -3},
+    /* Y */ {-2, -2, -2, -3, -2, -1, -2, -3, 2, -1, -1, -2, -1, 3, -3, -2, -2, 2, 7, -1},
+    /* V */ {0, -3, -3, -3, -1, -2, -2, -3, -3, 3, 1, -2, 1, -1, -2, -2, 0, -3, -1, 4},
+};
+
+static const char kCodeOrder[] = "ACDEFGHIKLMNPQRSTVWY";
+
+static int code_of(char c) {
+  for (int i = 0; i < 20; ++i)
+    if (kCodeOrder[i] == c) return i;
+  return -1;
+}
+
+void blosum62_code_order(int8_t* m) {
+  for (int r = 0; r < 20; ++r)
+    for (int c = 0; c < 20; ++c) m[code_of(kNcbiOrder[r]) * 20 + code_of(kNcbiOrder[c])] = kBlosum62Ncbi[r][c];
+}
+
+SeedClasses seed_classes() {
+  // Sec. 3.3.1 subset seed: position 2 classes c and g, position 3 classes
+  // A, C, f, G, i, m, n, P, q, r, t (ids in that order).
+  static const char* pos2_g = "GPATSNHQEDRK";
+  static const char* pos3[11] = {"A", "C", "FYW", "G", "IV", "ML", "NH", "P", "QED", "RK", "TS"};
+  SeedClasses sc{0u, 0ull, 0ull};
+  for (const char* p = pos2_g; *p; ++p) sc.pos2_g_mask |= 1u << code_of(*p);
+  for (int k = 0; k < 11; ++k)
+    for (const char* p = pos3[k]; *p; ++p) {
+      int c = code_of(*p);
+      if (c < 16)
+        sc.pos3_lo |= (uint64_t)k << (4 * c);
+      else
+        sc.pos3_hi |= (uint64_t)k << (4 * (c - 16));
+    }
+  return sc;
+}
+
+static thread_local char g_last_error[512] = "";
+
+int set_error(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+int hip_check(hipError_t e, const char* what) {
+  return set_error(PLAST_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+}  // namespace plast
+
+using namespace plast;
+
+extern "C" {
+
+const char* plast_strerror(int code) {
+  switch (code) {
+    case PLAST_OK: return "ok";
+    case PLAST_E_ARG: return "invalid argument";
+    case PLAST_E_ALPHABET: return "residue code outside 0..19 or separator code not 20";
+    case PLAST_E_CAPACITY: return "hit buffer too small";
+    case PLAST_E_WORKSPACE: return "workspace or index buffer too small";
+    case PLAST_E_HIP: return "HIP runtime error";
+    case PLAST_E_LAYOUT: return "sequence offsets do not describe a padded bank";
+    default: return "unknown error";
+  }
+}
+
+const char* plast_last_error(void) { return g_last_error; }
+
+int plast_index_bytes(int64_t n_padded, int32_t n_seqs, size_t* index_bytes, size_t* ws_bytes) {
+  if (!index_bytes || !ws_bytes) return set_error(PLAST_E_ARG, "null output pointer");
+  if (n_seqs < 0 || n_padded < kPadLen || n_padded > (int64_t)INT32_MAX - 2 * kScanSlack)
+    return set_error(PLAST_E_ARG, "bad sizes n_padded=%lld n_seqs=%d", (long long)n_padded, n_seqs);
+  *index_bytes = index_layout(n_padded).total;
+  *ws_bytes = index_ws_bytes(n_padded);
+  return PLAST_OK;
+}
+
+int plast_build_index(const uint8_t* d_codes, const int64_t* d_seq_start, int32_t n_seqs, int64_t n_padded,
+                      void* d_index, size_t index_bytes, void* d_ws, size_t ws_bytes, plast_index_t* out,
+                      void* stream) {
+  g_last_error[0] = 0;
+  if (!d_codes || !d_seq_start || !d_index || !d_ws || !out) return set_error(PLAST_E_ARG, "null pointer");
+  size_t need_idx = 0, need_ws = 0;
+  int rc = plast_index_bytes(n_padded, n_seqs, &need_idx, &need_ws);
+  if (rc != PLAST_OK) return rc;
+  if (index_bytes < need_idx || ws_bytes < need_ws)
+    return set_error(PLAST_E_WORKSPACE, "index buffer %zu < %zu or workspace %zu < %zu", index_bytes, need_idx,
+                     ws_bytes, need_ws);
+  if (((uintptr_t)d_index & 255) || ((uintptr_t)d_ws & 255))
+    return set_error(PLAST_E_ARG, "index and workspace buffers must be 256-byte aligned");
+  return build_index_impl(d_codes, d_seq_start, n_seqs, n_padded, d_index, d_ws, out, (hipStream_t)stream);
+}
+
+static int check_index(const plast_index_t* x, const char* name) {
+  if (!x) return set_error(PLAST_E_ARG, "%s: null index", name);
+  if (!x->codes || !x->seq_start || !x->key_off || !x->occ || !x->occ_seq || !x->scan_codes || x->n_seqs < 0 ||
+      x->n_words < 0 || x->n_padded < kPadLen)
+    return set_error(PLAST_E_ARG, "%s: index view is incomplete (not from plast_build_index?)", name);
+  return PLAST_OK;
+}
+
+int plast_ungapped_workspace_bytes(const plast_index_t* a, const plast_index_t* b, int32_t mode, size_t* bytes,
+                                   int64_t* n_ext, void* stream) {
+  g_last_error[0] = 0;
+  int rc;
+  if ((rc = check_index(a, "a")) || (rc = check_index(b, "b"))) return rc;
+  if (!bytes) return set_error(PLAST_E_ARG, "null output pointer");
+  if (mode != PLAST_PLAIN && mode != PLAST_BATCHED) return set_error(PLAST_E_ARG, "unknown mode %d", mode);
+  return ungapped_ws_bytes_impl(a, b, mode, bytes, n_ext, (hipStream_t)stream);
+}
+
+int plast_ungapped_extend(const plast_index_t* a, const plast_index_t* b, const plast_ungapped_params_t* p,
+                          int32_t mode, void* d_ws, size_t ws_bytes, plast_hit_t* d_hits, int64_t capacity,
+                          int64_t* h_n_hits, int64_t* h_n_ext, void* stream) {
+  g_last_error[0] = 0;
+  int rc;
+  if ((rc = check_index(a, "a")) || (rc = check_index(b, "b"))) return rc;
+  if (!p || !h_n_hits || !d_ws || capacity < 0 || (capacity > 0 && !d_hits))
+    return set_error(PLAST_E_ARG, "null pointer or negative capacity");
+  if (p->nbr != kNbr) return set_error(PLAST_E_ARG, "nbr=%d unsupported (only %d)", p->nbr, kNbr);
+  if (mode != PLAST_PLAIN && mode != PLAST_BATCHED) return set_error(PLAST_E_ARG, "unknown mode %d", mode);
+  if ((uintptr_t)d_ws & 255) return set_error(PLAST_E_ARG, "workspace must be 256-byte aligned");
+  return ungapped_extend_impl(a, b, p, mode, d_ws, ws_bytes, d_hits, capacity, h_n_hits, h_n_ext,
+                              (hipStream_t)stream);
+}
+
+int plast_gapped_filter(const plast_index_t* a, const plast_index_t* b, const plast_hit_t* d_hits, int64_t n_hits,
+                        const plast_gapped_params_t* g, int32_t* d_gscore, uint8_t* d_pass, void* stream) {
+  g_last_error[0] = 0;
+  int rc;
+  if ((rc = check_index(a, "a")) || (rc = check_index(b, "b"))) return rc;
+  if (!g || n_hits < 0 || (n_hits > 0 && (!d_hits || !d_gscore || !d_pass)))
+    return set_error(PLAST_E_ARG, "null pointer or negative hit count");
+  if (g->window < 1 || g->window > 64 || g->band < 0 || g->band > 16 || g->gap_open < 0 || g->gap_extend < 0 ||
+      g->gap_open + g->gap_extend > 1000)
+    return set_error(PLAST_E_ARG, "gapped parameters out of range (window 1..64, band 0..16, costs >= 0)");
+  if (n_hits == 0) return PLAST_OK;
+  return gapped_filter_impl(a, b, d_hits, n_hits, g, d_gscore, d_pass, (hipStream_t)stream);
+}
+
+}  // extern "C"

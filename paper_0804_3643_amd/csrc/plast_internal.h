@@ -1,0 +1,104 @@
+// Internal declarations of the gfx950 PLAST-P library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "plast.h"
+
+namespace plast {
+
+constexpr int kNKeys = PLAST_NKEYS;
+constexpr int kSeed = PLAST_SEED_LEN;
+constexpr int kNbr = PLAST_NBR;
+constexpr int kRight = kSeed + kNbr;     // letters scanned rightward, seed included
+constexpr int kSpan = kRight + kNbr;     // 44 scan steps per pair
+constexpr int kPadCode = PLAST_PAD_CODE;
+constexpr int kPadLen = PLAST_PAD_LEN;
+constexpr int kNLet = 21;                // 20 residues + separator
+constexpr int kScale = 8;                // scan_codes[p] = codes[p] * kScale
+constexpr int kScanSlack = 64;           // separator bytes appended to scan_codes
+
+// ---------------------------------------------------------------- tables
+// BLOSUM62 (Henikoff & Henikoff 1992); this library's transcription, rows and
+// columns in the NCBI order ARNDCQEGHILKMFPSTWYV, permuted to code order when
+// kernels stage it.
+extern const char kNcbiOrder[21];
+extern const int8_t kBlosum62Ncbi[20][20];
+// Fill m[20*20] (code order ACDEFGHIKLMNPQRSTVWY) with BLOSUM62.
+void blosum62_code_order(int8_t* m);
+
+// Subset seed of Sec. 3.3.1: position 2 has two classes, position 3 eleven.
+// Class ids are packed 4 bits per residue code (code c at bits 4c of a
+// 128-bit value split in two words) so kernels evaluate them in registers.
+struct SeedClasses {
+  uint32_t pos2_g_mask;   // bit c set iff residue c is in class g (id 1), else class c (id 0)
+  uint64_t pos3_lo;       // codes 0..15
+  uint64_t pos3_hi;       // codes 16..19
+};
+SeedClasses seed_classes();
+
+__device__ __forceinline__ int seed_key_dev(const SeedClasses& sc, int w0, int w1, int w2, int w3) {
+  int c2 = (sc.pos2_g_mask >> w1) & 1;
+  int c3 = (int)((w2 < 16 ? (sc.pos3_lo >> (4 * w2)) : (sc.pos3_hi >> (4 * (w2 - 16)))) & 15u);
+  return ((w0 * 2 + c2) * 11 + c3) * 20 + w3;
+}
+
+// ---------------------------------------------------------------- errors
+int set_error(int code, const char* fmt, ...);
+int hip_check(hipError_t e, const char* what);
+#define PLAST_HIP(call)                                   \
+  do {                                                    \
+    hipError_t e_ = (call);                               \
+    if (e_ != hipSuccess) return ::plast::hip_check(e_, #call); \
+  } while (0)
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// ---------------------------------------------------------------- index build
+struct IndexLayout {
+  size_t key_off, occ, occ_seq, scan, total;
+};
+IndexLayout index_layout(int64_t n_padded);
+struct IndexChunks {
+  int64_t chunk;
+  int32_t nchunks;
+};
+IndexChunks index_chunks(int64_t n_padded);
+size_t index_ws_bytes(int64_t n_padded);
+
+int build_index_impl(const uint8_t* d_codes, const int64_t* d_seq_start, int32_t n_seqs, int64_t n_padded,
+                     void* d_index, void* d_ws, plast_index_t* out, hipStream_t stream);
+
+// ---------------------------------------------------------------- scans
+// Exclusive int32 scan of n elements in place; d_tmp needs scan_tmp_bytes(n).
+size_t scan_tmp_bytes(int64_t n);
+void exclusive_scan_i32(int32_t* d_data, int64_t n, int32_t* d_total, void* d_tmp, hipStream_t s);
+
+// ---------------------------------------------------------------- ungapped
+constexpr int kTileRows = 32;           // bank-a occurrences per work item (profile rows)
+constexpr int kRowGroups = kTileRows / 4;
+constexpr int kThreads = 256;           // threads per workgroup
+constexpr int kColsPerLane = 8;         // bank-b occurrences per lane per item
+constexpr int kTileCols = kThreads * kColsPerLane;
+
+struct WorkItem {
+  int32_t key, row0, col0, ncols;
+};
+
+struct UngappedPlan {
+  int64_t n_ext;
+  int64_t n_items;
+};
+
+int ungapped_extend_impl(const plast_index_t* a, const plast_index_t* b, const plast_ungapped_params_t* p,
+                         int32_t mode, void* d_ws, size_t ws_bytes, plast_hit_t* d_hits, int64_t capacity,
+                         int64_t* h_n_hits, int64_t* h_n_ext, hipStream_t stream);
+int ungapped_ws_bytes_impl(const plast_index_t* a, const plast_index_t* b, int32_t mode, size_t* bytes,
+                           int64_t* n_ext, hipStream_t stream);
+
+// ---------------------------------------------------------------- gapped
+int gapped_filter_impl(const plast_index_t* a, const plast_index_t* b, const plast_hit_t* d_hits, int64_t n_hits,
+                       const plast_gapped_params_t* g, int32_t* d_gscore, uint8_t* d_pass, hipStream_t stream);
+
+}  // namespace plast

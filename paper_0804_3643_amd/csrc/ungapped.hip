@@ -1,0 +1,459 @@
+// Stage 2, ungapped extension (Sec. 3.2 generic algorithm, Sec. 3.3.3), with
+// hit compaction and two schedules over the same tile routine.
+//
+// Tile routine.  A work item is (key, 32 bank-a occurrences, up to 2048 bank-b
+// occurrences).  The 32 rows are turned into a profile in LDS: for scan step t
+// (t < 24: letter p+t; t >= 24: letter p-(t-23)) and bank-b letter c, the 8-byte
+// entry holds the substitution scores of four rows as int16 (59 KB for 32 rows
+// x 44 steps x 21 letters).  Each lane owns one bank-b occurrence: its 44-letter
+// window sits in 11 registers as (letter * 8) bytes, so one bit-field extract
+// gives the LDS address of the entry and eight 8-byte LDS reads give the scores
+// of all 32 rows; the running sum and running best are packed int16 pairs
+// (v_pk_add_u16 / v_pk_max_i16), one instruction each per two pairs.  At step 24
+// the running sum is reset to the running best, so the best of the leftward
+// prefixes is added to the best rightward prefix (the composition of the GPU
+// kernel of Annex 4).  Letters outside a sequence are separators scoring
+// kSepScore <= 0 against everything; the separator run after a sequence is at
+// least as long as the scan, so a scan that leaves its sequence only meets
+// separators and its best prefix is the clipped one.
+//
+// Hits: per lane a 32-bit mask of rows with score >= s1; wavefront prefix sum
+// of the mask popcounts, one 64-bit atomic per wavefront reserves the output
+// slots (order of hits is unspecified).
+//
+// Schedules.  PLAIN: one grid per key with candidate pairs, in key order, one
+// item per workgroup (the paper's one-launch-per-seed GPU offload, Sec. 5.2.1,
+// without its per-seed copies).  BATCHED: a device work list over all keys and
+// one persistent kernel whose workgroups pop items from an atomic counter (the
+// dynamic seed distribution of the multicore version, Sec. 5.1).
+#include <stddef.h>
+#include <string.h>
+
+#include <vector>
+
+#include "plast_internal.h"
+
+namespace plast {
+
+namespace {
+
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+
+constexpr int kSepScore = -4;
+constexpr int kProfT = kNLet * 8;                 // bytes per scan step
+constexpr int kProfRG = kSpan * kProfT;           // bytes per 4-row group
+constexpr int kProfBytes = kRowGroups * kProfRG;  // 59136
+static_assert(kProfBytes + 4096 < 65536, "profile offsets must fit the LDS instruction offset field");
+static_assert(kPadCode * kScale < 256, "scaled codes must fit a byte");
+
+struct BankView {
+  const int64_t* key_off;
+  const int32_t* occ;
+  const int32_t* occ_seq;
+  const uint8_t* scan;
+  const int64_t* seq_start;
+};
+
+struct UngappedArgs {
+  BankView a, b;
+  int32_t s1;
+  int32_t pad_;
+  plast_hit_t* hits;
+  int64_t capacity;
+  unsigned long long* n_hits;
+  int16_t mat[kNLet * kNLet];  // [a letter][b letter], separator row/column = kSepScore
+};
+
+struct __align__(16) Smem {
+  uint8_t prof[kProfBytes];            // 8-byte entries (offset 0)
+  uint8_t rowlet[kSpan * kTileRows];   // read as 4-byte groups (offset 59136)
+  int32_t rowq[kTileRows];
+  int32_t rowseq[kTileRows];
+  int32_t rowpos[kTileRows];
+  int32_t item;
+  int16_t mat[kNLet * kNLet];
+};
+static_assert(offsetof(Smem, rowlet) % 16 == 0 && offsetof(Smem, rowq) % 4 == 0, "LDS alignment");
+
+__device__ __forceinline__ s16x2 as_s16x2(uint32_t v) { return __builtin_bit_cast(s16x2, v); }
+
+__device__ __forceinline__ void load_matrix(const UngappedArgs& A, Smem& S) {
+  for (int i = threadIdx.x; i < kNLet * kNLet; i += kThreads) S.mat[i] = A.mat[i];
+}
+
+__device__ __forceinline__ int wave_incl_scan(int v) {
+  const int lane = __lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int t = __shfl_up(v, o);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+__device__ void run_item(const UngappedArgs& A, const WorkItem it, Smem& S) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wid = tid >> 6;
+  const int64_t a0 = A.a.key_off[it.key];
+  const int n1 = (int)(A.a.key_off[it.key + 1] - a0);
+  const int rows = min(kTileRows, n1 - it.row0);
+  const int64_t b0 = A.b.key_off[it.key];
+
+  // ---- rows of the tile: occurrence, sequence, position
+  if (tid < kTileRows) {
+    int q = -1, sq = 0, ps = 0;
+    if (tid < rows) {
+      int64_t o = a0 + it.row0 + tid;
+      q = A.a.occ[o];
+      sq = A.a.occ_seq[o];
+      ps = q - (int)A.a.seq_start[sq];
+    }
+    S.rowq[tid] = q;
+    S.rowseq[tid] = sq;
+    S.rowpos[tid] = ps;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < kSpan * kTileRows; idx += kThreads) {
+    int t = idx / kTileRows, r = idx - t * kTileRows;
+    int q = S.rowq[r];
+    int letter = kPadCode;
+    if (q >= 0) {
+      int off = t < kRight ? q + t : q - (t - kRight + 1);
+      letter = A.a.scan[off] / kScale;
+    }
+    S.rowlet[t * kTileRows + r] = (uint8_t)letter;
+  }
+  __syncthreads();
+  // ---- profile: prof[rg][t][c] = scores of rows 4rg..4rg+3 at step t against letter c
+  for (int e = tid; e < kRowGroups * kSpan * kNLet; e += kThreads) {
+    int rg = e / (kSpan * kNLet);
+    int rem = e - rg * (kSpan * kNLet);
+    int t = rem / kNLet;
+    int c = rem - t * kNLet;
+    uint32_t l4 = *(const uint32_t*)&S.rowlet[t * kTileRows + 4 * rg];
+    uint32_t v0 = (uint16_t)S.mat[(l4 & 0xff) * kNLet + c];
+    uint32_t v1 = (uint16_t)S.mat[((l4 >> 8) & 0xff) * kNLet + c];
+    uint32_t v2 = (uint16_t)S.mat[((l4 >> 16) & 0xff) * kNLet + c];
+    uint32_t v3 = (uint16_t)S.mat[(l4 >> 24) * kNLet + c];
+    uint2 w;
+    w.x = v0 | (v1 << 16);
+    w.y = v2 | (v3 << 16);
+    *(uint2*)&S.prof[rg * kProfRG + t * kProfT + c * 8] = w;
+  }
+  __syncthreads();
+
+  // ---- columns: lane owns bank-b occurrences col0 + tid + 256*k
+  const int col_end = it.col0 + it.ncols;
+  for (int k = 0; k < kColsPerLane; ++k) {
+    const int wave_first = it.col0 + wid * 64 + kThreads * k;
+    if (wave_first >= col_end) break;  // uniform in the wavefront
+    const int j = it.col0 + tid + kThreads * k;
+    const bool active = j < col_end;
+    const int64_t o = b0 + (active ? j : it.col0);
+    const int q2 = A.b.occ[o];
+    const int s2 = A.b.occ_seq[o];
+    const int base = q2 - kNbr;
+    const uint32_t* src = (const uint32_t*)A.b.scan + (base >> 2);
+    uint32_t d[12];
+#pragma unroll
+    for (int i = 0; i < 12; ++i) d[i] = src[i];
+    const int sh = base & 3;
+    uint32_t win[11];
+#pragma unroll
+    for (int i = 0; i < 11; ++i) win[i] = __builtin_amdgcn_alignbyte(d[i + 1], d[i], sh);
+
+    s16x2 s[2 * kRowGroups], m[2 * kRowGroups];
+#pragma unroll
+    for (int t = 0; t < kSpan; ++t) {
+      const int bidx = t < kRight ? kNbr + t : (kSpan - 1) - t;
+      const uint32_t c8 = (win[bidx >> 2] >> (8 * (bidx & 3))) & 0xffu;
+      const uint8_t* p = S.prof + c8 + t * kProfT;
+      if (t == kRight) {
+#pragma unroll
+        for (int i = 0; i < 2 * kRowGroups; ++i) s[i] = m[i];
+      }
+#pragma unroll
+      for (int rg = 0; rg < kRowGroups; ++rg) {
+        const uint2 v = *(const uint2*)(p + rg * kProfRG);
+        const s16x2 x = as_s16x2(v.x), y = as_s16x2(v.y);
+        if (t == 0) {
+          const s16x2 z = {0, 0};
+          s[2 * rg] = x;
+          s[2 * rg + 1] = y;
+          m[2 * rg] = __builtin_elementwise_max(x, z);
+          m[2 * rg + 1] = __builtin_elementwise_max(y, z);
+        } else {
+          s[2 * rg] += x;
+          s[2 * rg + 1] += y;
+          m[2 * rg] = __builtin_elementwise_max(m[2 * rg], s[2 * rg]);
+          m[2 * rg + 1] = __builtin_elementwise_max(m[2 * rg + 1], s[2 * rg + 1]);
+        }
+      }
+    }
+    // ---- hits
+    s16x2 mx = m[0];
+#pragma unroll
+    for (int i = 1; i < 2 * kRowGroups; ++i) mx = __builtin_elementwise_max(mx, m[i]);
+    const int best = max((int)mx.x, (int)mx.y);
+    const bool cand = active && best >= A.s1;
+    if (__ballot(cand)) {
+      uint32_t mask = 0;
+      if (cand) {
+#pragma unroll
+        for (int r = 0; r < kTileRows; ++r) {
+          const int v = (r & 1) ? (int)m[r >> 1].y : (int)m[r >> 1].x;
+          if (r < rows && v >= A.s1) mask |= 1u << r;
+        }
+      }
+      const int cnt = __popc(mask);
+      const int incl = wave_incl_scan(cnt);
+      unsigned long long at = 0;
+      if (lane == 63 && incl > 0) at = atomicAdd(A.n_hits, (unsigned long long)incl);
+      at = __shfl(at, 63) + (unsigned long long)(incl - cnt);
+      if (mask) {
+        const int p2 = q2 - (int)A.b.seq_start[s2];
+#pragma unroll
+        for (int r = 0; r < kTileRows; ++r) {
+          if (mask & (1u << r)) {
+            if (at < (unsigned long long)A.capacity) {
+              plast_hit_t h;
+              h.seq1 = S.rowseq[r];
+              h.pos1 = S.rowpos[r];
+              h.seq2 = s2;
+              h.pos2 = p2;
+              h.score = (r & 1) ? (int)m[r >> 1].y : (int)m[r >> 1].x;
+              A.hits[at] = h;
+            }
+            ++at;
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();  // LDS is rebuilt by the next item
+}
+
+__global__ __launch_bounds__(kThreads) void k_ungapped_plain(UngappedArgs A, int32_t key, int32_t n_row_tiles,
+                                                             int32_t n2) {
+  __shared__ Smem S;
+  load_matrix(A, S);
+  WorkItem it;
+  it.key = key;
+  it.row0 = (int32_t)(blockIdx.x % n_row_tiles) * kTileRows;
+  it.col0 = (int32_t)(blockIdx.x / n_row_tiles) * kTileCols;
+  it.ncols = min(kTileCols, n2 - it.col0);
+  run_item(A, it, S);
+}
+
+__global__ __launch_bounds__(kThreads) void k_ungapped_persistent(UngappedArgs A, const WorkItem* __restrict__ items,
+                                                                  const int32_t* __restrict__ n_items_p,
+                                                                  const int32_t* __restrict__ overflow,
+                                                                  int32_t* __restrict__ ctr) {
+  __shared__ Smem S;
+  load_matrix(A, S);
+  const int n_items = *overflow ? 0 : *n_items_p;
+  for (;;) {
+    if (threadIdx.x == 0) S.item = atomicAdd(ctr, 1);
+    __syncthreads();
+    const int i = S.item;
+    if (i >= n_items) break;
+    run_item(A, items[i], S);
+  }
+}
+
+// ---------------------------------------------------------------- planning
+__device__ __forceinline__ int64_t items_of(int64_t n1, int64_t n2) {
+  if (n1 <= 0 || n2 <= 0) return 0;
+  return ((n1 + kTileRows - 1) / kTileRows) * ((n2 + kTileCols - 1) / kTileCols);
+}
+
+__global__ void k_plan_count(const int64_t* __restrict__ a_off, const int64_t* __restrict__ b_off,
+                             int32_t* __restrict__ cnt, unsigned long long* __restrict__ n_ext) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= kNKeys) return;
+  int64_t n1 = a_off[k + 1] - a_off[k], n2 = b_off[k + 1] - b_off[k];
+  cnt[k] = (int32_t)items_of(n1, n2);
+  if (n1 > 0 && n2 > 0) atomicAdd(n_ext, (unsigned long long)(n1 * n2));
+}
+
+__global__ void k_plan_emit(const int64_t* __restrict__ a_off, const int64_t* __restrict__ b_off,
+                            const int32_t* __restrict__ item_off, const int32_t* __restrict__ total,
+                            int64_t max_items, WorkItem* __restrict__ items, int32_t* __restrict__ overflow) {
+  const int k = blockIdx.x;
+  if ((int64_t)*total > max_items) {
+    if (k == 0 && threadIdx.x == 0) *overflow = 1;
+    return;
+  }
+  int64_t n1 = a_off[k + 1] - a_off[k], n2 = b_off[k + 1] - b_off[k];
+  int cnt = (int)items_of(n1, n2);
+  if (cnt == 0) return;
+  int nrt = (int)((n1 + kTileRows - 1) / kTileRows);
+  for (int idx = threadIdx.x; idx < cnt; idx += blockDim.x) {
+    int rt = idx % nrt, ct = idx / nrt;
+    WorkItem w;
+    w.key = k;
+    w.row0 = rt * kTileRows;
+    w.col0 = ct * kTileCols;
+    w.ncols = (int)min((int64_t)kTileCols, n2 - (int64_t)w.col0);
+    items[item_off[k] + idx] = w;
+  }
+}
+
+__global__ void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// ---------------------------------------------------------------- workspace
+// [0, 256): counters  n_hits u64 @0, n_ext u64 @8, item counter i32 @16,
+//           item total i32 @20, overflow flag i32 @24
+// [256, ...): per-key item counts/offsets (int32[kNKeys]), scan scratch, items
+struct UngappedWs {
+  unsigned long long* n_hits;
+  unsigned long long* n_ext;
+  int32_t* ctr;
+  int32_t* total;
+  int32_t* overflow;
+  int32_t* cnt;
+  void* scan_tmp;
+  WorkItem* items;
+  int64_t max_items;
+};
+
+size_t ws_fixed_bytes() { return 256 + align_up(sizeof(int32_t) * kNKeys, 256) + scan_tmp_bytes(kNKeys); }
+
+UngappedWs carve(void* d_ws, size_t ws_bytes) {
+  UngappedWs W;
+  uint8_t* p = (uint8_t*)d_ws;
+  W.n_hits = (unsigned long long*)p;
+  W.n_ext = (unsigned long long*)(p + 8);
+  W.ctr = (int32_t*)(p + 16);
+  W.total = (int32_t*)(p + 20);
+  W.overflow = (int32_t*)(p + 24);
+  W.cnt = (int32_t*)(p + 256);
+  W.scan_tmp = p + 256 + align_up(sizeof(int32_t) * kNKeys, 256);
+  W.items = (WorkItem*)(p + ws_fixed_bytes());
+  W.max_items = ws_bytes > ws_fixed_bytes() ? (int64_t)((ws_bytes - ws_fixed_bytes()) / sizeof(WorkItem)) : 0;
+  return W;
+}
+
+int read_key_offsets(const plast_index_t* x, std::vector<int64_t>& h, hipStream_t s) {
+  h.resize(kNKeys + 1);
+  PLAST_HIP(hipMemcpyAsync(h.data(), x->key_off, sizeof(int64_t) * (kNKeys + 1), hipMemcpyDeviceToHost, s));
+  PLAST_HIP(hipStreamSynchronize(s));
+  return PLAST_OK;
+}
+
+UngappedPlan host_plan(const std::vector<int64_t>& ha, const std::vector<int64_t>& hb) {
+  UngappedPlan P{0, 0};
+  for (int k = 0; k < kNKeys; ++k) {
+    int64_t n1 = ha[k + 1] - ha[k], n2 = hb[k + 1] - hb[k];
+    if (n1 > 0 && n2 > 0) {
+      P.n_ext += n1 * n2;
+      P.n_items += ((n1 + kTileRows - 1) / kTileRows) * ((n2 + kTileCols - 1) / kTileCols);
+    }
+  }
+  return P;
+}
+
+void fill_args(UngappedArgs& A, const plast_index_t* a, const plast_index_t* b, const plast_ungapped_params_t* p,
+               plast_hit_t* d_hits, int64_t capacity, unsigned long long* n_hits) {
+  A.a = BankView{a->key_off, a->occ, a->occ_seq, a->scan_codes, a->seq_start};
+  A.b = BankView{b->key_off, b->occ, b->occ_seq, b->scan_codes, b->seq_start};
+  A.s1 = p->s1;
+  A.pad_ = 0;
+  A.hits = d_hits;
+  A.capacity = capacity;
+  A.n_hits = n_hits;
+  int8_t m[400];
+  if (p->matrix)
+    memcpy(m, p->matrix, sizeof(m));
+  else
+    blosum62_code_order(m);
+  for (int x = 0; x < kNLet; ++x)
+    for (int y = 0; y < kNLet; ++y) A.mat[x * kNLet + y] = (x < 20 && y < 20) ? m[x * 20 + y] : kSepScore;
+}
+
+int persistent_grid() {
+  static int cached = 0;
+  if (!cached) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_ungapped_persistent, kThreads, 0) != hipSuccess)
+      return 0;
+    cached = cus * (per > 0 ? per : 1);
+  }
+  return cached;
+}
+
+}  // namespace
+
+int ungapped_ws_bytes_impl(const plast_index_t* a, const plast_index_t* b, int32_t mode, size_t* bytes,
+                           int64_t* n_ext, hipStream_t stream) {
+  std::vector<int64_t> ha, hb;
+  int rc;
+  if ((rc = read_key_offsets(a, ha, stream)) || (rc = read_key_offsets(b, hb, stream))) return rc;
+  UngappedPlan P = host_plan(ha, hb);
+  if (n_ext) *n_ext = P.n_ext;
+  *bytes = mode == PLAST_BATCHED ? ws_fixed_bytes() + sizeof(WorkItem) * (size_t)P.n_items : 256;
+  if (P.n_items > INT32_MAX) return set_error(PLAST_E_ARG, "too many work items");
+  return PLAST_OK;
+}
+
+int ungapped_extend_impl(const plast_index_t* a, const plast_index_t* b, const plast_ungapped_params_t* p,
+                         int32_t mode, void* d_ws, size_t ws_bytes, plast_hit_t* d_hits, int64_t capacity,
+                         int64_t* h_n_hits, int64_t* h_n_ext, hipStream_t stream) {
+  if (ws_bytes < 256) return set_error(PLAST_E_WORKSPACE, "workspace smaller than 256 bytes");
+  UngappedWs W = carve(d_ws, ws_bytes);
+  UngappedArgs A;
+  fill_args(A, a, b, p, d_hits, capacity, W.n_hits);
+  unsigned long long h_cnt[2] = {0, 0};
+
+  if (mode == PLAST_PLAIN) {
+    std::vector<int64_t> ha, hb;
+    int rc;
+    if ((rc = read_key_offsets(a, ha, stream)) || (rc = read_key_offsets(b, hb, stream))) return rc;
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, stream, (uint32_t*)d_ws, (int64_t)8, 0u);
+    int64_t n_ext = 0;
+    for (int k = 0; k < kNKeys; ++k) {
+      int64_t n1 = ha[k + 1] - ha[k], n2 = hb[k + 1] - hb[k];
+      if (n1 <= 0 || n2 <= 0) continue;
+      n_ext += n1 * n2;
+      int64_t nrt = (n1 + kTileRows - 1) / kTileRows, nct = (n2 + kTileCols - 1) / kTileCols;
+      hipLaunchKernelGGL(k_ungapped_plain, dim3((unsigned)(nrt * nct)), dim3(kThreads), 0, stream, A, k,
+                         (int32_t)nrt, (int32_t)n2);
+    }
+    PLAST_HIP(hipGetLastError());
+    PLAST_HIP(hipMemcpyAsync(h_cnt, W.n_hits, sizeof(unsigned long long), hipMemcpyDeviceToHost, stream));
+    PLAST_HIP(hipStreamSynchronize(stream));
+    h_cnt[1] = (unsigned long long)n_ext;
+  } else {
+    if (ws_bytes < ws_fixed_bytes())
+      return set_error(PLAST_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, ws_fixed_bytes());
+    int grid = persistent_grid();
+    if (grid <= 0) return set_error(PLAST_E_HIP, "cannot query device occupancy");
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, stream, (uint32_t*)d_ws, (int64_t)8, 0u);
+    hipLaunchKernelGGL(k_plan_count, dim3((kNKeys + 255) / 256), dim3(256), 0, stream, a->key_off, b->key_off,
+                       W.cnt, W.n_ext);
+    exclusive_scan_i32(W.cnt, kNKeys, W.total, W.scan_tmp, stream);
+    hipLaunchKernelGGL(k_plan_emit, dim3(kNKeys), dim3(256), 0, stream, a->key_off, b->key_off,
+                       (const int32_t*)W.cnt, (const int32_t*)W.total, W.max_items, W.items, W.overflow);
+    hipLaunchKernelGGL(k_ungapped_persistent, dim3(grid), dim3(kThreads), 0, stream, A,
+                       (const WorkItem*)W.items, (const int32_t*)W.total, (const int32_t*)W.overflow, W.ctr);
+    PLAST_HIP(hipGetLastError());
+    int32_t ovf = 0;
+    PLAST_HIP(hipMemcpyAsync(h_cnt, W.n_hits, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, stream));
+    PLAST_HIP(hipMemcpyAsync(&ovf, W.overflow, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+    PLAST_HIP(hipStreamSynchronize(stream));
+    if (ovf) return set_error(PLAST_E_WORKSPACE, "workspace too small for the work list");
+  }
+  *h_n_hits = (int64_t)h_cnt[0];
+  if (h_n_ext) *h_n_ext = (int64_t)h_cnt[1];
+  if ((int64_t)h_cnt[0] > capacity)
+    return set_error(PLAST_E_CAPACITY, "%lld hits > capacity %lld", (long long)h_cnt[0], (long long)capacity);
+  return PLAST_OK;
+}
+
+}  // namespace plast

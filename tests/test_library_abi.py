@@ -1,0 +1,102 @@
+"""CPU-side checks of the C ABI: the built library loads, exports every entry
+point declared in include/plast.h, struct layouts agree with the binding, and
+argument validation rejects bad calls before touching a GPU."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "plast.h")
+
+binding = pytest.importorskip("paper_0804_3643_amd.binding")
+
+
+def _declared():
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(plast_\w+)\s*\(", src, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = binding.load()
+    names = _declared()
+    assert set(names) == set(binding.EXPORTS)
+    for n in names:
+        assert hasattr(lib, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", binding.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (plast_\w+)", out))
+    assert set(names) <= exported
+
+
+def test_struct_layouts_match_binding(tmp_path):
+    prog = tmp_path / "layout.c"
+    prog.write_text("""
+#include <stdio.h>
+#include <stddef.h>
+#include "plast.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu\\n", sizeof(plast_index_t), offsetof(plast_index_t, n_words),
+         offsetof(plast_index_t, scan_codes), sizeof(plast_ungapped_params_t), sizeof(plast_gapped_params_t));
+  printf("%zu %d %d %d %d\\n", sizeof(plast_hit_t), PLAST_NKEYS, PLAST_PAD_CODE, PLAST_PAD_LEN, PLAST_NBR);
+  return 0;
+}
+""")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c99", "-I" + os.path.join(ROOT, "include"), str(prog), "-o", str(exe)])
+    a, b = subprocess.check_output([str(exe)], text=True).strip().splitlines()
+    a = [int(x) for x in a.split()]
+    b = [int(x) for x in b.split()]
+    assert a == [ctypes.sizeof(binding.IndexView), binding.IndexView.n_words.offset,
+                 binding.IndexView.scan_codes.offset, ctypes.sizeof(binding.UngappedParams),
+                 ctypes.sizeof(binding.GappedParams)]
+    assert b == [20, binding.NKEYS, binding.PAD_CODE, binding.PAD_LEN, binding.NBR]
+
+
+def test_strerror_and_argument_validation_without_gpu():
+    lib = binding.load()
+    assert lib.plast_strerror(0) == b"ok"
+    assert lib.plast_strerror(binding.E_CAPACITY) == b"hit buffer too small"
+    ib, wb = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    assert lib.plast_index_bytes(10, 1, ctypes.byref(ib), ctypes.byref(wb)) == binding.E_ARG
+    assert lib.plast_index_bytes(100, -1, ctypes.byref(ib), ctypes.byref(wb)) == binding.E_ARG
+    assert lib.plast_index_bytes(1 << 31, 5, ctypes.byref(ib), ctypes.byref(wb)) == binding.E_ARG
+    assert lib.plast_index_bytes(1000, 5, ctypes.byref(ib), ctypes.byref(wb)) == binding.OK
+    assert ib.value > 8 * 1000 and wb.value > 8800 * 4
+    view = binding.IndexView()
+    assert lib.plast_build_index(None, None, 0, 20, None, 0, None, 0, ctypes.byref(view), None) == binding.E_ARG
+    assert b"null" in lib.plast_last_error()
+    # fake device pointers are never dereferenced: validation fails first
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.plast_build_index(fake, fake, 1, 1000, fake, 1, fake, 1, ctypes.byref(view), None) == \
+        binding.E_WORKSPACE
+    p = binding.UngappedParams(binding.NBR, 38, None)
+    n = ctypes.c_int64(0)
+    assert lib.plast_ungapped_extend(None, None, ctypes.byref(p), 1, fake, 256, fake, 10, ctypes.byref(n), None,
+                                     None) == binding.E_ARG
+    v = binding.IndexView(fake.value, fake.value, 1, 1000, fake.value, fake.value, fake.value, fake.value, 10)
+    p_bad = binding.UngappedParams(7, 38, None)
+    assert lib.plast_ungapped_extend(ctypes.byref(v), ctypes.byref(v), ctypes.byref(p_bad), 1, fake, 256, fake, 10,
+                                     ctypes.byref(n), None, None) == binding.E_ARG
+    assert lib.plast_ungapped_extend(ctypes.byref(v), ctypes.byref(v), ctypes.byref(p), 7, fake, 256, fake, 10,
+                                     ctypes.byref(n), None, None) == binding.E_ARG
+    g = binding.GappedParams(0, 16, 11, 1, 48, None)
+    assert lib.plast_gapped_filter(ctypes.byref(v), ctypes.byref(v), fake, 5, ctypes.byref(g), fake, fake,
+                                   None) == binding.E_ARG
+    g = binding.GappedParams(64, 17, 11, 1, 48, None)
+    assert lib.plast_gapped_filter(ctypes.byref(v), ctypes.byref(v), fake, 5, ctypes.byref(g), fake, fake,
+                                   None) == binding.E_ARG
+    g = binding.GappedParams(64, 16, 11, 1, 48, None)
+    assert lib.plast_gapped_filter(ctypes.byref(v), ctypes.byref(v), fake, 0, ctypes.byref(g), fake, fake,
+                                   None) == binding.OK
+
+
+def test_product_code_never_touches_the_oracle():
+    pkg = os.path.join(ROOT, "paper_0804_3643_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                src = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"^\s*(from|import)\s+oracle", src, re.M), f
+                assert "plast_oracle" not in src and "coracle" not in src, f
