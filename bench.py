@@ -1,0 +1,315 @@
+#!/usr/bin/env python3
+"""Benchmark of the PLAST-P bank-versus-bank hot path on one MI355X.
+
+One step = the whole hot path over one pair of banks already resident in HBM:
+index bank 1 and bank 2 (stage 0), batched ungapped extension of every
+candidate pair with hit compaction (stage 2), small gapped filter on the hits
+(stage 3.1).  ``value`` = candidate pairs (ungapped extensions) per second of
+step wall time.  Also reported:
+  * the ungapped stage alone, PLAIN (one grid per key) vs BATCHED (persistent
+    work queue), device time from HIP events, after checking that both give the
+    same hit multiset;
+  * bank-vs-bank wall time from host-resident encoded banks to the host hit
+    list (host-to-device copy, both indexes, ungapped, gapped, device-to-host),
+    for both schedules;
+  * ``roofline`` for the dominant kernel (the persistent ungapped kernel):
+    algorithmic int16 ALU operations (44 additions and 44 maxima per
+    extension) per second against the packed-int16 VALU peak;
+  * ``cpu_baseline``: the CPU oracle (plain C, all allotted host threads) on a
+    seeded sample of keys of the same workload, scaled to the whole job, and
+    its hits compared with the GPU's for those keys.
+
+Usage: python bench.py [--steps K] [--warmup W] [--config 1]
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ungapped extensions/sec and bank-vs-bank wall time (plain vs batched, bit-exact)"
+OPS_PER_EXT = 88           # 44 scan steps x (1 add + 1 max), int16
+# MI355X: 256 CUs x 64 VALU lanes x 2 int16 ops per packed instruction x 2.4 GHz
+PEAK_INT16_TOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ungapped_persistent_cfg1_traffic.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_0804_3643_amd", "csrc", "ungapped.hip")
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def recorded_traffic():
+    """HBM bytes per launch of the ungapped kernel from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    txt = open(TRAFFIC_FILE).read()
+    m = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", txt)
+    b = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m or not b or m.group(1) != kernel_source_hash():
+        return None
+    return float(b.group(1))
+
+
+def pair_keys_device(torch, hits):
+    h = hits.to(torch.int64)
+    k = (((h[:, 0] << 11) | h[:, 1]) << 28) | (h[:, 2] << 11) | h[:, 3]
+    k, o = torch.sort(k)
+    return k, h[o, 4]
+
+
+def cpu_baseline(w, gpu_hits_host, n_ext_total, sample_ext, s1, s2):
+    """Oracle (plain C) on a seeded key sample; returns the JSON object."""
+    import numpy as np
+
+    from oracle import coracle as C
+    from oracle import plast_oracle as O
+
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(cores, 16))
+    t0 = time.perf_counter()
+    i1, i2 = C.build_index(w.bank1), C.build_index(w.bank2)
+    t_index = time.perf_counter() - t0
+    work = np.diff(i1[0]) * np.diff(i2[0])
+    rng = np.random.default_rng(6513)
+    keys = []
+    acc = 0
+    for k in rng.permutation(np.nonzero(work)[0]):
+        keys.append(int(k))
+        acc += int(work[k])
+        if acc >= sample_ext:
+            break
+    keys = np.array(sorted(keys), dtype=np.int32)
+    t0 = time.perf_counter()
+    ref, n_ext_s = C.ungapped_hits(w.bank1, w.bank2, s1, keys=keys, idx1=i1, idx2=i2, nthreads=cores)
+    t_ung = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    g = C.gapped_scores(w.bank1, w.bank2, ref, nthreads=cores)
+    t_gap = time.perf_counter() - t0
+    # bit-exact check of the GPU hits on the sampled keys
+    c = w.bank1.codes
+    q = w.bank1.seq_start[gpu_hits_host[:, 0]] + gpu_hits_host[:, 1]
+    hk = O.seed_key(c[q].astype(np.int64), c[q + 1].astype(np.int64), c[q + 2].astype(np.int64),
+                    c[q + 3].astype(np.int64))
+    mine = O.canonical(gpu_hits_host[np.isin(hk, keys)])
+    equal = bool(np.array_equal(mine, ref))
+    t_job = t_index + (t_ung + t_gap) * (n_ext_total / max(1, n_ext_s))
+    return {
+        "value": n_ext_total / t_job, "unit": "ext/s", "cores": cores, "kind": "oracle",
+        "sample": ("plain C oracle, %d threads: index of both full banks (%.2f s) + %d seeded random keys "
+                   "(%d extensions, %.1f%% of the job; ungapped %.2f s, gapped on its %d hits %.2f s), "
+                   "scaled to all %d extensions" % (cores, t_index, len(keys), n_ext_s, 100.0 * n_ext_s /
+                                                    n_ext_total, t_ung, len(ref), t_gap, n_ext_total)),
+        "oracle_hits_equal_gpu_on_sample": equal, "n_gapped_pass_sample": int((g >= s2).sum()),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", type=int, default=1, help="synthetic workload (1 = 10,000 x 100,000 proteins)")
+    ap.add_argument("--plain-reps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-ext", type=float, default=1.5e9)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a 256 MiB device copy (counter scaling for rocprofv3 --pmc runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (the hot path is single-GPU); "
+              "--gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_0804_3643_amd import binding as B
+    from paper_0804_3643_amd import params, synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    B.load()
+    log("generating configuration %d" % args.config)
+    w = synth.make_workload(args.config)
+    spec = synth.CONFIGS[args.config]
+
+    # ---- resident inputs and preallocated buffers
+    ca, sa = B.bank_to_device(w.bank1, dev)
+    cb, sb = B.bank_to_device(w.bank2, dev)
+    iba, wba = B.index_bytes(ca.numel(), sa.numel() - 1)
+    ibb, wbb = B.index_bytes(cb.numel(), sb.numel() - 1)
+    buf_a = B._alloc(iba, dev)
+    buf_b = B._alloc(ibb, dev)
+    ws_idx = B._alloc(max(wba, wbb), dev)
+    ia = B.build_index(ca, sa, workspace=ws_idx, out_buf=buf_a)
+    ib = B.build_index(cb, sb, workspace=ws_idx, out_buf=buf_b)
+    ext = B.Extender(ia, ib, params.S1, mode="batched")
+    hits, n_ext = ext.run()
+    cap = ext.hits.shape[0]
+    gbuf = torch.empty(cap, dtype=torch.int32, device=dev)
+    pbuf = torch.empty(cap, dtype=torch.uint8, device=dev)
+
+    def step():
+        xa = B.build_index(ca, sa, workspace=ws_idx, out_buf=buf_a)
+        xb = B.build_index(cb, sb, workspace=ws_idx, out_buf=buf_b)
+        h, ne = ext.run(xa, xb)
+        B.gapped_filter(xa, xb, h, params.S2, out=(gbuf, pbuf))
+        return h, ne
+
+    log("warmup %d" % args.warmup)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    B.timing_enable(True)
+    stage_ms = {"index_ms": [], "plan_ms": [], "ungapped_ms": [], "gapped_ms": []}
+    log("timing %d steps" % args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        hits, n_ext = step()
+        t = B.timing_read()  # waits for this step's last kernel
+        for k in stage_ms:
+            stage_ms[k].append(t[k])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = dt * 1e3 / args.steps
+    n_hits = int(hits.shape[0])
+    n_pass = int(pbuf[:n_hits].sum().item())
+    batched_kernel_ms = float(np.mean(stage_ms["ungapped_ms"]))
+
+    # ---- PLAIN vs BATCHED (ungapped stage only), same output required
+    log("plain vs batched")
+    if args.plain_reps < 1:
+        B.timing_enable(False)
+        out = {"metric": METRIC, "value": n_ext / (ms_per_step * 1e-3), "unit": "ext/s", "n_gpus": 1,
+               "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+               "note": "profiling run (--plain-reps 0): plain schedule, wall times and baselines skipped",
+               "stages_device_ms": {k: float(np.mean(v)) for k, v in stage_ms.items()}}
+        if args.copy_calibration:
+            src = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
+            dst = torch.empty_like(src)
+            for _ in range(3):
+                dst.copy_(src)
+            torch.cuda.synchronize()
+        print(json.dumps(out), flush=True)
+        return
+    ext_p = B.Extender(ia, ib, params.S1, mode="plain", capacity=cap)
+    plain_ms, plain_wall = [], []
+    for _ in range(args.plain_reps):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        hp, ne_p = ext_p.run()
+        plain_wall.append(time.perf_counter() - t1)
+        tp = B.timing_read()
+        plain_ms.append(tp["ungapped_ms"])
+        plain_launches = tp["ungapped_launches"]
+    batched_wall = []
+    for _ in range(args.plain_reps):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        hb, ne_b = ext.run()
+        batched_wall.append(time.perf_counter() - t1)
+    kp, sp = pair_keys_device(torch, hp)
+    kb, sbat = pair_keys_device(torch, hb)
+    plain_eq = bool(ne_p == ne_b == n_ext and torch.equal(kp, kb) and torch.equal(sp, sbat))
+    assert plain_eq, "PLAIN and BATCHED hit lists differ"
+    no_dups = bool((kb[1:] != kb[:-1]).all().item()) if kb.numel() > 1 else True
+    del kp, sp, kb, sbat, hp
+    B.timing_enable(False)
+
+    # ---- bank-vs-bank wall time from host-resident banks to the host hit list
+    def bank_vs_bank(mode):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        xa_c, xa_s = B.bank_to_device(w.bank1, dev)
+        xb_c, xb_s = B.bank_to_device(w.bank2, dev)
+        xa = B.build_index(xa_c, xa_s, workspace=ws_idx, out_buf=buf_a)
+        xb = B.build_index(xb_c, xb_s, workspace=ws_idx, out_buf=buf_b)
+        e = ext if mode == "batched" else ext_p
+        h, _ = e.run(xa, xb)
+        g, p = B.gapped_filter(xa, xb, h, params.S2, out=(gbuf, pbuf))
+        host = (h.cpu(), g.cpu(), p.cpu())
+        torch.cuda.synchronize()
+        return time.perf_counter() - t1, host
+    log("bank-vs-bank wall")
+    wall_b, host_b = bank_vs_bank("batched")
+    wall_p, _ = bank_vs_bank("plain")
+    ext.run(ia, ib)  # restore views on the resident banks
+
+    if args.copy_calibration:
+        src = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+
+    achieved = n_ext * OPS_PER_EXT / (batched_kernel_ms * 1e-3) / 1e12
+    out = {
+        "metric": METRIC,
+        "value": n_ext / (ms_per_step * 1e-3),
+        "unit": "ext/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int16",
+        "data": "synthetic",
+        "config": {
+            "workload": "PLAST-P configuration %d: %s; seeded lognormal lengths (mean 300, clamped 50-1000), "
+                        "BLOSUM62 background residues; N=20, S1=%d, gapped window 64 band 16 open 11 extend 1 "
+                        "S2=%d" % (args.config, spec.description, params.S1, params.S2),
+            "bank1_proteins": w.bank1.n_seqs, "bank2_proteins": w.bank2.n_seqs,
+            "bank1_residues": w.bank1.n_residues, "bank2_residues": w.bank2.n_residues,
+            "step": "index both banks + batched ungapped extension + gapped filter",
+        },
+        "n_ext": n_ext, "n_hits": n_hits, "n_gapped_pass": n_pass,
+        "stages_device_ms": {k: float(np.mean(v)) for k, v in stage_ms.items()},
+        "ungapped": {
+            "batched_kernel_ms": batched_kernel_ms,
+            "batched_ext_per_s": n_ext / (batched_kernel_ms * 1e-3),
+            "plain_kernels_ms": float(np.mean(plain_ms)),
+            "plain_ext_per_s": n_ext / (float(np.mean(plain_ms)) * 1e-3),
+            "plain_launches": int(plain_launches),
+            "batched_call_wall_ms": 1e3 * float(np.min(batched_wall)),
+            "plain_call_wall_ms": 1e3 * float(np.min(plain_wall)),
+            "batched_over_plain_speedup": float(np.mean(plain_ms)) / batched_kernel_ms,
+        },
+        "bank_vs_bank_wall_s": {"batched": wall_b, "plain": wall_p},
+        "bit_exact": {"plain_equals_batched": plain_eq, "no_duplicate_pairs": no_dups},
+        "roofline": {
+            "bound": "alu", "achieved": achieved, "peak": PEAK_INT16_TOPS, "unit": "TOP/s",
+            "frac": achieved / PEAK_INT16_TOPS, "traffic": recorded_traffic(),
+            "kernel": "k_ungapped_persistent", "ops_per_ext": OPS_PER_EXT,
+        },
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle on a key sample)")
+        hh = host_b[0].numpy().astype(np.int64)
+        cb_ = cpu_baseline(w, hh, n_ext, args.cpu_sample_ext, params.S1, params.S2)
+        out["bit_exact"]["oracle_equals_gpu_on_sample_keys"] = cb_.pop("oracle_hits_equal_gpu_on_sample")
+        out["cpu_baseline"] = cb_
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -166,6 +166,25 @@ int plast_ungapped_extend(const plast_index_t* a, const plast_index_t* b, const 
 int plast_gapped_filter(const plast_index_t* a, const plast_index_t* b, const plast_hit_t* d_hits, int64_t n_hits,
                         const plast_gapped_params_t* g, int32_t* d_gscore, uint8_t* d_pass, void* stream);
 
+/*
+ * Kernel timing (tracing aid, not needed for results).  While enabled, the
+ * library records HIP events on the caller's stream around the kernels of each
+ * call; plast_timing_read() waits for the events of the most recent calls and
+ * reports device milliseconds.  Process-wide and not thread-safe: meant for
+ * benchmarks and profiling runs.
+ */
+typedef struct {
+  float index_ms;              /* last plast_build_index: from its first to its last kernel */
+  float plan_ms;               /* last PLAST_BATCHED extension: work-list kernels */
+  float ungapped_ms;           /* last plast_ungapped_extend: the extension kernel(s) only
+                                  (all per-key grids in PLAST_PLAIN mode) */
+  float gapped_ms;             /* last plast_gapped_filter: its kernel */
+  int64_t ungapped_launches;   /* extension-kernel launches of the last extension call */
+} plast_timing_t;
+
+int plast_timing_enable(int on);
+int plast_timing_read(plast_timing_t* out);
+
 const char* plast_strerror(int code);
 const char* plast_last_error(void);
 

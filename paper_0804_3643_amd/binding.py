@@ -25,7 +25,7 @@ MODES = {"plain": PLAIN, "batched": BATCHED}
 OK, E_ARG, E_ALPHABET, E_CAPACITY, E_WORKSPACE, E_HIP, E_LAYOUT = 0, -1, -2, -3, -4, -5, -6
 
 EXPORTS = ("plast_index_bytes", "plast_build_index", "plast_ungapped_workspace_bytes", "plast_ungapped_extend",
-           "plast_gapped_filter", "plast_strerror", "plast_last_error")
+           "plast_gapped_filter", "plast_timing_enable", "plast_timing_read", "plast_strerror", "plast_last_error")
 
 
 class PlastError(RuntimeError):
@@ -38,6 +38,11 @@ class IndexView(ctypes.Structure):
     _fields_ = [("codes", ctypes.c_void_p), ("seq_start", ctypes.c_void_p), ("n_seqs", ctypes.c_int32),
                 ("n_padded", ctypes.c_int64), ("key_off", ctypes.c_void_p), ("occ", ctypes.c_void_p),
                 ("occ_seq", ctypes.c_void_p), ("scan_codes", ctypes.c_void_p), ("n_words", ctypes.c_int64)]
+
+
+class Timing(ctypes.Structure):
+    _fields_ = [("index_ms", ctypes.c_float), ("plan_ms", ctypes.c_float), ("ungapped_ms", ctypes.c_float),
+                ("gapped_ms", ctypes.c_float), ("ungapped_launches", ctypes.c_int64)]
 
 
 class UngappedParams(ctypes.Structure):
@@ -70,8 +75,10 @@ def load():
                                               ctypes.POINTER(i64), ctypes.POINTER(i64), P]
         lib.plast_gapped_filter.argtypes = [ctypes.POINTER(IndexView), ctypes.POINTER(IndexView), P, i64,
                                             ctypes.POINTER(GappedParams), P, P, P]
+        lib.plast_timing_enable.argtypes = [ctypes.c_int]
+        lib.plast_timing_read.argtypes = [ctypes.POINTER(Timing)]
         for f in ("plast_index_bytes", "plast_build_index", "plast_ungapped_workspace_bytes",
-                  "plast_ungapped_extend", "plast_gapped_filter"):
+                  "plast_ungapped_extend", "plast_gapped_filter", "plast_timing_enable", "plast_timing_read"):
             getattr(lib, f).restype = ctypes.c_int
         lib.plast_strerror.argtypes = [ctypes.c_int]
         lib.plast_strerror.restype = ctypes.c_char_p
@@ -154,13 +161,15 @@ def index_bytes(n_padded, n_seqs):
     return ib.value, wb.value
 
 
-def build_index(codes, seq_start, stream=None, workspace=None):
-    """Stage 0 on the device: ``codes`` uint8 and ``seq_start`` int64 CUDA tensors."""
+def build_index(codes, seq_start, stream=None, workspace=None, out_buf=None):
+    """Stage 0 on the device: ``codes`` uint8 and ``seq_start`` int64 CUDA tensors.
+    ``workspace`` / ``out_buf`` (uint8 device tensors of at least
+    :func:`index_bytes` sizes) are used instead of allocating when given."""
     assert codes.is_cuda and codes.dtype == torch.uint8 and seq_start.dtype == torch.int64
     n_seqs = seq_start.numel() - 1
     n_padded = codes.numel()
     ib, wb = index_bytes(n_padded, n_seqs)
-    buf = _alloc(ib, codes.device)
+    buf = out_buf if out_buf is not None and out_buf.numel() >= ib else _alloc(ib, codes.device)
     ws = workspace if workspace is not None and workspace.numel() >= wb else _alloc(wb, codes.device)
     view = IndexView()
     _check(load().plast_build_index(_ptr(codes), _ptr(seq_start), n_seqs, n_padded, _ptr(buf), buf.numel(),
@@ -199,7 +208,12 @@ class Extender:
         self.params = UngappedParams(NBR, int(s1), mp)
         self.stream = stream
 
-    def run(self):
+    def run(self, ia=None, ib=None):
+        """One extension call; ``ia``/``ib`` replace the index views (same sizes)."""
+        if ia is not None:
+            self.ia = ia
+        if ib is not None:
+            self.ib = ib
         n_hits, n_ext = ctypes.c_int64(0), ctypes.c_int64(0)
         while True:
             rc = load().plast_ungapped_extend(ctypes.byref(self.ia.view), ctypes.byref(self.ib.view),
@@ -244,3 +258,14 @@ def canonical_hits(hits):
     if len(h) == 0:
         return h
     return h[np.lexsort(h.T[::-1])]
+
+
+def timing_enable(on=True):
+    _check(load().plast_timing_enable(1 if on else 0), "plast_timing_enable")
+
+
+def timing_read():
+    t = Timing()
+    _check(load().plast_timing_read(ctypes.byref(t)), "plast_timing_read")
+    return {"index_ms": t.index_ms, "plan_ms": t.plan_ms, "ungapped_ms": t.ungapped_ms, "gapped_ms": t.gapped_ms,
+            "ungapped_launches": int(t.ungapped_launches)}

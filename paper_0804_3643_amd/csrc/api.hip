@@ -79,6 +79,22 @@ int hip_check(hipError_t e, const char* what) {
   return set_error(PLAST_E_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
+// ---------------------------------------------------------------- timing
+static bool g_timing = false;
+static hipEvent_t g_ev[kNumStages][2];
+static bool g_ev_made = false;
+static bool g_ev_used[kNumStages];
+static int64_t g_launches = 0;
+
+bool timing_on() { return g_timing; }
+
+void timing_mark(TimedStage st, bool stop, hipStream_t s) {
+  if (!g_timing) return;
+  if (hipEventRecord(g_ev[st][stop ? 1 : 0], s) == hipSuccess && stop) g_ev_used[st] = true;
+}
+
+void timing_launches(int64_t n) { g_launches = n; }
+
 }  // namespace plast
 
 using namespace plast;
@@ -99,6 +115,35 @@ const char* plast_strerror(int code) {
 }
 
 const char* plast_last_error(void) { return g_last_error; }
+
+int plast_timing_enable(int on) {
+  g_last_error[0] = 0;
+  if (on && !g_ev_made) {
+    for (int i = 0; i < kNumStages; ++i)
+      for (int j = 0; j < 2; ++j) PLAST_HIP(hipEventCreate(&g_ev[i][j]));
+    g_ev_made = true;
+  }
+  g_timing = on != 0;
+  for (int i = 0; i < kNumStages; ++i) g_ev_used[i] = false;
+  return PLAST_OK;
+}
+
+int plast_timing_read(plast_timing_t* out) {
+  g_last_error[0] = 0;
+  if (!out) return set_error(PLAST_E_ARG, "null output pointer");
+  float ms[kNumStages] = {0.f, 0.f, 0.f, 0.f};
+  for (int i = 0; i < kNumStages; ++i) {
+    if (!g_ev_made || !g_ev_used[i]) continue;
+    PLAST_HIP(hipEventSynchronize(g_ev[i][1]));
+    PLAST_HIP(hipEventElapsedTime(&ms[i], g_ev[i][0], g_ev[i][1]));
+  }
+  out->index_ms = ms[kStageIndex];
+  out->plan_ms = ms[kStagePlan];
+  out->ungapped_ms = ms[kStageUngapped];
+  out->gapped_ms = ms[kStageGapped];
+  out->ungapped_launches = g_launches;
+  return PLAST_OK;
+}
 
 int plast_index_bytes(int64_t n_padded, int32_t n_seqs, size_t* index_bytes, size_t* ws_bytes) {
   if (!index_bytes || !ws_bytes) return set_error(PLAST_E_ARG, "null output pointer");

@@ -172,11 +172,13 @@ int gapped_filter_impl(const plast_index_t* a, const plast_index_t* b, const pla
     for (int y = 0; y < 22; ++y)
       G.mat[x * 22 + y] = (x < 20 && y < 20) ? m[x * 20 + y] : kWallScore;
   unsigned blocks = (unsigned)((n_hits + kGThreads - 1) / kGThreads);
+  timing_mark(kStageGapped, false, stream);
   if (g->band == kGMaxBand)
     hipLaunchKernelGGL(k_gapped<kGMaxBand>, dim3(blocks), dim3(kGThreads), 0, stream, G, d_hits, n_hits, d_gscore,
                        d_pass);
   else
     hipLaunchKernelGGL(k_gapped<-1>, dim3(blocks), dim3(kGThreads), 0, stream, G, d_hits, n_hits, d_gscore, d_pass);
+  timing_mark(kStageGapped, true, stream);
   PLAST_HIP(hipGetLastError());
   return PLAST_OK;
 }

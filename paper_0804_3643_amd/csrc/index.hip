@@ -297,6 +297,7 @@ int build_index_impl(const uint8_t* d_codes, const int64_t* d_seq_start, int32_t
   if (h_err[0] & 1) return set_error(PLAST_E_LAYOUT, "seq_start does not describe the padded layout");
 
   SeedClasses sc = seed_classes();
+  timing_mark(kStageIndex, false, stream);
   int64_t waves = (int64_t)n_seqs + 1;
   hipLaunchKernelGGL(k_codes_check, dim3((unsigned)((waves * 64 + 255) / 256)), dim3(256), 0, stream, d_codes,
                      d_seq_start, n_seqs, n_padded, scan, scan_len, err);
@@ -307,6 +308,7 @@ int build_index_impl(const uint8_t* d_codes, const int64_t* d_seq_start, int32_t
                      d_seq_start, n_seqs, n_padded, C.chunk, C.nchunks, sc, (const int32_t*)counts, occ, occ_seq);
   hipLaunchKernelGGL(k_key_off, dim3((kNKeys + 1 + 255) / 256), dim3(256), 0, stream, (const int32_t*)counts,
                      C.nchunks, (const int32_t*)total, key_off);
+  timing_mark(kStageIndex, true, stream);
   PLAST_HIP(hipGetLastError());
   PLAST_HIP(hipMemcpyAsync(h_err, err, sizeof(h_err), hipMemcpyDeviceToHost, stream));
   PLAST_HIP(hipStreamSynchronize(stream));

@@ -55,6 +55,13 @@ int hip_check(hipError_t e, const char* what);
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// ---------------------------------------------------------------- timing
+enum TimedStage { kStageIndex = 0, kStagePlan = 1, kStageUngapped = 2, kStageGapped = 3, kNumStages = 4 };
+bool timing_on();
+// Record the start / stop event of a stage on `s` (no-ops while timing is off).
+void timing_mark(TimedStage st, bool stop, hipStream_t s);
+void timing_launches(int64_t n);
+
 // ---------------------------------------------------------------- index build
 struct IndexLayout {
   size_t key_off, occ, occ_seq, scan, total;
@@ -78,8 +85,8 @@ void exclusive_scan_i32(int32_t* d_data, int64_t n, int32_t* d_total, void* d_tm
 // ---------------------------------------------------------------- ungapped
 constexpr int kTileRows = 32;           // bank-a occurrences per work item (profile rows)
 constexpr int kRowGroups = kTileRows / 4;
-constexpr int kThreads = 256;           // threads per workgroup
-constexpr int kColsPerLane = 8;         // bank-b occurrences per lane per item
+constexpr int kThreads = 512;           // threads per workgroup (8 wavefronts share one profile)
+constexpr int kColsPerLane = 4;         // bank-b occurrences per lane per item
 constexpr int kTileCols = kThreads * kColsPerLane;
 
 struct WorkItem {

@@ -64,21 +64,37 @@ struct UngappedArgs {
   int16_t mat[kNLet * kNLet];  // [a letter][b letter], separator row/column = kSepScore
 };
 
+// Hits found in an item are staged in LDS as (row | score << 5, seq2, pos2)
+// and written out once per item with one global atomic; a wavefront whose
+// reservation does not fit the staging area writes its hits directly.
+constexpr int kHitSlots = 1024;
+
 struct __align__(16) Smem {
   uint8_t prof[kProfBytes];            // 8-byte entries (offset 0)
-  uint8_t rowlet[kSpan * kTileRows];   // read as 4-byte groups (offset 59136)
+  uint8_t rowlet[kSpan * kTileRows];   // read as 4-byte groups
   int32_t rowq[kTileRows];
   int32_t rowseq[kTileRows];
   int32_t rowpos[kTileRows];
+  uint32_t hit_rs[kHitSlots];          // row | score << 5
+  int32_t hit_seq[kHitSlots];
+  int32_t hit_pos[kHitSlots];
+  int32_t n_hit;                       // slots reserved so far in this item
+  int32_t n_fit;                       // end of the last reservation that fitted
+  int32_t n_flush;                     // staged hits of the item being flushed
   int32_t item;
+  unsigned long long hit_base;
   int16_t mat[kNLet * kNLet];
 };
 static_assert(offsetof(Smem, rowlet) % 16 == 0 && offsetof(Smem, rowq) % 4 == 0, "LDS alignment");
 
 __device__ __forceinline__ s16x2 as_s16x2(uint32_t v) { return __builtin_bit_cast(s16x2, v); }
 
-__device__ __forceinline__ void load_matrix(const UngappedArgs& A, Smem& S) {
+__device__ __forceinline__ void smem_init(const UngappedArgs& A, Smem& S) {
   for (int i = threadIdx.x; i < kNLet * kNLet; i += kThreads) S.mat[i] = A.mat[i];
+  if (threadIdx.x == 0) {
+    S.n_hit = 0;
+    S.n_fit = 0;
+  }
 }
 
 __device__ __forceinline__ int wave_incl_scan(int v) {
@@ -91,16 +107,11 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
   return v;
 }
 
-__device__ void run_item(const UngappedArgs& A, const WorkItem it, Smem& S) {
+// Rows of the tile (bank-a occurrences row0 .. row0+rows-1 of the key) and
+// their 44-step profile.
+__device__ __forceinline__ void build_profile(const UngappedArgs& A, const WorkItem& it, int64_t a0, int rows,
+                                              Smem& S) {
   const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wid = tid >> 6;
-  const int64_t a0 = A.a.key_off[it.key];
-  const int n1 = (int)(A.a.key_off[it.key + 1] - a0);
-  const int rows = min(kTileRows, n1 - it.row0);
-  const int64_t b0 = A.b.key_off[it.key];
-
-  // ---- rows of the tile: occurrence, sequence, position
   if (tid < kTileRows) {
     int q = -1, sq = 0, ps = 0;
     if (tid < rows) {
@@ -125,7 +136,7 @@ __device__ void run_item(const UngappedArgs& A, const WorkItem it, Smem& S) {
     S.rowlet[t * kTileRows + r] = (uint8_t)letter;
   }
   __syncthreads();
-  // ---- profile: prof[rg][t][c] = scores of rows 4rg..4rg+3 at step t against letter c
+  // prof[rg][t][c] = scores of rows 4rg..4rg+3 at step t against bank-b letter c
   for (int e = tid; e < kRowGroups * kSpan * kNLet; e += kThreads) {
     int rg = e / (kSpan * kNLet);
     int rem = e - rg * (kSpan * kNLet);
@@ -142,102 +153,218 @@ __device__ void run_item(const UngappedArgs& A, const WorkItem it, Smem& S) {
     *(uint2*)&S.prof[rg * kProfRG + t * kProfT + c * 8] = w;
   }
   __syncthreads();
+}
 
-  // ---- columns: lane owns bank-b occurrences col0 + tid + 256*k
-  const int col_end = it.col0 + it.ncols;
-  for (int k = 0; k < kColsPerLane; ++k) {
-    const int wave_first = it.col0 + wid * 64 + kThreads * k;
-    if (wave_first >= col_end) break;  // uniform in the wavefront
-    const int j = it.col0 + tid + kThreads * k;
-    const bool active = j < col_end;
-    const int64_t o = b0 + (active ? j : it.col0);
-    const int q2 = A.b.occ[o];
-    const int s2 = A.b.occ_seq[o];
-    const int base = q2 - kNbr;
-    const uint32_t* src = (const uint32_t*)A.b.scan + (base >> 2);
-    uint32_t d[12];
+// The 44-step scan of one bank-b window against the 32 profile rows.
+// win: the window as (letter * 8) bytes, byte b = position q - 20 + b.
+// Returns best-right + best-left for each row as packed int16 pairs in m.
+__device__ __forceinline__ void scan_window(const Smem& S, const uint32_t (&win)[11], s16x2 (&m)[2 * kRowGroups]) {
+  s16x2 s[2 * kRowGroups];
+  uint2 cur[kRowGroups], nxt[kRowGroups];
+  auto addr = [&](int t) {
+    const int bidx = t < kRight ? kNbr + t : (kSpan - 1) - t;
+    const uint32_t c8 = (win[bidx >> 2] >> (8 * (bidx & 3))) & 0xffu;
+    return S.prof + c8 + t * kProfT;
+  };
+  {
+    const uint8_t* p = addr(0);
 #pragma unroll
-    for (int i = 0; i < 12; ++i) d[i] = src[i];
-    const int sh = base & 3;
-    uint32_t win[11];
+    for (int rg = 0; rg < kRowGroups; ++rg) cur[rg] = *(const uint2*)(p + rg * kProfRG);
+  }
 #pragma unroll
-    for (int i = 0; i < 11; ++i) win[i] = __builtin_amdgcn_alignbyte(d[i + 1], d[i], sh);
-
-    s16x2 s[2 * kRowGroups], m[2 * kRowGroups];
+  for (int t = 0; t < kSpan; ++t) {
+    if (t + 1 < kSpan) {
+      const uint8_t* p = addr(t + 1);
 #pragma unroll
-    for (int t = 0; t < kSpan; ++t) {
-      const int bidx = t < kRight ? kNbr + t : (kSpan - 1) - t;
-      const uint32_t c8 = (win[bidx >> 2] >> (8 * (bidx & 3))) & 0xffu;
-      const uint8_t* p = S.prof + c8 + t * kProfT;
-      if (t == kRight) {
+      for (int rg = 0; rg < kRowGroups; ++rg) nxt[rg] = *(const uint2*)(p + rg * kProfRG);
+    }
+    if (t == kRight) {
 #pragma unroll
-        for (int i = 0; i < 2 * kRowGroups; ++i) s[i] = m[i];
-      }
+      for (int i = 0; i < 2 * kRowGroups; ++i) s[i] = m[i];
+    }
 #pragma unroll
-      for (int rg = 0; rg < kRowGroups; ++rg) {
-        const uint2 v = *(const uint2*)(p + rg * kProfRG);
-        const s16x2 x = as_s16x2(v.x), y = as_s16x2(v.y);
-        if (t == 0) {
-          const s16x2 z = {0, 0};
-          s[2 * rg] = x;
-          s[2 * rg + 1] = y;
-          m[2 * rg] = __builtin_elementwise_max(x, z);
-          m[2 * rg + 1] = __builtin_elementwise_max(y, z);
-        } else {
-          s[2 * rg] += x;
-          s[2 * rg + 1] += y;
-          m[2 * rg] = __builtin_elementwise_max(m[2 * rg], s[2 * rg]);
-          m[2 * rg + 1] = __builtin_elementwise_max(m[2 * rg + 1], s[2 * rg + 1]);
-        }
+    for (int rg = 0; rg < kRowGroups; ++rg) {
+      const s16x2 x = as_s16x2(cur[rg].x), y = as_s16x2(cur[rg].y);
+      if (t == 0) {
+        const s16x2 z = {0, 0};
+        s[2 * rg] = x;
+        s[2 * rg + 1] = y;
+        m[2 * rg] = __builtin_elementwise_max(x, z);
+        m[2 * rg + 1] = __builtin_elementwise_max(y, z);
+      } else {
+        s[2 * rg] += x;
+        s[2 * rg + 1] += y;
+        m[2 * rg] = __builtin_elementwise_max(m[2 * rg], s[2 * rg]);
+        m[2 * rg + 1] = __builtin_elementwise_max(m[2 * rg + 1], s[2 * rg + 1]);
       }
     }
-    // ---- hits
-    s16x2 mx = m[0];
+    if (t + 1 < kSpan) {
 #pragma unroll
-    for (int i = 1; i < 2 * kRowGroups; ++i) mx = __builtin_elementwise_max(mx, m[i]);
-    const int best = max((int)mx.x, (int)mx.y);
-    const bool cand = active && best >= A.s1;
-    if (__ballot(cand)) {
-      uint32_t mask = 0;
-      if (cand) {
+      for (int rg = 0; rg < kRowGroups; ++rg) cur[rg] = nxt[rg];
+    }
+  }
+}
+
+__device__ __forceinline__ int row_score(const s16x2 (&m)[2 * kRowGroups], int r) {
+  return (r & 1) ? (int)m[r >> 1].y : (int)m[r >> 1].x;
+}
+
+__device__ __forceinline__ void emit_hits(const UngappedArgs& A, Smem& S, const s16x2 (&m)[2 * kRowGroups],
+                                          bool active, int rows, int s2, int p2) {
+  const int lane = __lane_id();
+  s16x2 mx = m[0];
 #pragma unroll
-        for (int r = 0; r < kTileRows; ++r) {
-          const int v = (r & 1) ? (int)m[r >> 1].y : (int)m[r >> 1].x;
-          if (r < rows && v >= A.s1) mask |= 1u << r;
-        }
+  for (int i = 1; i < 2 * kRowGroups; ++i) mx = __builtin_elementwise_max(mx, m[i]);
+  const bool cand = active && max((int)mx.x, (int)mx.y) >= A.s1;
+  if (!__ballot(cand)) return;
+  uint32_t mask = 0;
+  if (cand) {
+#pragma unroll
+    for (int r = 0; r < kTileRows; ++r)
+      if (r < rows && row_score(m, r) >= A.s1) mask |= 1u << r;
+  }
+  const int cnt = __popc(mask);
+  const int incl = wave_incl_scan(cnt);
+  const int total = __shfl(incl, 63);
+  int base = 0;
+  if (lane == 63) {
+    base = atomicAdd(&S.n_hit, total);
+    if (base + total <= kHitSlots) atomicMax(&S.n_fit, base + total);
+  }
+  base = __shfl(base, 63);
+  if (base + total <= kHitSlots) {  // staged in LDS
+    int at = base + incl - cnt;
+#pragma unroll
+    for (int r = 0; r < kTileRows; ++r) {
+      if (mask & (1u << r)) {
+        S.hit_rs[at] = (uint32_t)r | ((uint32_t)row_score(m, r) << 5);
+        S.hit_seq[at] = s2;
+        S.hit_pos[at] = p2;
+        ++at;
       }
-      const int cnt = __popc(mask);
-      const int incl = wave_incl_scan(cnt);
-      unsigned long long at = 0;
-      if (lane == 63 && incl > 0) at = atomicAdd(A.n_hits, (unsigned long long)incl);
-      at = __shfl(at, 63) + (unsigned long long)(incl - cnt);
-      if (mask) {
-        const int p2 = q2 - (int)A.b.seq_start[s2];
+    }
+  } else {  // staging area full: write directly
+    unsigned long long g = 0;
+    if (lane == 63) g = atomicAdd(A.n_hits, (unsigned long long)total);
+    g = __shfl(g, 63) + (unsigned long long)(incl - cnt);
 #pragma unroll
-        for (int r = 0; r < kTileRows; ++r) {
-          if (mask & (1u << r)) {
-            if (at < (unsigned long long)A.capacity) {
-              plast_hit_t h;
-              h.seq1 = S.rowseq[r];
-              h.pos1 = S.rowpos[r];
-              h.seq2 = s2;
-              h.pos2 = p2;
-              h.score = (r & 1) ? (int)m[r >> 1].y : (int)m[r >> 1].x;
-              A.hits[at] = h;
-            }
-            ++at;
-          }
+    for (int r = 0; r < kTileRows; ++r) {
+      if (mask & (1u << r)) {
+        if (g < (unsigned long long)A.capacity) {
+          plast_hit_t h;
+          h.seq1 = S.rowseq[r];
+          h.pos1 = S.rowpos[r];
+          h.seq2 = s2;
+          h.pos2 = p2;
+          h.score = row_score(m, r);
+          A.hits[g] = h;
         }
+        ++g;
       }
     }
   }
-  __syncthreads();  // LDS is rebuilt by the next item
 }
 
-__global__ __launch_bounds__(kThreads) void k_ungapped_plain(UngappedArgs A, int32_t key, int32_t n_row_tiles,
-                                                             int32_t n2) {
+// Every thread calls this (it contains barriers); it ends with a barrier so the
+// next item may overwrite the staging area and the row data.
+__device__ __forceinline__ void flush_hits(const UngappedArgs& A, Smem& S) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int n = min(S.n_hit, S.n_fit);
+    S.n_flush = n;
+    S.hit_base = n ? atomicAdd(A.n_hits, (unsigned long long)n) : 0ull;
+    S.n_hit = 0;
+    S.n_fit = 0;
+  }
+  __syncthreads();
+  const int n = __builtin_amdgcn_readfirstlane(S.n_flush);
+  const unsigned long long base = S.hit_base;
+  for (int e = threadIdx.x; e < n; e += kThreads) {
+    if (base + e < (unsigned long long)A.capacity) {
+      const uint32_t rs = S.hit_rs[e];
+      plast_hit_t h;
+      h.seq1 = S.rowseq[rs & 31u];
+      h.pos1 = S.rowpos[rs & 31u];
+      h.seq2 = S.hit_seq[e];
+      h.pos2 = S.hit_pos[e];
+      h.score = (int)(rs >> 5);
+      A.hits[base + e] = h;
+    }
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ void load_window_raw(const UngappedArgs& A, int q2, uint32_t (&raw)[12]) {
+  const uint32_t* src = (const uint32_t*)A.b.scan + ((q2 - kNbr) >> 2);
+#pragma unroll
+  for (int i = 0; i < 12; ++i) raw[i] = src[i];
+}
+
+// All threads of the workgroup call run_item with the same item (it contains
+// barriers); every branch around a barrier depends only on wave-uniform values.
+__device__ void run_item(const UngappedArgs& A, const WorkItem it, Smem& S) {
+  const int tid = threadIdx.x;
+  const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t a0 = A.a.key_off[it.key];
+  const int n1 = (int)(A.a.key_off[it.key + 1] - a0);
+  const int rows = min(kTileRows, n1 - it.row0);
+  const int64_t b0 = A.b.key_off[it.key];
+  build_profile(A, it, a0, rows, S);
+
+  // Lane columns: col0 + tid + kThreads * k.  Column data is software-pipelined:
+  // the occurrence two columns ahead and the window one column ahead are in
+  // flight while the current column is scanned.
+  const int col_end = it.col0 + it.ncols;
+  int nk = 0;  // column steps of this wavefront
+  while (nk < kColsPerLane && it.col0 + wid * 64 + kThreads * nk < col_end) ++nk;
+  nk = __builtin_amdgcn_readfirstlane(nk);
+  auto occ_index = [&](int k) {
+    const int j = it.col0 + tid + kThreads * k;
+    return b0 + (j < col_end ? j : it.col0);
+  };
+  int q_cur = 0, s_cur = 0, q_nxt = 0, s_nxt = 0;
+  uint32_t raw[12];
+  if (nk > 0) {
+    const int64_t o = occ_index(0);
+    q_cur = A.b.occ[o];
+    s_cur = A.b.occ_seq[o];
+    load_window_raw(A, q_cur, raw);
+  }
+  if (nk > 1) {
+    const int64_t o = occ_index(1);
+    q_nxt = A.b.occ[o];
+    s_nxt = A.b.occ_seq[o];
+  }
+  for (int k = 0; k < nk; ++k) {
+    const bool active = it.col0 + tid + kThreads * k < col_end;
+    const int q2 = q_cur, s2 = s_cur;
+    uint32_t win[11];
+    const int sh = (q2 - kNbr) & 3;
+#pragma unroll
+    for (int i = 0; i < 11; ++i) win[i] = __builtin_amdgcn_alignbyte(raw[i + 1], raw[i], sh);
+    if (k + 1 < nk) {
+      load_window_raw(A, q_nxt, raw);
+      q_cur = q_nxt;
+      s_cur = s_nxt;
+    }
+    if (k + 2 < nk) {
+      const int64_t o = occ_index(k + 2);
+      q_nxt = A.b.occ[o];
+      s_nxt = A.b.occ_seq[o];
+    }
+    const int st2 = (int)A.b.seq_start[s2];
+    s16x2 m[2 * kRowGroups];
+    scan_window(S, win, m);
+    emit_hits(A, S, m, active, rows, s2, q2 - st2);
+  }
+  flush_hits(A, S);  // ends with a barrier: LDS may be rebuilt by the next item
+}
+
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
+void k_ungapped_plain(UngappedArgs A, int32_t key, int32_t n_row_tiles, int32_t n2) {
   __shared__ Smem S;
-  load_matrix(A, S);
+  smem_init(A, S);
+  __syncthreads();
   WorkItem it;
   it.key = key;
   it.row0 = (int32_t)(blockIdx.x % n_row_tiles) * kTileRows;
@@ -246,17 +373,19 @@ __global__ __launch_bounds__(kThreads) void k_ungapped_plain(UngappedArgs A, int
   run_item(A, it, S);
 }
 
-__global__ __launch_bounds__(kThreads) void k_ungapped_persistent(UngappedArgs A, const WorkItem* __restrict__ items,
-                                                                  const int32_t* __restrict__ n_items_p,
-                                                                  const int32_t* __restrict__ overflow,
-                                                                  int32_t* __restrict__ ctr) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
+void k_ungapped_persistent(UngappedArgs A, const WorkItem* __restrict__ items, const int32_t* __restrict__ n_items_p,
+                           const int32_t* __restrict__ overflow, int32_t* __restrict__ ctr) {
   __shared__ Smem S;
-  load_matrix(A, S);
-  const int n_items = *overflow ? 0 : *n_items_p;
+  smem_init(A, S);
+  const int n_items = __builtin_amdgcn_readfirstlane(*overflow ? 0 : *n_items_p);
+  // The item index is read back as a scalar so that the loop exit is uniform:
+  // with a per-lane exit the compiler may let lanes other than thread 0 reach
+  // the barrier below before thread 0 has fetched the next item.
   for (;;) {
     if (threadIdx.x == 0) S.item = atomicAdd(ctr, 1);
     __syncthreads();
-    const int i = S.item;
+    const int i = __builtin_amdgcn_readfirstlane(S.item);
     if (i >= n_items) break;
     run_item(A, items[i], S);
   }
@@ -416,7 +545,8 @@ int ungapped_extend_impl(const plast_index_t* a, const plast_index_t* b, const p
     int rc;
     if ((rc = read_key_offsets(a, ha, stream)) || (rc = read_key_offsets(b, hb, stream))) return rc;
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, stream, (uint32_t*)d_ws, (int64_t)8, 0u);
-    int64_t n_ext = 0;
+    int64_t n_ext = 0, launches = 0;
+    timing_mark(kStageUngapped, false, stream);
     for (int k = 0; k < kNKeys; ++k) {
       int64_t n1 = ha[k + 1] - ha[k], n2 = hb[k + 1] - hb[k];
       if (n1 <= 0 || n2 <= 0) continue;
@@ -424,7 +554,10 @@ int ungapped_extend_impl(const plast_index_t* a, const plast_index_t* b, const p
       int64_t nrt = (n1 + kTileRows - 1) / kTileRows, nct = (n2 + kTileCols - 1) / kTileCols;
       hipLaunchKernelGGL(k_ungapped_plain, dim3((unsigned)(nrt * nct)), dim3(kThreads), 0, stream, A, k,
                          (int32_t)nrt, (int32_t)n2);
+      ++launches;
     }
+    timing_mark(kStageUngapped, true, stream);
+    timing_launches(launches);
     PLAST_HIP(hipGetLastError());
     PLAST_HIP(hipMemcpyAsync(h_cnt, W.n_hits, sizeof(unsigned long long), hipMemcpyDeviceToHost, stream));
     PLAST_HIP(hipStreamSynchronize(stream));
@@ -435,13 +568,18 @@ int ungapped_extend_impl(const plast_index_t* a, const plast_index_t* b, const p
     int grid = persistent_grid();
     if (grid <= 0) return set_error(PLAST_E_HIP, "cannot query device occupancy");
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, stream, (uint32_t*)d_ws, (int64_t)8, 0u);
+    timing_mark(kStagePlan, false, stream);
     hipLaunchKernelGGL(k_plan_count, dim3((kNKeys + 255) / 256), dim3(256), 0, stream, a->key_off, b->key_off,
                        W.cnt, W.n_ext);
     exclusive_scan_i32(W.cnt, kNKeys, W.total, W.scan_tmp, stream);
     hipLaunchKernelGGL(k_plan_emit, dim3(kNKeys), dim3(256), 0, stream, a->key_off, b->key_off,
                        (const int32_t*)W.cnt, (const int32_t*)W.total, W.max_items, W.items, W.overflow);
+    timing_mark(kStagePlan, true, stream);
+    timing_mark(kStageUngapped, false, stream);
     hipLaunchKernelGGL(k_ungapped_persistent, dim3(grid), dim3(kThreads), 0, stream, A,
                        (const WorkItem*)W.items, (const int32_t*)W.total, (const int32_t*)W.overflow, W.ctr);
+    timing_mark(kStageUngapped, true, stream);
+    timing_launches(1);
     PLAST_HIP(hipGetLastError());
     int32_t ovf = 0;
     PLAST_HIP(hipMemcpyAsync(h_cnt, W.n_hits, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, stream));
