@@ -86,7 +86,7 @@ void exclusive_scan_i32(int32_t* d_data, int64_t n, int32_t* d_total, void* d_tm
 constexpr int kTileRows = 32;           // bank-a occurrences per work item (profile rows)
 constexpr int kRowGroups = kTileRows / 4;
 constexpr int kThreads = 512;           // threads per workgroup (8 wavefronts share one profile)
-constexpr int kColsPerLane = 4;         // bank-b occurrences per lane per item
+constexpr int kColsPerLane = 8;         // bank-b occurrences per lane per item
 constexpr int kTileCols = kThreads * kColsPerLane;
 
 struct WorkItem {

@@ -1,25 +1,33 @@
 // Stage 2, ungapped extension (Sec. 3.2 generic algorithm, Sec. 3.3.3), with
 // hit compaction and two schedules over the same tile routine.
 //
-// Tile routine.  A work item is (key, 32 bank-a occurrences, up to 2048 bank-b
-// occurrences).  The 32 rows are turned into a profile in LDS: for scan step t
-// (t < 24: letter p+t; t >= 24: letter p-(t-23)) and bank-b letter c, the 8-byte
-// entry holds the substitution scores of four rows as int16 (59 KB for 32 rows
-// x 44 steps x 21 letters).  Each lane owns one bank-b occurrence: its 44-letter
+// Tile routine.  A work item is (key, 32 bank-a occurrences, up to 4096 bank-b
+// occurrences).  The 32 rows become a profile in LDS: for scan step t (t < 24:
+// letter p+t; t >= 24: letter p-(t-23)) and bank-b letter c, an 8-byte entry
+// holds the substitution scores of four rows (59 KB for 32 rows x 44 steps x 21
+// letters).  Each lane owns one bank-b occurrence at a time: its 44-letter
 // window sits in 11 registers as (letter * 8) bytes, so one bit-field extract
 // gives the LDS address of the entry and eight 8-byte LDS reads give the scores
-// of all 32 rows; the running sum and running best are packed int16 pairs
-// (v_pk_add_u16 / v_pk_max_i16), one instruction each per two pairs.  At step 24
-// the running sum is reset to the running best, so the best of the leftward
-// prefixes is added to the best rightward prefix (the composition of the GPU
-// kernel of Annex 4).  Letters outside a sequence are separators scoring
+// of all 32 rows.  Running sums and running bests are packed pairs, two rows per
+// register.  At step 24 the running sum is reset to the running best, so the
+// best leftward prefix is added to the best rightward prefix (the composition of
+// the GPU kernel of Annex 4).  Letters outside a sequence are separators scoring
 // kSepScore <= 0 against everything; the separator run after a sequence is at
 // least as long as the scan, so a scan that leaves its sequence only meets
 // separators and its best prefix is the clipped one.
 //
-// Hits: per lane a 32-bit mask of rows with score >= s1; wavefront prefix sum
-// of the mask popcounts, one 64-bit atomic per wavefront reserves the output
-// slots (order of hits is unspecified).
+// Two arithmetic variants give identical integers:
+//   * f16 (used when |M| <= 23, which covers BLOSUM62): every partial sum is an
+//     integer of magnitude <= 44 * 23 < 1024, exactly representable in binary16,
+//     so packed f16 adds are exact; two steps cost two v_pk_add_f16 and one
+//     v_pk_maximum3_f16 per register;
+//   * int16 (any int8 matrix): v_pk_add_u16 / v_pk_max_i16, one add and one max
+//     per step and register.
+//
+// Hits: a 32-bit row mask per lane comes from the sign bits of (threshold -
+// best), rotated into place; hits are staged in LDS and written out once per
+// item with one global atomic (a wavefront whose reservation does not fit the
+// staging area writes directly).  Order of hits is unspecified.
 //
 // Schedules.  PLAIN: one grid per key with candidate pairs, in key order, one
 // item per workgroup (the paper's one-launch-per-seed GPU offload, Sec. 5.2.1,
@@ -29,6 +37,7 @@
 #include <stddef.h>
 #include <string.h>
 
+#include <type_traits>
 #include <vector>
 
 #include "plast_internal.h"
@@ -38,13 +47,18 @@ namespace plast {
 namespace {
 
 typedef short s16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 h16x2 __attribute__((ext_vector_type(2)));
 
 constexpr int kSepScore = -4;
+constexpr int kF16MaxEntry = 23;                  // 44 * 23 = 1012 < 1024
 constexpr int kProfT = kNLet * 8;                 // bytes per scan step
 constexpr int kProfRG = kSpan * kProfT;           // bytes per 4-row group
 constexpr int kProfBytes = kRowGroups * kProfRG;  // 59136
+constexpr int kPairs = 2 * kRowGroups;            // packed registers per lane (16)
 static_assert(kProfBytes + 4096 < 65536, "profile offsets must fit the LDS instruction offset field");
 static_assert(kPadCode * kScale < 256, "scaled codes must fit a byte");
+static_assert(kTileRows == 32 && kPairs == 16, "row mask layout assumes 32 rows");
+static_assert(kSpan * kF16MaxEntry < 1024, "f16 partial sums must stay exact");
 
 struct BankView {
   const int64_t* key_off;
@@ -56,17 +70,15 @@ struct BankView {
 
 struct UngappedArgs {
   BankView a, b;
+  uint32_t thr;                // packed pair: threshold - 1 (int16) or threshold - 0.5 (f16)
   int32_t s1;
-  int32_t pad_;
   plast_hit_t* hits;
   int64_t capacity;
   unsigned long long* n_hits;
   int16_t mat[kNLet * kNLet];  // [a letter][b letter], separator row/column = kSepScore
 };
 
-// Hits found in an item are staged in LDS as (row | score << 5, seq2, pos2)
-// and written out once per item with one global atomic; a wavefront whose
-// reservation does not fit the staging area writes its hits directly.
+// Hits found in an item are staged in LDS as (row | score << 5, seq2, pos2).
 constexpr int kHitSlots = 1024;
 
 struct __align__(16) Smem {
@@ -83,14 +95,55 @@ struct __align__(16) Smem {
   int32_t n_flush;                     // staged hits of the item being flushed
   int32_t item;
   unsigned long long hit_base;
-  int16_t mat[kNLet * kNLet];
+  uint16_t mat[kNLet * kNLet];         // profile values (int16 or binary16 bits)
 };
 static_assert(offsetof(Smem, rowlet) % 16 == 0 && offsetof(Smem, rowq) % 4 == 0, "LDS alignment");
 
-__device__ __forceinline__ s16x2 as_s16x2(uint32_t v) { return __builtin_bit_cast(s16x2, v); }
+template <bool F16>
+using vec2 = typename std::conditional<F16, h16x2, s16x2>::type;
 
+template <bool F16>
+__device__ __forceinline__ vec2<F16> as_vec(uint32_t v) {
+  return __builtin_bit_cast(vec2<F16>, v);
+}
+
+template <bool F16>
+__device__ __forceinline__ vec2<F16> vmax(vec2<F16> a, vec2<F16> b) {
+  if constexpr (F16)
+    return __builtin_elementwise_maximum(a, b);
+  else
+    return __builtin_elementwise_max(a, b);
+}
+
+template <bool F16>
+__device__ __forceinline__ vec2<F16> vmax3(vec2<F16> a, vec2<F16> b, vec2<F16> c) {
+  if constexpr (F16) {
+    // One v_pk_maximum3_f16 (register operands only).  Written out so that the
+    // compiler does not re-associate a chain of maxima into more instructions.
+    uint32_t r;
+    asm("v_pk_maximum3_f16 %0, %1, %2, %3"
+        : "=v"(r)
+        : "v"(__builtin_bit_cast(uint32_t, a)), "v"(__builtin_bit_cast(uint32_t, b)),
+          "v"(__builtin_bit_cast(uint32_t, c)));
+    return __builtin_bit_cast(vec2<F16>, r);
+  } else {
+    return __builtin_elementwise_max(a, __builtin_elementwise_max(b, c));
+  }
+}
+
+template <bool F16>
+__device__ __forceinline__ int to_int(vec2<F16> v, int half) {
+  return half ? (int)v.y : (int)v.x;
+}
+
+template <bool F16>
 __device__ __forceinline__ void smem_init(const UngappedArgs& A, Smem& S) {
-  for (int i = threadIdx.x; i < kNLet * kNLet; i += kThreads) S.mat[i] = A.mat[i];
+  for (int i = threadIdx.x; i < kNLet * kNLet; i += kThreads) {
+    if constexpr (F16)
+      S.mat[i] = __builtin_bit_cast(uint16_t, (_Float16)A.mat[i]);
+    else
+      S.mat[i] = (uint16_t)A.mat[i];
+  }
   if (threadIdx.x == 0) {
     S.n_hit = 0;
     S.n_fit = 0;
@@ -108,7 +161,7 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
 }
 
 // Rows of the tile (bank-a occurrences row0 .. row0+rows-1 of the key) and
-// their 44-step profile.
+// their 44-step profile.  Called by all threads (contains barriers).
 __device__ __forceinline__ void build_profile(const UngappedArgs& A, const WorkItem& it, int64_t a0, int rows,
                                               Smem& S) {
   const int tid = threadIdx.x;
@@ -143,10 +196,10 @@ __device__ __forceinline__ void build_profile(const UngappedArgs& A, const WorkI
     int t = rem / kNLet;
     int c = rem - t * kNLet;
     uint32_t l4 = *(const uint32_t*)&S.rowlet[t * kTileRows + 4 * rg];
-    uint32_t v0 = (uint16_t)S.mat[(l4 & 0xff) * kNLet + c];
-    uint32_t v1 = (uint16_t)S.mat[((l4 >> 8) & 0xff) * kNLet + c];
-    uint32_t v2 = (uint16_t)S.mat[((l4 >> 16) & 0xff) * kNLet + c];
-    uint32_t v3 = (uint16_t)S.mat[(l4 >> 24) * kNLet + c];
+    uint32_t v0 = S.mat[(l4 & 0xff) * kNLet + c];
+    uint32_t v1 = S.mat[((l4 >> 8) & 0xff) * kNLet + c];
+    uint32_t v2 = S.mat[((l4 >> 16) & 0xff) * kNLet + c];
+    uint32_t v3 = S.mat[(l4 >> 24) * kNLet + c];
     uint2 w;
     w.x = v0 | (v1 << 16);
     w.y = v2 | (v3 << 16);
@@ -157,45 +210,52 @@ __device__ __forceinline__ void build_profile(const UngappedArgs& A, const WorkI
 
 // The 44-step scan of one bank-b window against the 32 profile rows.
 // win: the window as (letter * 8) bytes, byte b = position q - 20 + b.
-// Returns best-right + best-left for each row as packed int16 pairs in m.
-__device__ __forceinline__ void scan_window(const Smem& S, const uint32_t (&win)[11], s16x2 (&m)[2 * kRowGroups]) {
-  s16x2 s[2 * kRowGroups];
+// m receives best-right + best-left of every row (register i: rows 2i, 2i+1).
+template <bool F16>
+__device__ __forceinline__ void scan_window(const Smem& S, const uint32_t (&win)[11], vec2<F16> (&m)[kPairs]) {
+  typedef vec2<F16> V;
+  V s[kPairs];
   uint2 cur[kRowGroups], nxt[kRowGroups];
-  auto addr = [&](int t) {
+  auto load = [&](int t, uint2(&dst)[kRowGroups]) {
     const int bidx = t < kRight ? kNbr + t : (kSpan - 1) - t;
     const uint32_t c8 = (win[bidx >> 2] >> (8 * (bidx & 3))) & 0xffu;
-    return S.prof + c8 + t * kProfT;
+    const uint8_t* p = S.prof + c8 + t * kProfT;
+#pragma unroll
+    for (int rg = 0; rg < kRowGroups; ++rg) dst[rg] = *(const uint2*)(p + rg * kProfRG);
   };
-  {
-    const uint8_t* p = addr(0);
+  auto val = [&](const uint2(&src)[kRowGroups], int i) {
+    return as_vec<F16>((i & 1) ? src[i >> 1].y : src[i >> 1].x);
+  };
+  const V zero = {0, 0};
+  load(0, cur);
+  load(1, nxt);
 #pragma unroll
-    for (int rg = 0; rg < kRowGroups; ++rg) cur[rg] = *(const uint2*)(p + rg * kProfRG);
-  }
+  for (int i = 0; i < kPairs; ++i) s[i] = val(cur, i);
 #pragma unroll
-  for (int t = 0; t < kSpan; ++t) {
-    if (t + 1 < kSpan) {
-      const uint8_t* p = addr(t + 1);
+  for (int rg = 0; rg < kRowGroups; ++rg) cur[rg] = nxt[rg];
+  // Steps 1 .. 43; the scores of step t are in cur when step t is applied.
 #pragma unroll
-      for (int rg = 0; rg < kRowGroups; ++rg) nxt[rg] = *(const uint2*)(p + rg * kProfRG);
-    }
+  for (int t = 1; t < kSpan; ++t) {
+    if (t + 1 < kSpan) load(t + 1, nxt);
     if (t == kRight) {
 #pragma unroll
-      for (int i = 0; i < 2 * kRowGroups; ++i) s[i] = m[i];
+      for (int i = 0; i < kPairs; ++i) s[i] = m[i];  // best right prefix, then left
     }
 #pragma unroll
-    for (int rg = 0; rg < kRowGroups; ++rg) {
-      const s16x2 x = as_s16x2(cur[rg].x), y = as_s16x2(cur[rg].y);
-      if (t == 0) {
-        const s16x2 z = {0, 0};
-        s[2 * rg] = x;
-        s[2 * rg + 1] = y;
-        m[2 * rg] = __builtin_elementwise_max(x, z);
-        m[2 * rg + 1] = __builtin_elementwise_max(y, z);
+    for (int i = 0; i < kPairs; ++i) {
+      const V prev = s[i];
+      s[i] = prev + val(cur, i);
+      if constexpr (F16) {
+        // Running best after every odd step: right prefixes (0,1) with the
+        // empty prefix, (2,3), ..., (22,23); after the reset the left prefixes
+        // (24,25), ..., (42,43).  Every prefix sum enters one 3-way maximum.
+        if (t == 1)
+          m[i] = vmax3<F16>(zero, prev, s[i]);
+        else if (t & 1)
+          m[i] = vmax3<F16>(m[i], prev, s[i]);
       } else {
-        s[2 * rg] += x;
-        s[2 * rg + 1] += y;
-        m[2 * rg] = __builtin_elementwise_max(m[2 * rg], s[2 * rg]);
-        m[2 * rg + 1] = __builtin_elementwise_max(m[2 * rg + 1], s[2 * rg + 1]);
+        if (t == 1) m[i] = vmax<F16>(prev, zero);
+        m[i] = vmax<F16>(m[i], s[i]);
       }
     }
     if (t + 1 < kSpan) {
@@ -205,24 +265,51 @@ __device__ __forceinline__ void scan_window(const Smem& S, const uint32_t (&win)
   }
 }
 
-__device__ __forceinline__ int row_score(const s16x2 (&m)[2 * kRowGroups], int r) {
-  return (r & 1) ? (int)m[r >> 1].y : (int)m[r >> 1].x;
+// Bit layout of the row mask: bit i (i < 16) is row 2i (low half of register
+// i), bit 16 + i is row 2i + 1 (high half).
+__device__ __forceinline__ uint32_t valid_rows_mask(int rows) {
+  uint32_t m = 0;
+#pragma unroll
+  for (int r = 0; r < kTileRows; ++r)
+    if (r < rows) m |= 1u << ((r >> 1) + ((r & 1) << 4));
+  return m;
 }
 
-__device__ __forceinline__ void emit_hits(const UngappedArgs& A, Smem& S, const s16x2 (&m)[2 * kRowGroups],
-                                          bool active, int rows, int s2, int p2) {
-  const int lane = __lane_id();
-  s16x2 mx = m[0];
-#pragma unroll
-  for (int i = 1; i < 2 * kRowGroups; ++i) mx = __builtin_elementwise_max(mx, m[i]);
-  const bool cand = active && max((int)mx.x, (int)mx.y) >= A.s1;
-  if (!__ballot(cand)) return;
+template <bool F16>
+__device__ __forceinline__ uint32_t hit_mask(uint32_t thr, const vec2<F16> (&m)[kPairs]) {
+  typedef vec2<F16> V;
+  const V th = as_vec<F16>(thr);
   uint32_t mask = 0;
-  if (cand) {
 #pragma unroll
-    for (int r = 0; r < kTileRows; ++r)
-      if (r < rows && row_score(m, r) >= A.s1) mask |= 1u << r;
+  for (int i = 0; i < kPairs; ++i) {
+    const V diff = th - m[i];                                       // negative where best >= s1
+    const uint32_t d = __builtin_bit_cast(uint32_t, diff);
+    const uint32_t rot = __builtin_amdgcn_alignbit(d, d, 15 - i);  // bit 15 -> i, bit 31 -> 16 + i
+    mask |= rot & ((1u << i) | (1u << (16 + i)));
   }
+  return mask;
+}
+
+// Hit rows of this lane in register order (rows 2i and 2i+1 from register i);
+// every register index is a compile-time constant, and a block whose bits are
+// clear in every lane of the wavefront is skipped as a whole.
+template <bool F16, typename Put>
+__device__ __forceinline__ void for_each_hit(const vec2<F16> (&m)[kPairs], uint32_t mask, Put put) {
+#pragma unroll
+  for (int i = 0; i < kPairs; ++i) {
+    const uint32_t bits = mask & ((1u << i) | (1u << (16 + i)));
+    if (bits) {
+      if (bits & (1u << i)) put(2 * i, to_int<F16>(m[i], 0));
+      if (bits >> 16) put(2 * i + 1, to_int<F16>(m[i], 1));
+    }
+  }
+}
+
+template <bool F16>
+__device__ __forceinline__ void emit_hits(const UngappedArgs& A, Smem& S, const vec2<F16> (&m)[kPairs],
+                                          uint32_t mask, int s2, int p2) {
+  const int lane = __lane_id();
+  if (!__ballot(mask != 0)) return;
   const int cnt = __popc(mask);
   const int incl = wave_incl_scan(cnt);
   const int total = __shfl(incl, 63);
@@ -234,39 +321,33 @@ __device__ __forceinline__ void emit_hits(const UngappedArgs& A, Smem& S, const 
   base = __shfl(base, 63);
   if (base + total <= kHitSlots) {  // staged in LDS
     int at = base + incl - cnt;
-#pragma unroll
-    for (int r = 0; r < kTileRows; ++r) {
-      if (mask & (1u << r)) {
-        S.hit_rs[at] = (uint32_t)r | ((uint32_t)row_score(m, r) << 5);
-        S.hit_seq[at] = s2;
-        S.hit_pos[at] = p2;
-        ++at;
-      }
-    }
+    for_each_hit<F16>(m, mask, [&](int r, int score) {
+      S.hit_rs[at] = (uint32_t)r | ((uint32_t)score << 5);
+      S.hit_seq[at] = s2;
+      S.hit_pos[at] = p2;
+      ++at;
+    });
   } else {  // staging area full: write directly
     unsigned long long g = 0;
     if (lane == 63) g = atomicAdd(A.n_hits, (unsigned long long)total);
     g = __shfl(g, 63) + (unsigned long long)(incl - cnt);
-#pragma unroll
-    for (int r = 0; r < kTileRows; ++r) {
-      if (mask & (1u << r)) {
-        if (g < (unsigned long long)A.capacity) {
-          plast_hit_t h;
-          h.seq1 = S.rowseq[r];
-          h.pos1 = S.rowpos[r];
-          h.seq2 = s2;
-          h.pos2 = p2;
-          h.score = row_score(m, r);
-          A.hits[g] = h;
-        }
-        ++g;
+    for_each_hit<F16>(m, mask, [&](int r, int score) {
+      if (g < (unsigned long long)A.capacity) {
+        plast_hit_t h;
+        h.seq1 = S.rowseq[r];
+        h.pos1 = S.rowpos[r];
+        h.seq2 = s2;
+        h.pos2 = p2;
+        h.score = score;
+        A.hits[g] = h;
       }
-    }
+      ++g;
+    });
   }
 }
 
-// Every thread calls this (it contains barriers); it ends with a barrier so the
-// next item may overwrite the staging area and the row data.
+// Called by all threads (contains barriers); ends with a barrier so the next
+// item may overwrite the staging area and the row data.
 __device__ __forceinline__ void flush_hits(const UngappedArgs& A, Smem& S) {
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -302,6 +383,7 @@ __device__ __forceinline__ void load_window_raw(const UngappedArgs& A, int q2, u
 
 // All threads of the workgroup call run_item with the same item (it contains
 // barriers); every branch around a barrier depends only on wave-uniform values.
+template <bool F16>
 __device__ void run_item(const UngappedArgs& A, const WorkItem it, Smem& S) {
   const int tid = threadIdx.x;
   const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -309,6 +391,7 @@ __device__ void run_item(const UngappedArgs& A, const WorkItem it, Smem& S) {
   const int n1 = (int)(A.a.key_off[it.key + 1] - a0);
   const int rows = min(kTileRows, n1 - it.row0);
   const int64_t b0 = A.b.key_off[it.key];
+  const uint32_t valid = valid_rows_mask(rows);
   build_profile(A, it, a0, rows, S);
 
   // Lane columns: col0 + tid + kThreads * k.  Column data is software-pipelined:
@@ -353,31 +436,34 @@ __device__ void run_item(const UngappedArgs& A, const WorkItem it, Smem& S) {
       s_nxt = A.b.occ_seq[o];
     }
     const int st2 = (int)A.b.seq_start[s2];
-    s16x2 m[2 * kRowGroups];
-    scan_window(S, win, m);
-    emit_hits(A, S, m, active, rows, s2, q2 - st2);
+    vec2<F16> m[kPairs];
+    scan_window<F16>(S, win, m);
+    const uint32_t mask = active ? (hit_mask<F16>(A.thr, m) & valid) : 0u;
+    emit_hits<F16>(A, S, m, mask, s2, q2 - st2);
   }
-  flush_hits(A, S);  // ends with a barrier: LDS may be rebuilt by the next item
+  flush_hits(A, S);
 }
 
+template <bool F16>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
 void k_ungapped_plain(UngappedArgs A, int32_t key, int32_t n_row_tiles, int32_t n2) {
   __shared__ Smem S;
-  smem_init(A, S);
+  smem_init<F16>(A, S);
   __syncthreads();
   WorkItem it;
   it.key = key;
   it.row0 = (int32_t)(blockIdx.x % n_row_tiles) * kTileRows;
   it.col0 = (int32_t)(blockIdx.x / n_row_tiles) * kTileCols;
   it.ncols = min(kTileCols, n2 - it.col0);
-  run_item(A, it, S);
+  run_item<F16>(A, it, S);
 }
 
+template <bool F16>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
 void k_ungapped_persistent(UngappedArgs A, const WorkItem* __restrict__ items, const int32_t* __restrict__ n_items_p,
                            const int32_t* __restrict__ overflow, int32_t* __restrict__ ctr) {
   __shared__ Smem S;
-  smem_init(A, S);
+  smem_init<F16>(A, S);
   const int n_items = __builtin_amdgcn_readfirstlane(*overflow ? 0 : *n_items_p);
   // The item index is read back as a scalar so that the loop exit is uniform:
   // with a per-lane exit the compiler may let lanes other than thread 0 reach
@@ -387,7 +473,7 @@ void k_ungapped_persistent(UngappedArgs A, const WorkItem* __restrict__ items, c
     __syncthreads();
     const int i = __builtin_amdgcn_readfirstlane(S.item);
     if (i >= n_items) break;
-    run_item(A, items[i], S);
+    run_item<F16>(A, items[i], S);
   }
 }
 
@@ -486,12 +572,12 @@ UngappedPlan host_plan(const std::vector<int64_t>& ha, const std::vector<int64_t
   return P;
 }
 
-void fill_args(UngappedArgs& A, const plast_index_t* a, const plast_index_t* b, const plast_ungapped_params_t* p,
+// Returns true when the f16 variant is exact for this matrix.
+bool fill_args(UngappedArgs& A, const plast_index_t* a, const plast_index_t* b, const plast_ungapped_params_t* p,
                plast_hit_t* d_hits, int64_t capacity, unsigned long long* n_hits) {
   A.a = BankView{a->key_off, a->occ, a->occ_seq, a->scan_codes, a->seq_start};
   A.b = BankView{b->key_off, b->occ, b->occ_seq, b->scan_codes, b->seq_start};
   A.s1 = p->s1;
-  A.pad_ = 0;
   A.hits = d_hits;
   A.capacity = capacity;
   A.n_hits = n_hits;
@@ -500,17 +586,35 @@ void fill_args(UngappedArgs& A, const plast_index_t* a, const plast_index_t* b, 
     memcpy(m, p->matrix, sizeof(m));
   else
     blosum62_code_order(m);
+  int maxabs = -kSepScore;
   for (int x = 0; x < kNLet; ++x)
-    for (int y = 0; y < kNLet; ++y) A.mat[x * kNLet + y] = (x < 20 && y < 20) ? m[x * 20 + y] : kSepScore;
+    for (int y = 0; y < kNLet; ++y) {
+      A.mat[x * kNLet + y] = (x < 20 && y < 20) ? m[x * 20 + y] : kSepScore;
+      maxabs = max(maxabs, abs((int)A.mat[x * kNLet + y]));
+    }
+  const bool f16 = maxabs <= kF16MaxEntry;
+  // Threshold register: hit iff thr - best < 0.  Scores lie in [0, 44 * maxabs].
+  if (f16) {
+    // best is an integer in [0, 1012]: thr = s1 - 1/2 clamped to [-1/2, 1012.5], exact in binary16
+    const float t = (float)min(max(p->s1, 0), kSpan * kF16MaxEntry + 1) - 0.5f;
+    const uint16_t h = __builtin_bit_cast(uint16_t, (_Float16)t);
+    A.thr = (uint32_t)h | ((uint32_t)h << 16);
+  } else {
+    const int t = min(max(p->s1, -20000), 20000) - 1;
+    const uint16_t h = (uint16_t)(int16_t)t;
+    A.thr = (uint32_t)h | ((uint32_t)h << 16);
+  }
+  return f16;
 }
 
+template <bool F16>
 int persistent_grid() {
   static int cached = 0;
   if (!cached) {
     int dev = 0, cus = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_ungapped_persistent, kThreads, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_ungapped_persistent<F16>, kThreads, 0) != hipSuccess)
       return 0;
     cached = cus * (per > 0 ? per : 1);
   }
@@ -537,7 +641,7 @@ int ungapped_extend_impl(const plast_index_t* a, const plast_index_t* b, const p
   if (ws_bytes < 256) return set_error(PLAST_E_WORKSPACE, "workspace smaller than 256 bytes");
   UngappedWs W = carve(d_ws, ws_bytes);
   UngappedArgs A;
-  fill_args(A, a, b, p, d_hits, capacity, W.n_hits);
+  const bool f16 = fill_args(A, a, b, p, d_hits, capacity, W.n_hits);
   unsigned long long h_cnt[2] = {0, 0};
 
   if (mode == PLAST_PLAIN) {
@@ -552,8 +656,12 @@ int ungapped_extend_impl(const plast_index_t* a, const plast_index_t* b, const p
       if (n1 <= 0 || n2 <= 0) continue;
       n_ext += n1 * n2;
       int64_t nrt = (n1 + kTileRows - 1) / kTileRows, nct = (n2 + kTileCols - 1) / kTileCols;
-      hipLaunchKernelGGL(k_ungapped_plain, dim3((unsigned)(nrt * nct)), dim3(kThreads), 0, stream, A, k,
-                         (int32_t)nrt, (int32_t)n2);
+      if (f16)
+        hipLaunchKernelGGL(k_ungapped_plain<true>, dim3((unsigned)(nrt * nct)), dim3(kThreads), 0, stream, A, k,
+                           (int32_t)nrt, (int32_t)n2);
+      else
+        hipLaunchKernelGGL(k_ungapped_plain<false>, dim3((unsigned)(nrt * nct)), dim3(kThreads), 0, stream, A, k,
+                           (int32_t)nrt, (int32_t)n2);
       ++launches;
     }
     timing_mark(kStageUngapped, true, stream);
@@ -565,7 +673,7 @@ int ungapped_extend_impl(const plast_index_t* a, const plast_index_t* b, const p
   } else {
     if (ws_bytes < ws_fixed_bytes())
       return set_error(PLAST_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, ws_fixed_bytes());
-    int grid = persistent_grid();
+    int grid = f16 ? persistent_grid<true>() : persistent_grid<false>();
     if (grid <= 0) return set_error(PLAST_E_HIP, "cannot query device occupancy");
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, stream, (uint32_t*)d_ws, (int64_t)8, 0u);
     timing_mark(kStagePlan, false, stream);
@@ -576,8 +684,12 @@ int ungapped_extend_impl(const plast_index_t* a, const plast_index_t* b, const p
                        (const int32_t*)W.cnt, (const int32_t*)W.total, W.max_items, W.items, W.overflow);
     timing_mark(kStagePlan, true, stream);
     timing_mark(kStageUngapped, false, stream);
-    hipLaunchKernelGGL(k_ungapped_persistent, dim3(grid), dim3(kThreads), 0, stream, A,
-                       (const WorkItem*)W.items, (const int32_t*)W.total, (const int32_t*)W.overflow, W.ctr);
+    if (f16)
+      hipLaunchKernelGGL(k_ungapped_persistent<true>, dim3(grid), dim3(kThreads), 0, stream, A,
+                         (const WorkItem*)W.items, (const int32_t*)W.total, (const int32_t*)W.overflow, W.ctr);
+    else
+      hipLaunchKernelGGL(k_ungapped_persistent<false>, dim3(grid), dim3(kThreads), 0, stream, A,
+                         (const WorkItem*)W.items, (const int32_t*)W.total, (const int32_t*)W.overflow, W.ctr);
     timing_mark(kStageUngapped, true, stream);
     timing_launches(1);
     PLAST_HIP(hipGetLastError());

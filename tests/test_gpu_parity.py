@@ -173,6 +173,39 @@ def test_ungapped_custom_matrix(B, symmetric):
         assert np.array_equal(B.canonical_hits(hits), ref)
 
 
+def test_ungapped_wide_matrix_uses_int16_path(B):
+    """Entries beyond +-23 take the int16 scan (the f16 scan is exact only for
+    small entries); scores reach the thousands."""
+    _say("ungapped wide-range matrix")
+    rng = np.random.default_rng(12)
+    M = rng.integers(-120, 128, size=(20, 20))
+    np.fill_diagonal(M, 127)
+    w = synth.make_workload(0, scale=0.2)
+    ia, ib = _index(B, w.bank1), _index(B, w.bank2)
+    for mode in ("plain", "batched"):
+        hits, _ = B.ungapped_extend(ia, ib, 600, mode=mode, matrix=M)
+        ref, _ = C.ungapped_hits(w.bank1, w.bank2, 600, matrix=M)
+        assert len(ref) > 100 and ref[:, 4].max() > 1024
+        assert np.array_equal(B.canonical_hits(hits), ref)
+
+
+def test_ungapped_f16_boundary_matrix(B):
+    """Largest entries the f16 scan accepts (|M| = 23), thresholds at and beyond
+    the score range."""
+    _say("ungapped f16 boundary")
+    rng = np.random.default_rng(13)
+    M = rng.integers(-23, 24, size=(20, 20))
+    np.fill_diagonal(M, 23)
+    w = synth.make_workload(0, scale=0.2)
+    ia, ib = _index(B, w.bank1), _index(B, w.bank2)
+    for s1 in (150, 0, -5, 2000):
+        hits, n_ext = B.ungapped_extend(ia, ib, s1, mode="batched", matrix=M)
+        ref, _ = C.ungapped_hits(w.bank1, w.bank2, s1, matrix=M)
+        assert np.array_equal(B.canonical_hits(hits), ref)
+        if s1 <= 0:
+            assert len(ref) == n_ext
+
+
 def test_ungapped_empty_and_disjoint_banks(B):
     _say("ungapped empty banks")
     e = synth.Bank.from_seqs([])
