@@ -105,7 +105,7 @@ int plast_index_bytes(int64_t n_padded, int32_t n_seqs, size_t* index_bytes, siz
  * the last sequence, a final run.  d_seq_start[i] is the offset of the first
  * residue of sequence i, d_seq_start[n_seqs] == n_padded; sequence i has length
  * d_seq_start[i+1] - d_seq_start[i] - PLAST_PAD_LEN (0 allowed).  n_padded must
- * be < 2^31 - 64.
+ * be < 2^31 - 256.
  * Errors: PLAST_E_ARG (null pointer, bad sizes), PLAST_E_WORKSPACE (buffers
  * smaller than plast_index_bytes), PLAST_E_LAYOUT (seq_start inconsistent),
  * PLAST_E_ALPHABET (residue code > 19 or separator code != 20),

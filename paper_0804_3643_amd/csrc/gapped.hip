@@ -15,6 +15,19 @@
 // the end of y never feeds a cell inside it, and is reached only from cells
 // inside through wall letters or gaps, which cannot raise the score; so it never
 // exceeds the best existing cell and no per-cell length test is needed.
+//
+// Fast path (band 16, window <= 64, and every finite DP value an integer of
+// magnitude < 2048, which holds for BLOSUM62 with open 11 / extend 1): one lane
+// per hit computes both extensions at once, the right one in the low and the
+// left one in the high half of packed binary16 registers.  Sums of such
+// integers are exact in binary16, -inf marks cells outside the band or before
+// the anchor, and v_pk_maximum3_f16 takes H = max(diagonal, E, F) in one
+// instruction.  Letters are fetched from global memory one block of rows
+// ahead as aligned dwords (four letters per load).  Substitution scores come
+// from a binary16 table in LDS (optionally replicated per LDS bank).
+#include <stdio.h>
+#include <stdlib.h>
+
 #include "plast_internal.h"
 
 namespace plast {
@@ -37,7 +50,8 @@ struct GappedArgs {
   const int64_t* b_seq_start;
   int32_t a_nseq, b_nseq;
   int32_t window, band, gap_open, gap_extend, s2, pad_;
-  int16_t mat[kNLet * 22];  // [x letter][y letter or wall]
+  int16_t mat[kNLet * 22];     // [x letter][y letter or wall]
+  uint16_t tbl16[kNLet * kNLet];  // binary16 [x letter][y letter], -inf where either is the separator (20)
 };
 
 struct GSmem {
@@ -145,6 +159,223 @@ __global__ __launch_bounds__(kGThreads) void k_gapped(GappedArgs G, const plast_
   }
 }
 
+
+// ---------------------------------------------------------------- packed f16 path
+typedef _Float16 gh2 __attribute__((ext_vector_type(2)));
+// Tunables of the fast path (compile-time).  Defaults are the fastest of a sweep
+// on MI355X, configuration 1 (26.8M hits): a dense table, 256 threads, one hit
+// block per workgroup, up to 256 VGPRs (2 wavefronts per SIMD), 4 rows per block
+// (19.3 ms; table copies 16 or 32 and 3 wavefronts per SIMD were not faster).
+#ifndef PLAST_GAP_COPIES
+#define PLAST_GAP_COPIES 0
+#endif
+#ifndef PLAST_GAP_THREADS
+#define PLAST_GAP_THREADS 256
+#endif
+#ifndef PLAST_GAP_PERSIST
+#define PLAST_GAP_PERSIST 0
+#endif
+#ifndef PLAST_GAP_BLOCK
+#define PLAST_GAP_BLOCK 4
+#endif
+constexpr int kFThreads = PLAST_GAP_THREADS;
+constexpr int kFBlock = PLAST_GAP_BLOCK;        // rows per unrolled block (1..4)
+static_assert(kFBlock >= 1 && kFBlock <= 4, "rows per block");
+constexpr int kFY = kGCells + kFBlock - 1;      // y letters held for a block (36)
+// 0: one dense binary16 table (2-byte entries); n > 0: n copies of 4-byte entries,
+// copy c serving lanes l with l mod n = c.
+constexpr int kCopies = PLAST_GAP_COPIES;
+static_assert(kCopies == 0 || kCopies == 1 || kCopies == 16 || kCopies == 32, "table copies");
+constexpr int kTblDwords = kCopies == 0 ? (kNLet * kNLet + 1) / 2 : kNLet * kNLet * kCopies;
+constexpr uint32_t kWall8 = kPadCode * kScale;  // the separator letter serves as wall: it scores -inf
+// Table entry (x, y) of copy c is the low half of dword (x * 21 + y) * kCopies + c:
+// byte offset x * kRowBytes + y * kEntry + c * 4.
+constexpr uint32_t kEntry = kCopies == 0 ? 2 : kCopies * 4;
+constexpr uint32_t kRowBytes = kNLet * kEntry;
+static_assert(kNLet * kRowBytes < 65536, "table offsets must fit 16 bits");
+
+__device__ __forceinline__ gh2 gmax3(gh2 a, gh2 b, gh2 c) {
+  uint32_t r;
+  asm("v_pk_maximum3_f16 %0, %1, %2, %3"
+      : "=v"(r)
+      : "v"(__builtin_bit_cast(uint32_t, a)), "v"(__builtin_bit_cast(uint32_t, b)),
+        "v"(__builtin_bit_cast(uint32_t, c)));
+  return __builtin_bit_cast(gh2, r);
+}
+__device__ __forceinline__ gh2 gmax(gh2 a, gh2 b) { return __builtin_elementwise_maximum(a, b); }
+
+// Four consecutive scan-code bytes of `buf` from byte offset `off` (which may be
+// unaligned or negative): one aligned dword pair and a funnel shift.  The pair is
+// clamped at the start of the buffer and the buffer carries kScanSlack bytes of
+// tail slack, so no read leaves it; bytes outside the sequence are masked by
+// the caller.
+__device__ __forceinline__ uint32_t load4(const uint8_t* __restrict__ buf, int64_t off) {
+  const uint32_t* p = (const uint32_t*)buf + (off >= 0 ? (off >> 2) : 0);
+  return __builtin_amdgcn_alignbyte(p[1], p[0], (uint32_t)(off & 3));
+}
+
+__device__ __forceinline__ uint32_t byte_of(uint32_t v, int k) { return (v >> (8 * k)) & 0xffu; }
+
+// Letters of one hit: x rows i = 1.. and y indices k = 0.. for the rightward
+// (R) and leftward (L) extension, in scan-code units; walls outside.
+struct GLetters {
+  const uint8_t* A;  // bank a scan codes
+  const uint8_t* B;  // bank b scan codes
+  int64_t qa, qb;    // anchor offsets
+  int lxR, lxL, lyR, lyL;
+  // rows i0 .. i0+n-1 (n <= 4) of both extensions: table row offsets of this lane's copy
+  template <int n>
+  __device__ __forceinline__ void xrows(int i0, uint32_t copy4, uint32_t (&xbR)[n], uint32_t (&xbL)[n]) const {
+    const uint32_t r4 = load4(A, qa + i0 - 1);      // byte r: x_R row i0 + r
+    const uint32_t l4 = load4(A, qa - i0 - 3);      // byte 3 - r: x_L row i0 + r
+#pragma unroll
+    for (int r = 0; r < n; ++r) {
+      const uint32_t sr = i0 + r <= lxR ? byte_of(r4, r) : kWall8;
+      const uint32_t sl = i0 + r <= lxL ? byte_of(l4, 3 - r) : kWall8;
+      xbR[r] = (sr / kScale) * kRowBytes + copy4;
+      xbL[r] = (sl / kScale) * kRowBytes + copy4;
+    }
+  }
+  // y indices k0 .. k0+3 of both extensions: packed table column offsets
+  __device__ __forceinline__ void ycols(int k0, uint32_t (&y)[4]) const {
+    const uint32_t r4 = load4(B, qb + k0);          // byte t: y_R index k0 + t
+    const uint32_t l4 = load4(B, qb - 4 - k0);      // byte 3 - t: y_L index k0 + t
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int k = k0 + t;
+      const uint32_t sr = (k >= 0 && k < lyR) ? byte_of(r4, t) : kWall8;
+      const uint32_t sl = (k >= 0 && k < lyL) ? byte_of(l4, 3 - t) : kWall8;
+      y[t] = (sr / kScale) * kEntry | (((sl / kScale) * kEntry) << 16);
+    }
+  }
+};
+
+__device__ __forceinline__ void gapped_hit_f16(const GappedArgs& G, const uint32_t* tbl, uint32_t copy4,
+                                               const plast_hit_t* __restrict__ hits, int64_t h, int64_t n_hits,
+                                               int32_t* __restrict__ gscore, uint8_t* __restrict__ pass) {
+  const bool live = h < n_hits;
+  plast_hit_t hit = live ? hits[h] : plast_hit_t{0, 0, 0, 0, 0};
+  bool sane = live && hit.seq1 >= 0 && hit.seq1 < G.a_nseq && hit.seq2 >= 0 && hit.seq2 < G.b_nseq;
+  int64_t sa = 0, sb = 0;
+  int la = 0, lb = 0;
+  if (sane) {
+    sa = G.a_seq_start[hit.seq1];
+    sb = G.b_seq_start[hit.seq2];
+    la = (int)(G.a_seq_start[hit.seq1 + 1] - sa - kPadLen);
+    lb = (int)(G.b_seq_start[hit.seq2 + 1] - sb - kPadLen);
+    sane = hit.pos1 >= 0 && hit.pos1 < la && hit.pos2 >= 0 && hit.pos2 < lb;
+  }
+  GLetters L;
+  L.A = G.a_scan;
+  L.B = G.b_scan;
+  L.qa = sane ? sa + hit.pos1 : kPadLen;  // a lane without a valid record reads separators
+  L.qb = sane ? sb + hit.pos2 : kPadLen;
+  L.lxR = sane ? min(G.window, la - hit.pos1) : 0;
+  L.lyR = sane ? min(G.window, lb - hit.pos2) : 0;
+  L.lxL = sane ? min(G.window, hit.pos1) : 0;
+  L.lyL = sane ? min(G.window, hit.pos2) : 0;
+  const int rows = max(L.lxR, L.lxL);
+
+  const _Float16 ninf = -__builtin_inff16();
+  const gh2 NEG = {ninf, ninf};
+  const _Float16 oe = (_Float16)(G.gap_open + G.gap_extend), ex = (_Float16)G.gap_extend;
+  const gh2 OE = {oe, oe}, EX = {ex, ex};
+  gh2 H[kGCells], F[kGCells];
+  uint32_t Y[kFY];
+  // row 0: H(0, j) = 0 at j = 0, -(open + j * extend) for 0 < j <= 16; F holds F(1, j)
+#pragma unroll
+  for (int d = 0; d < kGCells; ++d) {
+    const int j = d - kGMaxBand;
+    const _Float16 v = j < 0 ? ninf : (j == 0 ? (_Float16)0 : (_Float16)(-(G.gap_open + j * G.gap_extend)));
+    H[d] = gh2{v, v};
+    F[d] = H[d] - OE;
+  }
+  // letters under the band of the first block (rows 1..4): Y[k] = y index k - 16
+#pragma unroll
+  for (int g = 0; g < (kFY + 3) / 4; ++g) {
+    uint32_t y4[4];
+    L.ycols(4 * g - kGMaxBand, y4);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      if (4 * g + t < kFY) Y[4 * g + t] = y4[t];
+  }
+  uint32_t xbR[kFBlock], xbL[kFBlock];
+  L.xrows<kFBlock>(1, copy4, xbR, xbL);
+  gh2 best = {(_Float16)0, (_Float16)0};
+  const char* tb = (const char*)tbl;
+  for (int i0 = 1; __builtin_amdgcn_readfirstlane(__ballot(i0 <= rows) != 0); i0 += kFBlock) {
+    // raw letters of the next block (x rows, and the y indices entering the band),
+    // decoded after this block's rows
+    const uint32_t nx4R = load4(L.A, L.qa + i0 + kFBlock - 1), nx4L = load4(L.A, L.qa - i0 - kFBlock - 3);
+    const int k0 = i0 + kFY - kGMaxBand - 1;
+    const uint32_t ny4R = load4(L.B, L.qb + k0), ny4L = load4(L.B, L.qb - 4 - k0);
+#pragma unroll
+    for (int r = 0; r < kFBlock; ++r) {
+      gh2 e = NEG, hprev = NEG;
+#pragma unroll
+      for (int d = 0; d < kGCells; ++d) {
+        const uint32_t y = Y[d + r];
+        const _Float16 scR = *(const _Float16*)(tb + xbR[r] + (y & 0xffffu));
+        const _Float16 scL = *(const _Float16*)(tb + xbL[r] + (y >> 16));
+        const gh2 diag = H[d] + gh2{scR, scL};
+        const gh2 f = d + 1 < kGCells ? F[d + 1] : NEG;
+        const gh2 hh = gmax3(diag, e, f);
+        if (d & 1) best = gmax3(best, hprev, hh);
+        else if (d == kGCells - 1) best = gmax(best, hh);
+        hprev = hh;
+        const gh2 ho = hh - OE;
+        e = gmax(e - EX, ho);
+        F[d] = gmax(f - EX, ho);
+        H[d] = hh;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k + kFBlock < kFY; ++k) Y[k] = Y[k + kFBlock];
+    const int i1 = i0 + kFBlock;
+#pragma unroll
+    for (int t = 0; t < kFBlock; ++t) {
+      const int k = k0 + t;
+      const uint32_t sr = (k >= 0 && k < L.lyR) ? byte_of(ny4R, t) : kWall8;
+      const uint32_t sl = (k >= 0 && k < L.lyL) ? byte_of(ny4L, 3 - t) : kWall8;
+      Y[kFY - kFBlock + t] = (sr / kScale) * kEntry | (((sl / kScale) * kEntry) << 16);
+      const uint32_t xr = i1 + t <= L.lxR ? byte_of(nx4R, t) : kWall8;
+      const uint32_t xl = i1 + t <= L.lxL ? byte_of(nx4L, 3 - t) : kWall8;
+      xbR[t] = (xr / kScale) * kRowBytes + copy4;
+      xbL[t] = (xl / kScale) * kRowBytes + copy4;
+    }
+  }
+  if (live) {
+    const int total = sane ? (int)best.x + (int)best.y : -1;
+    gscore[h] = total;
+    pass[h] = (sane && total >= G.s2) ? 1 : 0;
+  }
+}
+
+#ifndef PLAST_GAP_WAVES
+#define PLAST_GAP_WAVES 2
+#endif
+__global__ __launch_bounds__(kFThreads) __attribute__((amdgpu_waves_per_eu(PLAST_GAP_WAVES)))
+void k_gapped_f16(GappedArgs G, const plast_hit_t* __restrict__ hits,
+                                                          int64_t n_hits, int32_t* __restrict__ gscore,
+                                                          uint8_t* __restrict__ pass) {
+  __shared__ uint32_t tbl[kTblDwords];  // filled once per workgroup
+  if constexpr (kCopies == 0) {
+    for (int i = threadIdx.x; i < kTblDwords; i += kFThreads) {
+      const uint32_t lo = G.tbl16[2 * i], hi = 2 * i + 1 < kNLet * kNLet ? G.tbl16[2 * i + 1] : 0;
+      tbl[i] = lo | (hi << 16);
+    }
+  } else {
+    for (int i = threadIdx.x; i < kTblDwords; i += kFThreads) tbl[i] = G.tbl16[i / kCopies];
+  }
+  __syncthreads();
+  const uint32_t copy4 = kCopies > 1 ? (threadIdx.x & (kCopies - 1)) * 4 : 0;
+  // grid-stride over blocks of kFThreads hits; no barrier inside the loop
+  for (int64_t h = (int64_t)blockIdx.x * kFThreads + threadIdx.x; h - threadIdx.x < n_hits;
+       h += (int64_t)gridDim.x * kFThreads)
+    gapped_hit_f16(G, tbl, copy4, hits, h, n_hits, gscore, pass);
+}
+
+
 }  // namespace
 
 int gapped_filter_impl(const plast_index_t* a, const plast_index_t* b, const plast_hit_t* d_hits, int64_t n_hits,
@@ -168,11 +399,42 @@ int gapped_filter_impl(const plast_index_t* a, const plast_index_t* b, const pla
   } else {
     blosum62_code_order(m);
   }
+  int maxabs = 0;
   for (int x = 0; x < kNLet; ++x)
-    for (int y = 0; y < 22; ++y)
+    for (int y = 0; y < 22; ++y) {
       G.mat[x * 22 + y] = (x < 20 && y < 20) ? m[x * 20 + y] : kWallScore;
-  unsigned blocks = (unsigned)((n_hits + kGThreads - 1) / kGThreads);
+      if (x < 20 && y < 20) maxabs = max(maxabs, abs((int)m[x * 20 + y]));
+    }
+  const uint16_t ninf16 = 0xFC00;  // binary16 -inf
+  for (int x = 0; x < kNLet; ++x)
+    for (int y = 0; y < kNLet; ++y)
+      G.tbl16[x * kNLet + y] = (x < 20 && y < 20) ? __builtin_bit_cast(uint16_t, (_Float16)m[x * 20 + y]) : ninf16;
+  // Every finite DP value lies within [-(64 |M| + 3 (open + extend) + 130 extend), 64 |M|]:
+  // integers of that range are exact in binary16 when the bound stays below 2048.
+  const bool fast = g->band == kGMaxBand && g->window <= kGMaxWin &&
+                    64 * maxabs + 3 * (g->gap_open + g->gap_extend) + 130 * g->gap_extend <= 2000;
   timing_mark(kStageGapped, false, stream);
+  if (fast) {
+    static int resident = 0;  // workgroups that fit the device at once
+    if (!resident) {
+      int dev = 0, cus = 0, per = 0;
+      PLAST_HIP(hipGetDevice(&dev));
+      PLAST_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+      PLAST_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_gapped_f16, kFThreads, 0));
+      resident = cus * (per > 0 ? per : 1);
+    }
+    const int64_t need = (n_hits + kFThreads - 1) / kFThreads;
+    const int64_t grid = PLAST_GAP_PERSIST ? (need < resident ? need : resident) : need;
+    if (getenv("PLAST_DEBUG_OCCUPANCY"))
+      fprintf(stderr, "k_gapped_f16: copies %d threads %d resident %d grid %lld\n", kCopies, kFThreads, resident,
+              (long long)grid);
+    hipLaunchKernelGGL(k_gapped_f16, dim3((unsigned)grid), dim3(kFThreads), 0, stream, G, d_hits, n_hits, d_gscore,
+                       d_pass);
+    timing_mark(kStageGapped, true, stream);
+    PLAST_HIP(hipGetLastError());
+    return PLAST_OK;
+  }
+  unsigned blocks = (unsigned)((n_hits + kGThreads - 1) / kGThreads);
   if (g->band == kGMaxBand)
     hipLaunchKernelGGL(k_gapped<kGMaxBand>, dim3(blocks), dim3(kGThreads), 0, stream, G, d_hits, n_hits, d_gscore,
                        d_pass);

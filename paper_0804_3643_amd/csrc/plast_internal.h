@@ -17,7 +17,7 @@ constexpr int kPadCode = PLAST_PAD_CODE;
 constexpr int kPadLen = PLAST_PAD_LEN;
 constexpr int kNLet = 21;                // 20 residues + separator
 constexpr int kScale = 8;                // scan_codes[p] = codes[p] * kScale
-constexpr int kScanSlack = 64;           // separator bytes appended to scan_codes
+constexpr int kScanSlack = 128;          // separator bytes appended to scan_codes
 
 // ---------------------------------------------------------------- tables
 // BLOSUM62 (Henikoff & Henikoff 1992); this library's transcription, rows and

@@ -220,7 +220,10 @@ def test_ungapped_empty_and_disjoint_banks(B):
 
 # --------------------------------------------------------------------------- gapped
 
-@pytest.mark.parametrize("window,band,go,ge", [(64, 16, 11, 1), (32, 8, 5, 2), (17, 0, 11, 1), (64, 16, 0, 0)])
+# band 16 with moderate costs takes the packed-f16 kernel, the others the
+# generic int32 kernel
+@pytest.mark.parametrize("window,band,go,ge", [(64, 16, 11, 1), (32, 8, 5, 2), (17, 0, 11, 1), (64, 16, 0, 0),
+                                               (40, 16, 5, 2), (7, 16, 11, 1), (64, 16, 900, 50), (1, 16, 3, 1)])
 def test_gapped_matches_oracle(B, cfg0, window, band, go, ge):
     _say("gapped cfg0 w=%d band=%d open=%d ext=%d" % (window, band, go, ge))
     ia, ib = _index(B, cfg0.bank1), _index(B, cfg0.bank2)
@@ -230,6 +233,21 @@ def test_gapped_matches_oracle(B, cfg0, window, band, go, ge):
     ref = C.gapped_scores(cfg0.bank1, cfg0.bank2, h, window=window, band=band, gap_open=go, gap_extend=ge)
     assert np.array_equal(gs.cpu().numpy().astype(np.int64), ref)
     assert np.array_equal(ps.cpu().numpy().astype(bool), ref >= params.S2)
+
+
+@pytest.mark.parametrize("wide", [False, True])
+def test_gapped_custom_matrix(B, wide):
+    _say("gapped custom matrix wide=%s" % wide)
+    rng = np.random.default_rng(31)
+    M = rng.integers(-60, 61, size=(20, 20)) if wide else rng.integers(-5, 9, size=(20, 20))
+    w = synth.make_workload(0, scale=0.3)
+    ia, ib = _index(B, w.bank1), _index(B, w.bank2)
+    hits, _ = B.ungapped_extend(ia, ib, 30, mode="batched", matrix=M)
+    assert hits.shape[0] > 100
+    gs, ps = B.gapped_filter(ia, ib, hits, 40, matrix=M)
+    ref = C.gapped_scores(w.bank1, w.bank2, hits.cpu().numpy(), matrix=M)
+    assert np.array_equal(gs.cpu().numpy().astype(np.int64), ref)
+    assert np.array_equal(ps.cpu().numpy().astype(bool), ref >= 40)
 
 
 def test_gapped_sequence_ends_and_bad_records(B):
