@@ -4,8 +4,13 @@
 One step = the whole hot path over one pair of banks already resident in HBM:
 index bank 1 and bank 2 (stage 0), batched ungapped extension of every
 candidate pair with hit compaction (stage 2), small gapped filter on the hits
-(stage 3.1).  ``value`` = candidate pairs (ungapped extensions) per second of
-step wall time.  Also reported:
+(stage 3.1).  The step is replayed from one HIP graph (``plast_pipeline_*``),
+with launch shapes measured by the library's autotuner first.  ``value`` =
+candidate pairs (ungapped extensions) per second of step wall time.  Also
+reported:
+  * the same step made of the separate eager calls (with their host
+    synchronisations) and its per-stage device times, and a check that graph
+    and eager calls give the same hits;
   * the ungapped stage alone, PLAIN (one grid per key) vs BATCHED (persistent
     work queue), device time from HIP events, after checking that both give the
     same hit multiset;
@@ -131,7 +136,7 @@ def cpu_baseline(w, gpu_hits_host, n_ext_total, sample_ext, s1, s2):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", type=int, default=1, help="synthetic workload (1 = 10,000 x 100,000 proteins)")
     ap.add_argument("--plain-reps", type=int, default=2)
@@ -139,6 +144,8 @@ def main():
     ap.add_argument("--cpu-sample-ext", type=float, default=1.5e9)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 256 MiB device copy (counter scaling for rocprofv3 --pmc runs)")
+    ap.add_argument("--no-autotune", action="store_true", help="use the built-in launch shapes")
+    ap.add_argument("--tune-reps", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the hot path is single-GPU); "
@@ -169,7 +176,14 @@ def main():
     ws_idx = B._alloc(max(wba, wbb), dev)
     ia = B.build_index(ca, sa, workspace=ws_idx, out_buf=buf_a)
     ib = B.build_index(cb, sb, workspace=ws_idx, out_buf=buf_b)
-    ext = B.Extender(ia, ib, params.S1, mode="batched")
+    tuning, tune_report, tune_s = None, None, 0.0
+    if not args.no_autotune:
+        log("autotuning launch shapes")
+        t1 = time.perf_counter()
+        tuning, tune_report = B.autotune(ia, ib, params.S1, params.S2, reps=args.tune_reps)
+        tune_s = time.perf_counter() - t1
+        log("tuned: %s (%.1f s)" % (tuning.as_dict(), tune_s))
+    ext = B.Extender(ia, ib, params.S1, mode="batched", tuning=tuning)
     hits, n_ext = ext.run()
     cap = ext.hits.shape[0]
     gbuf = torch.empty(cap, dtype=torch.int32, device=dev)
@@ -179,17 +193,33 @@ def main():
         xa = B.build_index(ca, sa, workspace=ws_idx, out_buf=buf_a)
         xb = B.build_index(cb, sb, workspace=ws_idx, out_buf=buf_b)
         h, ne = ext.run(xa, xb)
-        B.gapped_filter(xa, xb, h, params.S2, out=(gbuf, pbuf))
+        B.gapped_filter(xa, xb, h, params.S2, out=(gbuf, pbuf), tuning=tuning)
         return h, ne
 
+    # ---- the step as one graph replay
+    log("capturing the pipeline graph")
+    pipe = B.Pipeline(ca, sa, cb, sb, params.S1, params.S2, ext.n_items, cap, tuning=tuning)
     log("warmup %d" % args.warmup)
+    for _ in range(args.warmup):
+        pipe.launch()
+    torch.cuda.synchronize()
+    log("timing %d graph steps" % args.steps)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        pipe.launch()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = dt * 1e3 / args.steps
+    res = pipe.result()
+    assert res["status"] == B.OK, res
+
+    # ---- the same step from the eager calls, with per-stage device times
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
     B.timing_enable(True)
     stage_ms = {"index_ms": [], "plan_ms": [], "ungapped_ms": [], "gapped_ms": []}
-    log("timing %d steps" % args.steps)
-    torch.cuda.synchronize()
+    log("timing %d eager steps" % args.steps)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         hits, n_ext = step()
@@ -197,11 +227,18 @@ def main():
         for k in stage_ms:
             stage_ms[k].append(t[k])
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ms_per_step = dt * 1e3 / args.steps
+    eager_ms_per_step = (time.perf_counter() - t0) * 1e3 / args.steps
     n_hits = int(hits.shape[0])
     n_pass = int(pbuf[:n_hits].sum().item())
     batched_kernel_ms = float(np.mean(stage_ms["ungapped_ms"]))
+    # graph replay == eager calls: same counts, same hit multiset, same gapped pass count
+    gh, gg, gp = pipe.outputs(res["n_hits"])
+    kg, sg = pair_keys_device(torch, gh)
+    ke, se = pair_keys_device(torch, hits)
+    graph_eq = bool(res["n_ext"] == n_ext and res["n_hits"] == n_hits and torch.equal(kg, ke) and
+                    torch.equal(sg, se) and int(gp.sum().item()) == n_pass)
+    assert graph_eq, "graph replay and eager calls differ"
+    del kg, sg, ke, se, gh, gg, gp
 
     # ---- PLAIN vs BATCHED (ungapped stage only), same output required
     log("plain vs batched")
@@ -209,6 +246,8 @@ def main():
         B.timing_enable(False)
         out = {"metric": METRIC, "value": n_ext / (ms_per_step * 1e-3), "unit": "ext/s", "n_gpus": 1,
                "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+               "eager_ms_per_step": eager_ms_per_step,
+               "tuning": tuning.as_dict() if tuning is not None else None,
                "note": "profiling run (--plain-reps 0): plain schedule, wall times and baselines skipped",
                "stages_device_ms": {k: float(np.mean(v)) for k, v in stage_ms.items()}}
         if args.copy_calibration:
@@ -249,7 +288,7 @@ def main():
         xb = B.build_index(xb_c, xb_s, workspace=ws_idx, out_buf=buf_b)
         e = ext if mode == "batched" else ext_p
         h, _ = e.run(xa, xb)
-        g, p = B.gapped_filter(xa, xb, h, params.S2, out=(gbuf, pbuf))
+        g, p = B.gapped_filter(xa, xb, h, params.S2, out=(gbuf, pbuf), tuning=tuning)
         host = (h.cpu(), g.cpu(), p.cpu())
         torch.cuda.synchronize()
         return time.perf_counter() - t1, host
@@ -273,7 +312,9 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int16",
+        "dtype": "f16",
+        "dtype_note": ("integer scores carried exactly in packed binary16 (every value an integer of magnitude "
+                       "< 2048); an int16 ungapped path and an int32 gapped path serve matrices outside that range"),
         "data": "synthetic",
         "config": {
             "workload": "PLAST-P configuration %d: %s; seeded lognormal lengths (mean 300, clamped 50-1000), "
@@ -281,8 +322,11 @@ def main():
                         "S2=%d" % (args.config, spec.description, params.S1, params.S2),
             "bank1_proteins": w.bank1.n_seqs, "bank2_proteins": w.bank2.n_seqs,
             "bank1_residues": w.bank1.n_residues, "bank2_residues": w.bank2.n_residues,
-            "step": "index both banks + batched ungapped extension + gapped filter",
+            "step": "index both banks + batched ungapped extension + gapped filter, replayed as one HIP graph",
         },
+        "eager_ms_per_step": eager_ms_per_step,
+        "tuning": tuning.as_dict() if tuning is not None else None,
+        "autotune": dict(tune_report, wall_s=tune_s) if tune_report is not None else None,
         "n_ext": n_ext, "n_hits": n_hits, "n_gapped_pass": n_pass,
         "stages_device_ms": {k: float(np.mean(v)) for k, v in stage_ms.items()},
         "ungapped": {
@@ -296,7 +340,8 @@ def main():
             "batched_over_plain_speedup": float(np.mean(plain_ms)) / batched_kernel_ms,
         },
         "bank_vs_bank_wall_s": {"batched": wall_b, "plain": wall_p},
-        "bit_exact": {"plain_equals_batched": plain_eq, "no_duplicate_pairs": no_dups},
+        "bit_exact": {"plain_equals_batched": plain_eq, "no_duplicate_pairs": no_dups,
+                      "graph_equals_eager": graph_eq},
         "roofline": {
             "bound": "alu", "achieved": achieved, "peak": PEAK_INT16_TOPS, "unit": "TOP/s",
             "frac": achieved / PEAK_INT16_TOPS, "traffic": recorded_traffic(),

@@ -71,10 +71,32 @@ typedef struct {
   int64_t n_words;           /* host copy of key_off[PLAST_NKEYS] */
 } plast_index_t;
 
+/*
+ * Launch shapes (performance only: every valid tuning gives the same results).
+ * Keys are put in size classes by n2, their number of bank-b occurrences: key
+ * k is in class c iff class_min_n2[c] <= n2 < class_min_n2[c + 1] (the last
+ * class is open above).  A BATCHED work item covers 32 bank-a occurrences and
+ * up to item_cols[c] bank-b occurrences of one key.  xcd_queues = 8 splits the
+ * work list into one contiguous queue per XCD (workgroup w starts on queue
+ * w mod 8 and then steals from the others), so the items sharing bank-b
+ * windows run under one L2; 1 keeps a single queue.  gapped_threads is the
+ * workgroup size of the gapped filter.  plast_tuning_default() gives the
+ * built-in values, plast_autotune() measured ones.
+ */
+#define PLAST_TUNE_CLASSES 4
+#define PLAST_TUNE_WIDTHS 5   /* candidate item widths: 1024, 2048, 4096, 8192, 16384 */
+typedef struct {
+  int32_t class_min_n2[PLAST_TUNE_CLASSES]; /* class_min_n2[0] == 1, strictly ascending */
+  int32_t item_cols[PLAST_TUNE_CLASSES];    /* multiple of 512 in [512, 16384] */
+  int32_t xcd_queues;                       /* 1 or 8 */
+  int32_t gapped_threads;                   /* 128, 256 or 512 */
+} plast_tuning_t;
+
 typedef struct {
   int32_t nbr;             /* must be PLAST_NBR (20) */
   int32_t s1;              /* a pair is a hit iff score >= s1 */
   const int8_t* matrix;    /* host, 20x20 row-major in code order; NULL = BLOSUM62 */
+  const plast_tuning_t* tuning;  /* host; NULL = plast_tuning_default() */
 } plast_ungapped_params_t;
 
 typedef struct {
@@ -84,6 +106,7 @@ typedef struct {
   int32_t gap_extend;
   int32_t s2;              /* pass iff gapped score >= s2 */
   const int8_t* matrix;    /* host, 20x20 row-major in code order; NULL = BLOSUM62 */
+  const plast_tuning_t* tuning;  /* host; NULL = plast_tuning_default() */
 } plast_gapped_params_t;
 
 /*
@@ -118,12 +141,15 @@ int plast_build_index(const uint8_t* d_codes, const int64_t* d_seq_start, int32_
 
 /*
  * Workspace size for plast_ungapped_extend in `mode` (PLAST_PLAIN or
- * PLAST_BATCHED) for these two indexes.  Reads both key tables back to the host
- * (synchronises `stream`).  *n_ext (may be NULL) receives the number of
- * candidate pairs, sum over keys of n1(k) * n2(k).
+ * PLAST_BATCHED) for these two indexes and this tuning (NULL = default; the
+ * work list grows as item widths shrink).  Reads both key tables back to the
+ * host (synchronises `stream`).  *n_ext (may be NULL) receives the number of
+ * candidate pairs, sum over keys of n1(k) * n2(k); *n_items (may be NULL) the
+ * length of the BATCHED work list.
  */
-int plast_ungapped_workspace_bytes(const plast_index_t* a, const plast_index_t* b, int32_t mode, size_t* bytes,
-                                   int64_t* n_ext, void* stream);
+int plast_ungapped_workspace_bytes(const plast_index_t* a, const plast_index_t* b, int32_t mode,
+                                   const plast_tuning_t* tuning, size_t* bytes, int64_t* n_ext, int64_t* n_items,
+                                   void* stream);
 
 /*
  * Stage 2, ungapped extension (Sec. 3.2 generic algorithm, Sec. 3.3.3) with hit
@@ -184,6 +210,91 @@ typedef struct {
 
 int plast_timing_enable(int on);
 int plast_timing_read(plast_timing_t* out);
+
+/* Built-in launch shapes: classes from n2 = 1, 2048, 8192, 32768, every item
+ * 4096 columns wide, one queue, 256-thread gapped workgroups. */
+int plast_tuning_default(plast_tuning_t* out);
+
+/* Per-candidate device times of one plast_autotune call, in milliseconds
+ * (best of `reps`; 0 = not run: empty class, or a width that gives the same
+ * items as a smaller one, or a work list that does not fit the workspace). */
+typedef struct {
+  int64_t class_ext[PLAST_TUNE_CLASSES];                  /* pairs scored per class */
+  float class_ms[PLAST_TUNE_CLASSES][PLAST_TUNE_WIDTHS];  /* class alone, per item width */
+  float queue_ms[2];                                      /* whole list: 1 queue, 8 queues */
+  float gapped_ms[3];                                     /* 128, 256, 512 threads */
+} plast_tune_report_t;
+
+/*
+ * Autotuner of the BATCHED launch shapes for one pair of indexes.  Starting
+ * from p->tuning (or the default): for each size class, the extension kernel
+ * runs over that class's work items alone at every candidate width and the
+ * fastest width is kept; then the whole work list runs with 1 and with 8
+ * queues; then the gapped filter runs over the hits with each workgroup size.
+ * Every timing is the best of `reps` (1..20) runs, measured with HIP events
+ * around the kernel.  The hit buffers are scratch during the search and hold
+ * the hits of the last extension run afterwards.  d_ws must hold the work list
+ * of the smallest width (plast_ungapped_workspace_bytes with item_cols all
+ * 1024); candidates whose list does not fit are skipped.
+ * Errors: as plast_ungapped_extend (PLAST_E_CAPACITY when the hits do not fit)
+ * and plast_gapped_filter.  Synchronises `stream`.
+ */
+int plast_autotune(const plast_index_t* a, const plast_index_t* b, const plast_ungapped_params_t* p,
+                   const plast_gapped_params_t* g, int32_t reps, void* d_ws, size_t ws_bytes,
+                   plast_hit_t* d_hits, int64_t capacity, int32_t* d_gscore, uint8_t* d_pass,
+                   plast_tuning_t* out, plast_tune_report_t* report, void* stream);
+
+/*
+ * Whole-search pipeline replayed from a HIP graph: index both banks, build the
+ * work list, run the persistent extension kernel and the gapped filter, with
+ * no host synchronisation inside.  The graph is captured once, on a stream the
+ * pipeline owns, from exactly the kernels that plast_build_index,
+ * plast_ungapped_extend (BATCHED) and plast_gapped_filter launch; error checks
+ * that those calls make on the host happen on the device instead (a bank with
+ * a layout or alphabet error yields no hits and sets the status).  The gapped
+ * filter reads the hit count from device memory and scores min(hits,
+ * capacity) records.
+ *
+ * A bank is described by its padded codes and seq_start (as for
+ * plast_build_index); the pointers and sizes are fixed at creation, the
+ * contents may change between launches (sizes, and so a new work-list length,
+ * may not).  max_items bounds the work list (plast_ungapped_workspace_bytes
+ * reports the current length in *n_items); a longer list yields
+ * PLAST_E_WORKSPACE in the result and no hits.
+ * The workspace (plast_pipeline_workspace_bytes, 256-byte aligned) holds both
+ * indexes, the build scratch and the work list; it and the output buffers are
+ * caller memory that must outlive the pipeline.
+ */
+typedef struct plast_pipeline plast_pipeline_t;
+typedef struct {
+  const uint8_t* codes;     /* device, padded layout, n_padded bytes */
+  const int64_t* seq_start; /* device, n_seqs + 1 */
+  int32_t n_seqs;
+  int64_t n_padded;
+} plast_bank_t;
+typedef struct {
+  int32_t status;           /* PLAST_OK, PLAST_E_LAYOUT, PLAST_E_ALPHABET, PLAST_E_WORKSPACE or PLAST_E_CAPACITY */
+  int32_t n_items;          /* work-list length */
+  int64_t n_hits;           /* hits found (may exceed capacity) */
+  int64_t n_ext;            /* pairs scored */
+  int64_t n_words_a, n_words_b;
+} plast_pipeline_result_t;
+
+int plast_pipeline_workspace_bytes(const plast_bank_t* a, const plast_bank_t* b, int64_t max_items, size_t* bytes);
+/* Captures and instantiates the graph (does not run it).  *out receives a host
+ * handle; release it with plast_pipeline_destroy. */
+int plast_pipeline_create(const plast_bank_t* a, const plast_bank_t* b, const plast_ungapped_params_t* p,
+                          const plast_gapped_params_t* g, int64_t max_items, void* d_ws, size_t ws_bytes,
+                          plast_hit_t* d_hits, int64_t capacity, int32_t* d_gscore, uint8_t* d_pass,
+                          plast_pipeline_t** out);
+/* Enqueues one replay on `stream`; does not synchronise. */
+int plast_pipeline_launch(plast_pipeline_t* pl, void* stream);
+/* Waits for `stream` and reads the counts and status of the last replay. */
+int plast_pipeline_result(plast_pipeline_t* pl, plast_pipeline_result_t* out, void* stream);
+/* Index views of the last replay's banks (which = 0: a, 1: b); n_words is -1
+ * until plast_pipeline_result has been called. */
+int plast_pipeline_index(const plast_pipeline_t* pl, int32_t which, plast_index_t* out);
+int plast_pipeline_destroy(plast_pipeline_t* pl);
 
 const char* plast_strerror(int code);
 const char* plast_last_error(void);

@@ -25,7 +25,14 @@ MODES = {"plain": PLAIN, "batched": BATCHED}
 OK, E_ARG, E_ALPHABET, E_CAPACITY, E_WORKSPACE, E_HIP, E_LAYOUT = 0, -1, -2, -3, -4, -5, -6
 
 EXPORTS = ("plast_index_bytes", "plast_build_index", "plast_ungapped_workspace_bytes", "plast_ungapped_extend",
-           "plast_gapped_filter", "plast_timing_enable", "plast_timing_read", "plast_strerror", "plast_last_error")
+           "plast_gapped_filter", "plast_timing_enable", "plast_timing_read", "plast_tuning_default",
+           "plast_autotune", "plast_pipeline_workspace_bytes", "plast_pipeline_create", "plast_pipeline_launch",
+           "plast_pipeline_result", "plast_pipeline_index", "plast_pipeline_destroy", "plast_strerror",
+           "plast_last_error")
+
+TUNE_CLASSES = 4
+TUNE_WIDTHS = (1024, 2048, 4096, 8192, 16384)
+GAPPED_THREADS = (128, 256, 512)
 
 
 class PlastError(RuntimeError):
@@ -45,13 +52,57 @@ class Timing(ctypes.Structure):
                 ("gapped_ms", ctypes.c_float), ("ungapped_launches", ctypes.c_int64)]
 
 
+class Tuning(ctypes.Structure):
+    """Launch shapes (``plast_tuning_t``): size classes by n2, item width per
+    class, work queues (1 or 8), gapped workgroup size."""
+    _fields_ = [("class_min_n2", ctypes.c_int32 * TUNE_CLASSES), ("item_cols", ctypes.c_int32 * TUNE_CLASSES),
+                ("xcd_queues", ctypes.c_int32), ("gapped_threads", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {"class_min_n2": list(self.class_min_n2), "item_cols": list(self.item_cols),
+                "xcd_queues": int(self.xcd_queues), "gapped_threads": int(self.gapped_threads)}
+
+    @classmethod
+    def from_dict(cls, d):
+        t = tuning_default()
+        for k in ("class_min_n2", "item_cols"):
+            if k in d:
+                getattr(t, k)[:] = [int(v) for v in d[k]]
+        for k in ("xcd_queues", "gapped_threads"):
+            if k in d:
+                setattr(t, k, int(d[k]))
+        return t
+
+
+class TuneReport(ctypes.Structure):
+    _fields_ = [("class_ext", ctypes.c_int64 * TUNE_CLASSES),
+                ("class_ms", (ctypes.c_float * len(TUNE_WIDTHS)) * TUNE_CLASSES),
+                ("queue_ms", ctypes.c_float * 2), ("gapped_ms", ctypes.c_float * 3)]
+
+    def as_dict(self):
+        return {"class_ext": list(self.class_ext), "class_ms": [list(r) for r in self.class_ms],
+                "queue_ms": list(self.queue_ms), "gapped_ms": list(self.gapped_ms)}
+
+
 class UngappedParams(ctypes.Structure):
-    _fields_ = [("nbr", ctypes.c_int32), ("s1", ctypes.c_int32), ("matrix", ctypes.c_void_p)]
+    _fields_ = [("nbr", ctypes.c_int32), ("s1", ctypes.c_int32), ("matrix", ctypes.c_void_p),
+                ("tuning", ctypes.c_void_p)]
 
 
 class GappedParams(ctypes.Structure):
     _fields_ = [("window", ctypes.c_int32), ("band", ctypes.c_int32), ("gap_open", ctypes.c_int32),
-                ("gap_extend", ctypes.c_int32), ("s2", ctypes.c_int32), ("matrix", ctypes.c_void_p)]
+                ("gap_extend", ctypes.c_int32), ("s2", ctypes.c_int32), ("matrix", ctypes.c_void_p),
+                ("tuning", ctypes.c_void_p)]
+
+
+class BankDesc(ctypes.Structure):
+    _fields_ = [("codes", ctypes.c_void_p), ("seq_start", ctypes.c_void_p), ("n_seqs", ctypes.c_int32),
+                ("n_padded", ctypes.c_int64)]
+
+
+class PipelineResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("n_items", ctypes.c_int32), ("n_hits", ctypes.c_int64),
+                ("n_ext", ctypes.c_int64), ("n_words_a", ctypes.c_int64), ("n_words_b", ctypes.c_int64)]
 
 
 _lib = None
@@ -68,8 +119,9 @@ def load():
         P, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
         lib.plast_index_bytes.argtypes = [i64, i32, ctypes.POINTER(sz), ctypes.POINTER(sz)]
         lib.plast_build_index.argtypes = [P, P, i32, i64, P, sz, P, sz, ctypes.POINTER(IndexView), P]
-        lib.plast_ungapped_workspace_bytes.argtypes = [ctypes.POINTER(IndexView), ctypes.POINTER(IndexView), i32,
-                                                       ctypes.POINTER(sz), ctypes.POINTER(i64), P]
+        IV = ctypes.POINTER(IndexView)
+        lib.plast_ungapped_workspace_bytes.argtypes = [IV, IV, i32, ctypes.POINTER(Tuning), ctypes.POINTER(sz),
+                                                       ctypes.POINTER(i64), ctypes.POINTER(i64), P]
         lib.plast_ungapped_extend.argtypes = [ctypes.POINTER(IndexView), ctypes.POINTER(IndexView),
                                               ctypes.POINTER(UngappedParams), i32, P, sz, P, i64,
                                               ctypes.POINTER(i64), ctypes.POINTER(i64), P]
@@ -77,8 +129,18 @@ def load():
                                             ctypes.POINTER(GappedParams), P, P, P]
         lib.plast_timing_enable.argtypes = [ctypes.c_int]
         lib.plast_timing_read.argtypes = [ctypes.POINTER(Timing)]
-        for f in ("plast_index_bytes", "plast_build_index", "plast_ungapped_workspace_bytes",
-                  "plast_ungapped_extend", "plast_gapped_filter", "plast_timing_enable", "plast_timing_read"):
+        lib.plast_tuning_default.argtypes = [ctypes.POINTER(Tuning)]
+        lib.plast_autotune.argtypes = [IV, IV, ctypes.POINTER(UngappedParams), ctypes.POINTER(GappedParams), i32, P,
+                                       sz, P, i64, P, P, ctypes.POINTER(Tuning), ctypes.POINTER(TuneReport), P]
+        BD = ctypes.POINTER(BankDesc)
+        lib.plast_pipeline_workspace_bytes.argtypes = [BD, BD, i64, ctypes.POINTER(sz)]
+        lib.plast_pipeline_create.argtypes = [BD, BD, ctypes.POINTER(UngappedParams), ctypes.POINTER(GappedParams),
+                                              i64, P, sz, P, i64, P, P, ctypes.POINTER(P)]
+        lib.plast_pipeline_launch.argtypes = [P, P]
+        lib.plast_pipeline_result.argtypes = [P, ctypes.POINTER(PipelineResult), P]
+        lib.plast_pipeline_index.argtypes = [P, i32, IV]
+        lib.plast_pipeline_destroy.argtypes = [P]
+        for f in EXPORTS[:-2]:
             getattr(lib, f).restype = ctypes.c_int
         lib.plast_strerror.argtypes = [ctypes.c_int]
         lib.plast_strerror.restype = ctypes.c_char_p
@@ -185,27 +247,50 @@ def _matrix_ptr(matrix):
     return m, ctypes.c_void_p(m.ctypes.data)
 
 
-def ungapped_workspace_bytes(ia, ib, mode="batched", stream=None):
-    sz, n_ext = ctypes.c_size_t(0), ctypes.c_int64(0)
+def tuning_default():
+    t = Tuning()
+    _check(load().plast_tuning_default(ctypes.byref(t)), "plast_tuning_default")
+    return t
+
+
+def _tuning(t):
+    """Accepts None, a Tuning or a dict; returns (object kept alive, pointer)."""
+    if t is None:
+        return None, ctypes.c_void_p(0)
+    if isinstance(t, dict):
+        t = Tuning.from_dict(t)
+    return t, ctypes.c_void_p(ctypes.addressof(t))
+
+
+def ungapped_workspace_bytes(ia, ib, mode="batched", stream=None, tuning=None):
+    """Returns (workspace bytes, pairs to score, BATCHED work-list length)."""
+    sz, n_ext, n_items = ctypes.c_size_t(0), ctypes.c_int64(0), ctypes.c_int64(0)
+    t, _ = _tuning(tuning)
     _check(load().plast_ungapped_workspace_bytes(ctypes.byref(ia.view), ctypes.byref(ib.view), MODES[mode],
-                                                 ctypes.byref(sz), ctypes.byref(n_ext), _stream(stream)),
+                                                 ctypes.byref(t) if t is not None else None, ctypes.byref(sz),
+                                                 ctypes.byref(n_ext), ctypes.byref(n_items), _stream(stream)),
            "plast_ungapped_workspace_bytes")
-    return sz.value, n_ext.value
+    return sz.value, n_ext.value, n_items.value
+
+
+def default_capacity(n_ext):
+    return int(n_ext * 0.004) + 4096
 
 
 class Extender:
     """Reusable ungapped-extension call: holds the workspace and the hit buffer
     so that repeated calls (benchmark steps) allocate nothing."""
 
-    def __init__(self, ia, ib, s1, mode="batched", capacity=None, matrix=None, stream=None):
+    def __init__(self, ia, ib, s1, mode="batched", capacity=None, matrix=None, stream=None, tuning=None):
         self.ia, self.ib, self.mode = ia, ib, MODES[mode]
-        wsb, self.n_ext_expected = ungapped_workspace_bytes(ia, ib, mode, stream)
+        self._tun, tp = _tuning(tuning)
+        wsb, self.n_ext_expected, self.n_items = ungapped_workspace_bytes(ia, ib, mode, stream, self._tun)
         self.ws = _alloc(wsb, ia.codes.device)
         if capacity is None:
-            capacity = int(self.n_ext_expected * 0.004) + 4096
+            capacity = default_capacity(self.n_ext_expected)
         self.hits = torch.empty((int(capacity), 5), dtype=torch.int32, device=ia.codes.device)
         self._mat, mp = _matrix_ptr(matrix)
-        self.params = UngappedParams(NBR, int(s1), mp)
+        self.params = UngappedParams(NBR, int(s1), mp, tp)
         self.stream = stream
 
     def run(self, ia=None, ib=None):
@@ -228,13 +313,13 @@ class Extender:
             return self.hits[:n_hits.value], n_ext.value
 
 
-def ungapped_extend(ia, ib, s1, mode="batched", capacity=None, matrix=None, stream=None):
+def ungapped_extend(ia, ib, s1, mode="batched", capacity=None, matrix=None, stream=None, tuning=None):
     """Stage 2: returns (hits int32[n, 5] device tensor in unspecified order, n_ext)."""
-    return Extender(ia, ib, s1, mode, capacity, matrix, stream).run()
+    return Extender(ia, ib, s1, mode, capacity, matrix, stream, tuning).run()
 
 
 def gapped_filter(ia, ib, hits, s2, window=64, band=16, gap_open=11, gap_extend=1, matrix=None, stream=None,
-                  out=None):
+                  out=None, tuning=None):
     """Stage 3.1: returns (gscore int32[n], pass uint8[n]) device tensors."""
     n = hits.shape[0]
     dev = ia.codes.device
@@ -244,12 +329,104 @@ def gapped_filter(ia, ib, hits, s2, window=64, band=16, gap_open=11, gap_extend=
     else:
         gs, ps = out[0][:n], out[1][:n]
     m, mp = _matrix_ptr(matrix)
-    g = GappedParams(int(window), int(band), int(gap_open), int(gap_extend), int(s2), mp)
+    t, tp = _tuning(tuning)
+    g = GappedParams(int(window), int(band), int(gap_open), int(gap_extend), int(s2), mp, tp)
     hp = hits if hits.is_contiguous() else hits.contiguous()
     _check(load().plast_gapped_filter(ctypes.byref(ia.view), ctypes.byref(ib.view), _ptr(hp), n, ctypes.byref(g),
                                       _ptr(gs), _ptr(ps), _stream(stream)), "plast_gapped_filter")
-    del m
+    del m, t
     return gs, ps
+
+
+def autotune(ia, ib, s1, s2, reps=3, capacity=None, matrix=None, window=64, band=16, gap_open=11, gap_extend=1,
+             start=None, stream=None):
+    """Measures the launch shapes for these banks (``plast_autotune``).
+    Returns (Tuning, report dict)."""
+    dev = ia.codes.device
+    smallest = tuning_default()
+    smallest.item_cols[:] = [TUNE_WIDTHS[0]] * TUNE_CLASSES
+    wsb, n_ext, _ = ungapped_workspace_bytes(ia, ib, "batched", stream, smallest)
+    if capacity is None:  # one extension call to learn the hit count
+        h, _ = Extender(ia, ib, s1, "batched", None, matrix, stream, start).run()
+        capacity = h.shape[0] + 1024
+        del h
+    ws = _alloc(wsb, dev)
+    cap = int(capacity)
+    hits = torch.empty((cap, 5), dtype=torch.int32, device=dev)
+    gs = torch.empty(cap, dtype=torch.int32, device=dev)
+    ps = torch.empty(cap, dtype=torch.uint8, device=dev)
+    m, mp = _matrix_ptr(matrix)
+    st, sp = _tuning(start)
+    u = UngappedParams(NBR, int(s1), mp, sp)
+    g = GappedParams(int(window), int(band), int(gap_open), int(gap_extend), int(s2), mp, sp)
+    out, rep = Tuning(), TuneReport()
+    _check(load().plast_autotune(ctypes.byref(ia.view), ctypes.byref(ib.view), ctypes.byref(u), ctypes.byref(g),
+                                 int(reps), _ptr(ws), ws.numel(), _ptr(hits), cap, _ptr(gs), _ptr(ps),
+                                 ctypes.byref(out), ctypes.byref(rep), _stream(stream)), "plast_autotune")
+    del m, st
+    return out, rep.as_dict()
+
+
+class Pipeline:
+    """Graph-replayed whole search over two device banks (``plast_pipeline_*``).
+    Owns its workspace and output tensors; ``launch()`` enqueues one replay,
+    ``result()`` waits and returns the counts and status."""
+
+    def __init__(self, codes_a, starts_a, codes_b, starts_b, s1, s2, max_items, capacity, matrix=None,
+                 tuning=None, window=64, band=16, gap_open=11, gap_extend=1):
+        dev = codes_a.device
+        self._keep = (codes_a, starts_a, codes_b, starts_b)
+        self.a = BankDesc(codes_a.data_ptr(), starts_a.data_ptr(), starts_a.numel() - 1, codes_a.numel())
+        self.b = BankDesc(codes_b.data_ptr(), starts_b.data_ptr(), starts_b.numel() - 1, codes_b.numel())
+        sz = ctypes.c_size_t(0)
+        _check(load().plast_pipeline_workspace_bytes(ctypes.byref(self.a), ctypes.byref(self.b), int(max_items),
+                                                     ctypes.byref(sz)), "plast_pipeline_workspace_bytes")
+        self.ws = _alloc(sz.value, dev)
+        self.capacity = int(capacity)
+        self.hits = torch.empty((max(self.capacity, 1), 5), dtype=torch.int32, device=dev)
+        self.gscore = torch.empty(max(self.capacity, 1), dtype=torch.int32, device=dev)
+        self.passed = torch.empty(max(self.capacity, 1), dtype=torch.uint8, device=dev)
+        m, mp = _matrix_ptr(matrix)
+        t, tp = _tuning(tuning)
+        u = UngappedParams(NBR, int(s1), mp, tp)
+        g = GappedParams(int(window), int(band), int(gap_open), int(gap_extend), int(s2), mp, tp)
+        h = ctypes.c_void_p(0)
+        torch.cuda.synchronize(dev)  # inputs written by torch are complete before the capture
+        _check(load().plast_pipeline_create(ctypes.byref(self.a), ctypes.byref(self.b), ctypes.byref(u),
+                                            ctypes.byref(g), int(max_items), _ptr(self.ws), self.ws.numel(),
+                                            _ptr(self.hits), self.capacity, _ptr(self.gscore), _ptr(self.passed),
+                                            ctypes.byref(h)), "plast_pipeline_create")
+        del m, t
+        self.handle = h
+
+    def launch(self, stream=None):
+        _check(load().plast_pipeline_launch(self.handle, _stream(stream)), "plast_pipeline_launch")
+
+    def result(self, stream=None):
+        r = PipelineResult()
+        _check(load().plast_pipeline_result(self.handle, ctypes.byref(r), _stream(stream)), "plast_pipeline_result")
+        return {"status": int(r.status), "n_items": int(r.n_items), "n_hits": int(r.n_hits), "n_ext": int(r.n_ext),
+                "n_words_a": int(r.n_words_a), "n_words_b": int(r.n_words_b)}
+
+    def outputs(self, n_hits):
+        n = min(int(n_hits), self.capacity)
+        return self.hits[:n], self.gscore[:n], self.passed[:n]
+
+    def index_view(self, which):
+        v = IndexView()
+        _check(load().plast_pipeline_index(self.handle, int(which), ctypes.byref(v)), "plast_pipeline_index")
+        return v
+
+    def close(self):
+        if getattr(self, "handle", None):
+            h, self.handle = self.handle, None
+            _check(load().plast_pipeline_destroy(h), "plast_pipeline_destroy")
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def canonical_hits(hits):

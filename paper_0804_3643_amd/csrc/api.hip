@@ -90,6 +90,8 @@ bool timing_on() { return g_timing; }
 
 void timing_mark(TimedStage st, bool stop, hipStream_t s) {
   if (!g_timing) return;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;  // not inside a graph
   if (hipEventRecord(g_ev[st][stop ? 1 : 0], s) == hipSuccess && stop) g_ev_used[st] = true;
 }
 
@@ -178,14 +180,55 @@ static int check_index(const plast_index_t* x, const char* name) {
   return PLAST_OK;
 }
 
-int plast_ungapped_workspace_bytes(const plast_index_t* a, const plast_index_t* b, int32_t mode, size_t* bytes,
-                                   int64_t* n_ext, void* stream) {
+static int tuning_or_default(const plast_tuning_t* t, plast_tuning_t* out) {
+  if (!t) {
+    tuning_default(out);
+    return PLAST_OK;
+  }
+  *out = *t;
+  return check_tuning(out);
+}
+
+int plast_tuning_default(plast_tuning_t* out) {
+  g_last_error[0] = 0;
+  if (!out) return set_error(PLAST_E_ARG, "null output pointer");
+  tuning_default(out);
+  return PLAST_OK;
+}
+
+int plast_ungapped_workspace_bytes(const plast_index_t* a, const plast_index_t* b, int32_t mode,
+                                   const plast_tuning_t* tuning, size_t* bytes, int64_t* n_ext, int64_t* n_items,
+                                   void* stream) {
   g_last_error[0] = 0;
   int rc;
   if ((rc = check_index(a, "a")) || (rc = check_index(b, "b"))) return rc;
   if (!bytes) return set_error(PLAST_E_ARG, "null output pointer");
   if (mode != PLAST_PLAIN && mode != PLAST_BATCHED) return set_error(PLAST_E_ARG, "unknown mode %d", mode);
-  return ungapped_ws_bytes_impl(a, b, mode, bytes, n_ext, (hipStream_t)stream);
+  plast_tuning_t t;
+  if ((rc = tuning_or_default(tuning, &t))) return rc;
+  return ungapped_ws_bytes_impl(a, b, mode, t, bytes, n_ext, n_items, (hipStream_t)stream);
+}
+
+static int check_uparams(const plast_ungapped_params_t* p) {
+  if (!p) return set_error(PLAST_E_ARG, "null ungapped parameters");
+  if (p->nbr != kNbr) return set_error(PLAST_E_ARG, "nbr=%d unsupported (only %d)", p->nbr, kNbr);
+  plast_tuning_t t;
+  return tuning_or_default(p->tuning, &t);
+}
+
+static int check_gparams(const plast_gapped_params_t* g) {
+  if (!g) return set_error(PLAST_E_ARG, "null gapped parameters");
+  if (g->window < 1 || g->window > 64 || g->band < 0 || g->band > 16 || g->gap_open < 0 || g->gap_extend < 0 ||
+      g->gap_open + g->gap_extend > 1000)
+    return set_error(PLAST_E_ARG, "gapped parameters out of range (window 1..64, band 0..16, costs >= 0)");
+  plast_tuning_t t;
+  return tuning_or_default(g->tuning, &t);
+}
+
+static int check_bank(const plast_bank_t* x, const char* name) {
+  if (!x || !x->codes || !x->seq_start) return set_error(PLAST_E_ARG, "%s: null bank pointer", name);
+  size_t ib = 0, wb = 0;
+  return plast_index_bytes(x->n_padded, x->n_seqs, &ib, &wb);
 }
 
 int plast_ungapped_extend(const plast_index_t* a, const plast_index_t* b, const plast_ungapped_params_t* p,
@@ -196,7 +239,7 @@ int plast_ungapped_extend(const plast_index_t* a, const plast_index_t* b, const 
   if ((rc = check_index(a, "a")) || (rc = check_index(b, "b"))) return rc;
   if (!p || !h_n_hits || !d_ws || capacity < 0 || (capacity > 0 && !d_hits))
     return set_error(PLAST_E_ARG, "null pointer or negative capacity");
-  if (p->nbr != kNbr) return set_error(PLAST_E_ARG, "nbr=%d unsupported (only %d)", p->nbr, kNbr);
+  if ((rc = check_uparams(p))) return rc;
   if (mode != PLAST_PLAIN && mode != PLAST_BATCHED) return set_error(PLAST_E_ARG, "unknown mode %d", mode);
   if ((uintptr_t)d_ws & 255) return set_error(PLAST_E_ARG, "workspace must be 256-byte aligned");
   return ungapped_extend_impl(a, b, p, mode, d_ws, ws_bytes, d_hits, capacity, h_n_hits, h_n_ext,
@@ -210,11 +253,76 @@ int plast_gapped_filter(const plast_index_t* a, const plast_index_t* b, const pl
   if ((rc = check_index(a, "a")) || (rc = check_index(b, "b"))) return rc;
   if (!g || n_hits < 0 || (n_hits > 0 && (!d_hits || !d_gscore || !d_pass)))
     return set_error(PLAST_E_ARG, "null pointer or negative hit count");
-  if (g->window < 1 || g->window > 64 || g->band < 0 || g->band > 16 || g->gap_open < 0 || g->gap_extend < 0 ||
-      g->gap_open + g->gap_extend > 1000)
-    return set_error(PLAST_E_ARG, "gapped parameters out of range (window 1..64, band 0..16, costs >= 0)");
+  if ((rc = check_gparams(g))) return rc;
   if (n_hits == 0) return PLAST_OK;
-  return gapped_filter_impl(a, b, d_hits, n_hits, g, d_gscore, d_pass, (hipStream_t)stream);
+  return gapped_filter_impl(a, b, d_hits, n_hits, nullptr, g, d_gscore, d_pass, (hipStream_t)stream);
+}
+
+int plast_autotune(const plast_index_t* a, const plast_index_t* b, const plast_ungapped_params_t* p,
+                   const plast_gapped_params_t* g, int32_t reps, void* d_ws, size_t ws_bytes,
+                   plast_hit_t* d_hits, int64_t capacity, int32_t* d_gscore, uint8_t* d_pass,
+                   plast_tuning_t* out, plast_tune_report_t* report, void* stream) {
+  g_last_error[0] = 0;
+  int rc;
+  if ((rc = check_index(a, "a")) || (rc = check_index(b, "b")) || (rc = check_uparams(p)) || (rc = check_gparams(g)))
+    return rc;
+  if (!out || !d_ws || capacity < 0 || (capacity > 0 && (!d_hits || !d_gscore || !d_pass)))
+    return set_error(PLAST_E_ARG, "null pointer or negative capacity");
+  if (reps < 1 || reps > 20) return set_error(PLAST_E_ARG, "reps=%d outside 1..20", reps);
+  if ((uintptr_t)d_ws & 255) return set_error(PLAST_E_ARG, "workspace must be 256-byte aligned");
+  return autotune_impl(a, b, p, g, reps, d_ws, ws_bytes, d_hits, capacity, d_gscore, d_pass, out, report,
+                       (hipStream_t)stream);
+}
+
+int plast_pipeline_workspace_bytes(const plast_bank_t* a, const plast_bank_t* b, int64_t max_items, size_t* bytes) {
+  g_last_error[0] = 0;
+  int rc;
+  if ((rc = check_bank(a, "a")) || (rc = check_bank(b, "b"))) return rc;
+  if (!bytes || max_items < 0 || max_items > INT32_MAX)
+    return set_error(PLAST_E_ARG, "null output pointer or max_items outside [0, 2^31)");
+  *bytes = pipeline_ws_bytes(a, b, max_items);
+  return PLAST_OK;
+}
+
+int plast_pipeline_create(const plast_bank_t* a, const plast_bank_t* b, const plast_ungapped_params_t* p,
+                          const plast_gapped_params_t* g, int64_t max_items, void* d_ws, size_t ws_bytes,
+                          plast_hit_t* d_hits, int64_t capacity, int32_t* d_gscore, uint8_t* d_pass,
+                          plast_pipeline_t** out) {
+  g_last_error[0] = 0;
+  int rc;
+  if ((rc = check_bank(a, "a")) || (rc = check_bank(b, "b")) || (rc = check_uparams(p)) || (rc = check_gparams(g)))
+    return rc;
+  if (!out || !d_ws || capacity < 0 || (capacity > 0 && (!d_hits || !d_gscore || !d_pass)) || max_items < 0 ||
+      max_items > INT32_MAX)
+    return set_error(PLAST_E_ARG, "null pointer, negative capacity or max_items outside [0, 2^31)");
+  if ((uintptr_t)d_ws & 255) return set_error(PLAST_E_ARG, "workspace must be 256-byte aligned");
+  if (ws_bytes < pipeline_ws_bytes(a, b, max_items))
+    return set_error(PLAST_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, pipeline_ws_bytes(a, b, max_items));
+  return pipeline_create_impl(a, b, p, g, max_items, d_ws, d_hits, capacity, d_gscore, d_pass, out);
+}
+
+int plast_pipeline_launch(plast_pipeline_t* pl, void* stream) {
+  g_last_error[0] = 0;
+  if (!pl) return set_error(PLAST_E_ARG, "null pipeline");
+  return pipeline_launch_impl(pl, (hipStream_t)stream);
+}
+
+int plast_pipeline_result(plast_pipeline_t* pl, plast_pipeline_result_t* out, void* stream) {
+  g_last_error[0] = 0;
+  if (!pl || !out) return set_error(PLAST_E_ARG, "null pointer");
+  return pipeline_result_impl(pl, out, (hipStream_t)stream);
+}
+
+int plast_pipeline_index(const plast_pipeline_t* pl, int32_t which, plast_index_t* out) {
+  g_last_error[0] = 0;
+  if (!pl || !out || (which != 0 && which != 1)) return set_error(PLAST_E_ARG, "null pointer or which not 0/1");
+  return pipeline_index_impl(pl, which, out);
+}
+
+int plast_pipeline_destroy(plast_pipeline_t* pl) {
+  g_last_error[0] = 0;
+  if (!pl) return PLAST_OK;
+  return pipeline_destroy_impl(pl);
 }
 
 }  // extern "C"

@@ -24,10 +24,8 @@
 // the anchor, and v_pk_maximum3_f16 takes H = max(diagonal, E, F) in one
 // instruction.  Letters are fetched from global memory one block of rows
 // ahead as aligned dwords (four letters per load).  Substitution scores come
-// from a binary16 table in LDS (optionally replicated per LDS bank).
-#include <stdio.h>
-#include <stdlib.h>
-
+// from a dense binary16 table in LDS.  The workgroup size is a launch-shape
+// parameter (128, 256 or 512 threads).
 #include "plast_internal.h"
 
 namespace plast {
@@ -113,10 +111,11 @@ __device__ int gapped_side(const GappedArgs& G, GSmem& S, int t, int lx, int ly,
 
 template <int BAND>
 __global__ __launch_bounds__(kGThreads) void k_gapped(GappedArgs G, const plast_hit_t* __restrict__ hits,
-                                                      int64_t n_hits, int32_t* __restrict__ gscore,
-                                                      uint8_t* __restrict__ pass) {
+                                                      int64_t n_hits, const unsigned long long* __restrict__ n_dev,
+                                                      int32_t* __restrict__ gscore, uint8_t* __restrict__ pass) {
   __shared__ GSmem S;
   for (int i = threadIdx.x; i < kNLet * 22; i += kGThreads) S.mat[i] = G.mat[i];
+  if (n_dev) n_hits = min(n_hits, (int64_t)*n_dev);
   __syncthreads();
   const int t = threadIdx.x;
   const int64_t h = (int64_t)blockIdx.x * kGThreads + t;
@@ -162,35 +161,16 @@ __global__ __launch_bounds__(kGThreads) void k_gapped(GappedArgs G, const plast_
 
 // ---------------------------------------------------------------- packed f16 path
 typedef _Float16 gh2 __attribute__((ext_vector_type(2)));
-// Tunables of the fast path (compile-time).  Defaults are the fastest of a sweep
-// on MI355X, configuration 1 (26.8M hits): a dense table, 256 threads, one hit
-// block per workgroup, up to 256 VGPRs (2 wavefronts per SIMD), 4 rows per block
-// (19.3 ms; table copies 16 or 32 and 3 wavefronts per SIMD were not faster).
-#ifndef PLAST_GAP_COPIES
-#define PLAST_GAP_COPIES 0
-#endif
-#ifndef PLAST_GAP_THREADS
-#define PLAST_GAP_THREADS 256
-#endif
-#ifndef PLAST_GAP_PERSIST
-#define PLAST_GAP_PERSIST 0
-#endif
-#ifndef PLAST_GAP_BLOCK
-#define PLAST_GAP_BLOCK 4
-#endif
-constexpr int kFThreads = PLAST_GAP_THREADS;
-constexpr int kFBlock = PLAST_GAP_BLOCK;        // rows per unrolled block (1..4)
+// Rows per unrolled block and register budget of the fast path: the fastest
+// of a sweep on MI355X (4 rows per block, up to 256 VGPRs, i.e. 2 wavefronts
+// per SIMD; replicated tables and 3 wavefronts per SIMD were not faster).
+constexpr int kFBlock = 4;                      // rows per unrolled block (1..4)
 static_assert(kFBlock >= 1 && kFBlock <= 4, "rows per block");
 constexpr int kFY = kGCells + kFBlock - 1;      // y letters held for a block (36)
-// 0: one dense binary16 table (2-byte entries); n > 0: n copies of 4-byte entries,
-// copy c serving lanes l with l mod n = c.
-constexpr int kCopies = PLAST_GAP_COPIES;
-static_assert(kCopies == 0 || kCopies == 1 || kCopies == 16 || kCopies == 32, "table copies");
-constexpr int kTblDwords = kCopies == 0 ? (kNLet * kNLet + 1) / 2 : kNLet * kNLet * kCopies;
+constexpr int kTblDwords = (kNLet * kNLet + 1) / 2;
 constexpr uint32_t kWall8 = kPadCode * kScale;  // the separator letter serves as wall: it scores -inf
-// Table entry (x, y) of copy c is the low half of dword (x * 21 + y) * kCopies + c:
-// byte offset x * kRowBytes + y * kEntry + c * 4.
-constexpr uint32_t kEntry = kCopies == 0 ? 2 : kCopies * 4;
+// Table entry (x, y) is the binary16 at byte offset x * kRowBytes + y * kEntry.
+constexpr uint32_t kEntry = 2;
 constexpr uint32_t kRowBytes = kNLet * kEntry;
 static_assert(kNLet * kRowBytes < 65536, "table offsets must fit 16 bits");
 
@@ -225,15 +205,15 @@ struct GLetters {
   int lxR, lxL, lyR, lyL;
   // rows i0 .. i0+n-1 (n <= 4) of both extensions: table row offsets of this lane's copy
   template <int n>
-  __device__ __forceinline__ void xrows(int i0, uint32_t copy4, uint32_t (&xbR)[n], uint32_t (&xbL)[n]) const {
+  __device__ __forceinline__ void xrows(int i0, uint32_t (&xbR)[n], uint32_t (&xbL)[n]) const {
     const uint32_t r4 = load4(A, qa + i0 - 1);      // byte r: x_R row i0 + r
     const uint32_t l4 = load4(A, qa - i0 - 3);      // byte 3 - r: x_L row i0 + r
 #pragma unroll
     for (int r = 0; r < n; ++r) {
       const uint32_t sr = i0 + r <= lxR ? byte_of(r4, r) : kWall8;
       const uint32_t sl = i0 + r <= lxL ? byte_of(l4, 3 - r) : kWall8;
-      xbR[r] = (sr / kScale) * kRowBytes + copy4;
-      xbL[r] = (sl / kScale) * kRowBytes + copy4;
+      xbR[r] = (sr / kScale) * kRowBytes;
+      xbL[r] = (sl / kScale) * kRowBytes;
     }
   }
   // y indices k0 .. k0+3 of both extensions: packed table column offsets
@@ -250,7 +230,7 @@ struct GLetters {
   }
 };
 
-__device__ __forceinline__ void gapped_hit_f16(const GappedArgs& G, const uint32_t* tbl, uint32_t copy4,
+__device__ __forceinline__ void gapped_hit_f16(const GappedArgs& G, const uint32_t* tbl,
                                                const plast_hit_t* __restrict__ hits, int64_t h, int64_t n_hits,
                                                int32_t* __restrict__ gscore, uint8_t* __restrict__ pass) {
   const bool live = h < n_hits;
@@ -300,7 +280,7 @@ __device__ __forceinline__ void gapped_hit_f16(const GappedArgs& G, const uint32
       if (4 * g + t < kFY) Y[4 * g + t] = y4[t];
   }
   uint32_t xbR[kFBlock], xbL[kFBlock];
-  L.xrows<kFBlock>(1, copy4, xbR, xbL);
+  L.xrows<kFBlock>(1, xbR, xbL);
   gh2 best = {(_Float16)0, (_Float16)0};
   const char* tb = (const char*)tbl;
   for (int i0 = 1; __builtin_amdgcn_readfirstlane(__ballot(i0 <= rows) != 0); i0 += kFBlock) {
@@ -340,8 +320,8 @@ __device__ __forceinline__ void gapped_hit_f16(const GappedArgs& G, const uint32
       Y[kFY - kFBlock + t] = (sr / kScale) * kEntry | (((sl / kScale) * kEntry) << 16);
       const uint32_t xr = i1 + t <= L.lxR ? byte_of(nx4R, t) : kWall8;
       const uint32_t xl = i1 + t <= L.lxL ? byte_of(nx4L, 3 - t) : kWall8;
-      xbR[t] = (xr / kScale) * kRowBytes + copy4;
-      xbL[t] = (xl / kScale) * kRowBytes + copy4;
+      xbR[t] = (xr / kScale) * kRowBytes;
+      xbL[t] = (xl / kScale) * kRowBytes;
     }
   }
   if (live) {
@@ -351,35 +331,37 @@ __device__ __forceinline__ void gapped_hit_f16(const GappedArgs& G, const uint32
   }
 }
 
-#ifndef PLAST_GAP_WAVES
-#define PLAST_GAP_WAVES 2
-#endif
-__global__ __launch_bounds__(kFThreads) __attribute__((amdgpu_waves_per_eu(PLAST_GAP_WAVES)))
-void k_gapped_f16(GappedArgs G, const plast_hit_t* __restrict__ hits,
-                                                          int64_t n_hits, int32_t* __restrict__ gscore,
-                                                          uint8_t* __restrict__ pass) {
+template <int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2)))
+void k_gapped_f16(GappedArgs G, const plast_hit_t* __restrict__ hits, int64_t n_hits,
+                  const unsigned long long* __restrict__ n_dev, int32_t* __restrict__ gscore,
+                  uint8_t* __restrict__ pass) {
   __shared__ uint32_t tbl[kTblDwords];  // filled once per workgroup
-  if constexpr (kCopies == 0) {
-    for (int i = threadIdx.x; i < kTblDwords; i += kFThreads) {
-      const uint32_t lo = G.tbl16[2 * i], hi = 2 * i + 1 < kNLet * kNLet ? G.tbl16[2 * i + 1] : 0;
-      tbl[i] = lo | (hi << 16);
-    }
-  } else {
-    for (int i = threadIdx.x; i < kTblDwords; i += kFThreads) tbl[i] = G.tbl16[i / kCopies];
+  for (int i = threadIdx.x; i < kTblDwords; i += NT) {
+    const uint32_t lo = G.tbl16[2 * i], hi = 2 * i + 1 < kNLet * kNLet ? G.tbl16[2 * i + 1] : 0;
+    tbl[i] = lo | (hi << 16);
   }
+  if (n_dev) n_hits = min(n_hits, (int64_t)*n_dev);
   __syncthreads();
-  const uint32_t copy4 = kCopies > 1 ? (threadIdx.x & (kCopies - 1)) * 4 : 0;
-  // grid-stride over blocks of kFThreads hits; no barrier inside the loop
-  for (int64_t h = (int64_t)blockIdx.x * kFThreads + threadIdx.x; h - threadIdx.x < n_hits;
-       h += (int64_t)gridDim.x * kFThreads)
-    gapped_hit_f16(G, tbl, copy4, hits, h, n_hits, gscore, pass);
+  // grid-stride over blocks of NT hits; no barrier inside the loop
+  for (int64_t h = (int64_t)blockIdx.x * NT + threadIdx.x; h - threadIdx.x < n_hits; h += (int64_t)gridDim.x * NT)
+    gapped_hit_f16(G, tbl, hits, h, n_hits, gscore, pass);
 }
 
+template <int NT>
+int launch_fast(const GappedArgs& G, const plast_hit_t* d_hits, int64_t n_hits, const unsigned long long* d_n,
+                int32_t* d_gscore, uint8_t* d_pass, hipStream_t stream) {
+  const int64_t grid = (n_hits + NT - 1) / NT;
+  hipLaunchKernelGGL(k_gapped_f16<NT>, dim3((unsigned)grid), dim3(NT), 0, stream, G, d_hits, n_hits, d_n, d_gscore,
+                     d_pass);
+  return PLAST_OK;
+}
 
 }  // namespace
 
 int gapped_filter_impl(const plast_index_t* a, const plast_index_t* b, const plast_hit_t* d_hits, int64_t n_hits,
-                       const plast_gapped_params_t* g, int32_t* d_gscore, uint8_t* d_pass, hipStream_t stream) {
+                       const unsigned long long* d_n, const plast_gapped_params_t* g, int32_t* d_gscore,
+                       uint8_t* d_pass, hipStream_t stream) {
   GappedArgs G;
   G.a_scan = a->scan_codes;
   G.a_seq_start = a->seq_start;
@@ -413,33 +395,25 @@ int gapped_filter_impl(const plast_index_t* a, const plast_index_t* b, const pla
   // integers of that range are exact in binary16 when the bound stays below 2048.
   const bool fast = g->band == kGMaxBand && g->window <= kGMaxWin &&
                     64 * maxabs + 3 * (g->gap_open + g->gap_extend) + 130 * g->gap_extend <= 2000;
+  const int threads = g->tuning ? g->tuning->gapped_threads : 256;
+  if (n_hits <= 0) return PLAST_OK;
   timing_mark(kStageGapped, false, stream);
   if (fast) {
-    static int resident = 0;  // workgroups that fit the device at once
-    if (!resident) {
-      int dev = 0, cus = 0, per = 0;
-      PLAST_HIP(hipGetDevice(&dev));
-      PLAST_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-      PLAST_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_gapped_f16, kFThreads, 0));
-      resident = cus * (per > 0 ? per : 1);
-    }
-    const int64_t need = (n_hits + kFThreads - 1) / kFThreads;
-    const int64_t grid = PLAST_GAP_PERSIST ? (need < resident ? need : resident) : need;
-    if (getenv("PLAST_DEBUG_OCCUPANCY"))
-      fprintf(stderr, "k_gapped_f16: copies %d threads %d resident %d grid %lld\n", kCopies, kFThreads, resident,
-              (long long)grid);
-    hipLaunchKernelGGL(k_gapped_f16, dim3((unsigned)grid), dim3(kFThreads), 0, stream, G, d_hits, n_hits, d_gscore,
-                       d_pass);
-    timing_mark(kStageGapped, true, stream);
-    PLAST_HIP(hipGetLastError());
-    return PLAST_OK;
+    if (threads == 128)
+      launch_fast<128>(G, d_hits, n_hits, d_n, d_gscore, d_pass, stream);
+    else if (threads == 512)
+      launch_fast<512>(G, d_hits, n_hits, d_n, d_gscore, d_pass, stream);
+    else
+      launch_fast<256>(G, d_hits, n_hits, d_n, d_gscore, d_pass, stream);
+  } else {
+    unsigned blocks = (unsigned)((n_hits + kGThreads - 1) / kGThreads);
+    if (g->band == kGMaxBand)
+      hipLaunchKernelGGL(k_gapped<kGMaxBand>, dim3(blocks), dim3(kGThreads), 0, stream, G, d_hits, n_hits, d_n,
+                         d_gscore, d_pass);
+    else
+      hipLaunchKernelGGL(k_gapped<-1>, dim3(blocks), dim3(kGThreads), 0, stream, G, d_hits, n_hits, d_n, d_gscore,
+                         d_pass);
   }
-  unsigned blocks = (unsigned)((n_hits + kGThreads - 1) / kGThreads);
-  if (g->band == kGMaxBand)
-    hipLaunchKernelGGL(k_gapped<kGMaxBand>, dim3(blocks), dim3(kGThreads), 0, stream, G, d_hits, n_hits, d_gscore,
-                       d_pass);
-  else
-    hipLaunchKernelGGL(k_gapped<-1>, dim3(blocks), dim3(kGThreads), 0, stream, G, d_hits, n_hits, d_gscore, d_pass);
   timing_mark(kStageGapped, true, stream);
   PLAST_HIP(hipGetLastError());
   return PLAST_OK;

@@ -58,7 +58,7 @@ __global__ void k_codes_check(const uint8_t* __restrict__ codes, const int64_t* 
                               int64_t scan_len, int32_t* __restrict__ err) {
   int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
   int lane = lane_id();
-  if (w > n_seqs) return;
+  if (w > n_seqs || (*err & 1)) return;  // no walk over a bad layout
   bool bad = false;
   if (w == 0) {
     for (int64_t p = lane; p < kPadLen; p += 64) {
@@ -133,6 +133,10 @@ __global__ __launch_bounds__(kChunkWave) void k_index_scatter(const uint8_t* __r
     if (key >= 0 && lane == 63 - __clzll(peers)) cur[key] += __popcll(peers);
     s_cur = __shfl(s, 63);
   }
+}
+
+__global__ void k_clear2(int32_t* __restrict__ p) {
+  if (threadIdx.x < 2) p[threadIdx.x] = 0;
 }
 
 __global__ void k_key_off(const int32_t* __restrict__ offs, int32_t nchunks, const int32_t* __restrict__ total,
@@ -270,8 +274,8 @@ size_t index_ws_bytes(int64_t n_padded) {
   return 256 + align_up(sizeof(int32_t) * (size_t)n, 256) + scan_tmp_bytes(n);
 }
 
-int build_index_impl(const uint8_t* d_codes, const int64_t* d_seq_start, int32_t n_seqs, int64_t n_padded,
-                     void* d_index, void* d_ws, plast_index_t* out, hipStream_t stream) {
+int index_enqueue(const uint8_t* d_codes, const int64_t* d_seq_start, int32_t n_seqs, int64_t n_padded,
+                  void* d_index, void* d_ws, int32_t* d_err, plast_index_t* out, hipStream_t stream) {
   IndexLayout L = index_layout(n_padded);
   IndexChunks C = index_chunks(n_padded);
   uint8_t* base = (uint8_t*)d_index;
@@ -282,25 +286,22 @@ int build_index_impl(const uint8_t* d_codes, const int64_t* d_seq_start, int32_t
   int64_t scan_len = (int64_t)(L.total - L.scan);
 
   uint8_t* ws = (uint8_t*)d_ws;
-  int32_t* err = (int32_t*)ws;          // [0] error bits, [1] word total
-  int32_t* total = err + 1;
+  int32_t* total = d_err + 1;
   int64_t ncount = (int64_t)kNKeys * C.nchunks;
   int32_t* counts = (int32_t*)(ws + 256);
   void* tmp = ws + 256 + align_up(sizeof(int32_t) * (size_t)ncount, 256);
 
-  PLAST_HIP(hipMemsetAsync(err, 0, 2 * sizeof(int32_t), stream));
-  hipLaunchKernelGGL(k_layout_check, dim3((unsigned)((n_seqs + 1 + 255) / 256)), dim3(256), 0, stream, d_seq_start,
-                     n_seqs, n_padded, err);
-  int32_t h_err[2] = {0, 0};
-  PLAST_HIP(hipMemcpyAsync(h_err, err, sizeof(h_err), hipMemcpyDeviceToHost, stream));
-  PLAST_HIP(hipStreamSynchronize(stream));
-  if (h_err[0] & 1) return set_error(PLAST_E_LAYOUT, "seq_start does not describe the padded layout");
-
   SeedClasses sc = seed_classes();
   timing_mark(kStageIndex, false, stream);
+  // a fill kernel rather than a memset node, so that the sequence can be captured in a graph
+  hipLaunchKernelGGL(k_clear2, dim3(1), dim3(64), 0, stream, d_err);
+  hipLaunchKernelGGL(k_layout_check, dim3((unsigned)((n_seqs + 1 + 255) / 256)), dim3(256), 0, stream, d_seq_start,
+                     n_seqs, n_padded, d_err);
   int64_t waves = (int64_t)n_seqs + 1;
   hipLaunchKernelGGL(k_codes_check, dim3((unsigned)((waves * 64 + 255) / 256)), dim3(256), 0, stream, d_codes,
-                     d_seq_start, n_seqs, n_padded, scan, scan_len, err);
+                     d_seq_start, n_seqs, n_padded, scan, scan_len, d_err);
+  // Counting and scattering read seq_start only as bounds of a search over
+  // [0, n_seqs), so they stay in bounds after a layout error.
   hipLaunchKernelGGL(k_index_count, dim3((unsigned)C.nchunks), dim3(kChunkWave), 0, stream, d_codes, n_padded,
                      C.chunk, C.nchunks, sc, counts);
   exclusive_scan_i32(counts, ncount, total, tmp, stream);
@@ -310,9 +311,6 @@ int build_index_impl(const uint8_t* d_codes, const int64_t* d_seq_start, int32_t
                      C.nchunks, (const int32_t*)total, key_off);
   timing_mark(kStageIndex, true, stream);
   PLAST_HIP(hipGetLastError());
-  PLAST_HIP(hipMemcpyAsync(h_err, err, sizeof(h_err), hipMemcpyDeviceToHost, stream));
-  PLAST_HIP(hipStreamSynchronize(stream));
-  if (h_err[0] & 2) return set_error(PLAST_E_ALPHABET, "a residue code is > 19 or a separator code is not 20");
 
   out->codes = d_codes;
   out->seq_start = d_seq_start;
@@ -322,7 +320,23 @@ int build_index_impl(const uint8_t* d_codes, const int64_t* d_seq_start, int32_t
   out->occ = occ;
   out->occ_seq = occ_seq;
   out->scan_codes = scan;
-  out->n_words = h_err[1];
+  out->n_words = -1;
+  return PLAST_OK;
+}
+
+int build_index_impl(const uint8_t* d_codes, const int64_t* d_seq_start, int32_t n_seqs, int64_t n_padded,
+                     void* d_index, void* d_ws, plast_index_t* out, hipStream_t stream) {
+  int32_t* err = (int32_t*)d_ws;  // [0] error bits, [1] word total
+  plast_index_t view;
+  int rc = index_enqueue(d_codes, d_seq_start, n_seqs, n_padded, d_index, d_ws, err, &view, stream);
+  if (rc != PLAST_OK) return rc;
+  int32_t h_err[2] = {0, 0};
+  PLAST_HIP(hipMemcpyAsync(h_err, err, sizeof(h_err), hipMemcpyDeviceToHost, stream));
+  PLAST_HIP(hipStreamSynchronize(stream));
+  if (h_err[0] & 1) return set_error(PLAST_E_LAYOUT, "seq_start does not describe the padded layout");
+  if (h_err[0] & 2) return set_error(PLAST_E_ALPHABET, "a residue code is > 19 or a separator code is not 20");
+  view.n_words = h_err[1];
+  *out = view;
   return PLAST_OK;
 }
 

@@ -74,6 +74,12 @@ struct IndexChunks {
 IndexChunks index_chunks(int64_t n_padded);
 size_t index_ws_bytes(int64_t n_padded);
 
+// Enqueues the whole build (no host synchronisation).  d_err[0] receives error
+// bits (1: layout, 2: alphabet), d_err[1] the number of words.  After a layout
+// error the kernels that would follow seq_start do nothing.  *out is filled
+// except n_words (-1).
+int index_enqueue(const uint8_t* d_codes, const int64_t* d_seq_start, int32_t n_seqs, int64_t n_padded,
+                  void* d_index, void* d_ws, int32_t* d_err, plast_index_t* out, hipStream_t stream);
 int build_index_impl(const uint8_t* d_codes, const int64_t* d_seq_start, int32_t n_seqs, int64_t n_padded,
                      void* d_index, void* d_ws, plast_index_t* out, hipStream_t stream);
 
@@ -86,26 +92,77 @@ void exclusive_scan_i32(int32_t* d_data, int64_t n, int32_t* d_total, void* d_tm
 constexpr int kTileRows = 32;           // bank-a occurrences per work item (profile rows)
 constexpr int kRowGroups = kTileRows / 4;
 constexpr int kThreads = 512;           // threads per workgroup (8 wavefronts share one profile)
-constexpr int kColsPerLane = 8;         // bank-b occurrences per lane per item
-constexpr int kTileCols = kThreads * kColsPerLane;
+constexpr int kMaxColsPerLane = 32;     // bank-b occurrences per lane per item, at most
+constexpr int kMaxItemCols = kThreads * kMaxColsPerLane;  // 16384
+constexpr int kClasses = PLAST_TUNE_CLASSES;
+constexpr int kMaxQueues = 8;           // one per XCD
+
+void tuning_default(plast_tuning_t* t);
+int check_tuning(const plast_tuning_t* t);  // PLAST_OK or PLAST_E_ARG (with detail)
 
 struct WorkItem {
   int32_t key, row0, col0, ncols;
 };
 
-struct UngappedPlan {
-  int64_t n_ext;
-  int64_t n_items;
-};
-
 int ungapped_extend_impl(const plast_index_t* a, const plast_index_t* b, const plast_ungapped_params_t* p,
                          int32_t mode, void* d_ws, size_t ws_bytes, plast_hit_t* d_hits, int64_t capacity,
                          int64_t* h_n_hits, int64_t* h_n_ext, hipStream_t stream);
-int ungapped_ws_bytes_impl(const plast_index_t* a, const plast_index_t* b, int32_t mode, size_t* bytes,
-                           int64_t* n_ext, hipStream_t stream);
+int ungapped_ws_bytes_impl(const plast_index_t* a, const plast_index_t* b, int32_t mode, const plast_tuning_t& t,
+                           size_t* bytes, int64_t* n_ext, int64_t* n_items, hipStream_t stream);
+
+// Bytes of the BATCHED workspace before the work list, and the list length
+// that a workspace of ws_bytes holds.
+size_t ungapped_ws_fixed_bytes();
+int64_t ungapped_ws_max_items(size_t ws_bytes);
+// Work-list length for these key tables (host copies, kNKeys + 1 each) under
+// tuning t, restricted to the classes in class_mask; *n_ext likewise.
+int64_t plan_items_host(const int64_t* ha, const int64_t* hb, const plast_tuning_t& t, uint32_t class_mask,
+                        int64_t* n_ext);
+int read_key_offsets(const plast_index_t* x, int64_t* h, hipStream_t s);  // h: kNKeys + 1
+
+// Enqueues the BATCHED schedule (counter reset, work list, persistent kernel)
+// with no host synchronisation.  Only keys of the classes in class_mask get
+// items.  err_a / err_b (may be null) are index error words: if either is
+// non-zero on the device the list is left empty.  ev0 / ev1 (may be null) are
+// recorded around the persistent kernel.
+int ungapped_enqueue_batched(const plast_index_t* a, const plast_index_t* b, const plast_ungapped_params_t* p,
+                             const plast_tuning_t& t, uint32_t class_mask, void* d_ws, size_t ws_bytes,
+                             plast_hit_t* d_hits, int64_t capacity, const int32_t* err_a, const int32_t* err_b,
+                             hipEvent_t ev0, hipEvent_t ev1, hipStream_t stream);
+// Device counters of the last BATCHED run at the start of d_ws: hits, pairs,
+// work-list length (the int32 scan total, and the same count summed in 64 bits
+// to catch a list too long for int32), overflow flag (1: list longer than the
+// workspace holds, 2: an index error).
+struct UngappedCounters {
+  unsigned long long n_hits, n_ext;
+  int32_t n_items, overflow;
+  unsigned long long n_items64;
+};
+const void* ungapped_counters_dev(const void* d_ws);
+unsigned long long* ungapped_n_hits_dev(void* d_ws);
 
 // ---------------------------------------------------------------- gapped
+// d_n (may be null): device hit count; when given, min(*d_n, n_hits) records
+// are scored and n_hits is only the bound the grid is sized for.
 int gapped_filter_impl(const plast_index_t* a, const plast_index_t* b, const plast_hit_t* d_hits, int64_t n_hits,
-                       const plast_gapped_params_t* g, int32_t* d_gscore, uint8_t* d_pass, hipStream_t stream);
+                       const unsigned long long* d_n, const plast_gapped_params_t* g, int32_t* d_gscore,
+                       uint8_t* d_pass, hipStream_t stream);
+
+// ---------------------------------------------------------------- autotuner, graph pipeline
+int autotune_impl(const plast_index_t* a, const plast_index_t* b, const plast_ungapped_params_t* p,
+                  const plast_gapped_params_t* g, int32_t reps, void* d_ws, size_t ws_bytes, plast_hit_t* d_hits,
+                  int64_t capacity, int32_t* d_gscore, uint8_t* d_pass, plast_tuning_t* out,
+                  plast_tune_report_t* report, hipStream_t stream);
+// Occupancy queries of the persistent kernels, made once before any graph capture.
+int ungapped_prepare();
+
+size_t pipeline_ws_bytes(const plast_bank_t* a, const plast_bank_t* b, int64_t max_items);
+int pipeline_create_impl(const plast_bank_t* a, const plast_bank_t* b, const plast_ungapped_params_t* p,
+                         const plast_gapped_params_t* g, int64_t max_items, void* d_ws, plast_hit_t* d_hits,
+                         int64_t capacity, int32_t* d_gscore, uint8_t* d_pass, plast_pipeline_t** out);
+int pipeline_launch_impl(plast_pipeline_t* pl, hipStream_t s);
+int pipeline_result_impl(plast_pipeline_t* pl, plast_pipeline_result_t* out, hipStream_t s);
+int pipeline_index_impl(const plast_pipeline_t* pl, int32_t which, plast_index_t* out);
+int pipeline_destroy_impl(plast_pipeline_t* pl);
 
 }  // namespace plast

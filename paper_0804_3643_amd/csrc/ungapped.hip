@@ -1,8 +1,8 @@
 // Stage 2, ungapped extension (Sec. 3.2 generic algorithm, Sec. 3.3.3), with
 // hit compaction and two schedules over the same tile routine.
 //
-// Tile routine.  A work item is (key, 32 bank-a occurrences, up to 4096 bank-b
-// occurrences).  The 32 rows become a profile in LDS: for scan step t (t < 24:
+// Tile routine.  A work item is (key, 32 bank-a occurrences, up to 16384 bank-b
+// occurrences; the width is set per size class of the key).  The 32 rows become a profile in LDS: for scan step t (t < 24:
 // letter p+t; t >= 24: letter p-(t-23)) and bank-b letter c, an 8-byte entry
 // holds the substitution scores of four rows (59 KB for 32 rows x 44 steps x 21
 // letters).  Each lane owns one bank-b occurrence at a time: its 44-letter
@@ -30,10 +30,15 @@
 // staging area writes directly).  Order of hits is unspecified.
 //
 // Schedules.  PLAIN: one grid per key with candidate pairs, in key order, one
-// item per workgroup (the paper's one-launch-per-seed GPU offload, Sec. 5.2.1,
-// without its per-seed copies).  BATCHED: a device work list over all keys and
-// one persistent kernel whose workgroups pop items from an atomic counter (the
-// dynamic seed distribution of the multicore version, Sec. 5.1).
+// item of 4096 columns per workgroup (the paper's one-launch-per-seed GPU
+// offload, Sec. 5.2.1, without its per-seed copies).  BATCHED: a device work
+// list over all keys, item widths chosen per size class of n2, and one
+// persistent kernel whose workgroups pop items from atomic counters (the
+// dynamic seed distribution of the multicore version, Sec. 5.1).  The list is
+// in key order with the row tiles of one column range next to each other, so
+// consecutive items read the same bank-b windows; with one queue per XCD each
+// XCD works through its own contiguous part of the list under its own L2, and
+// a workgroup whose queue is empty takes items from the others.
 #include <stddef.h>
 #include <string.h>
 
@@ -399,7 +404,7 @@ __device__ void run_item(const UngappedArgs& A, const WorkItem it, Smem& S) {
   // flight while the current column is scanned.
   const int col_end = it.col0 + it.ncols;
   int nk = 0;  // column steps of this wavefront
-  while (nk < kColsPerLane && it.col0 + wid * 64 + kThreads * nk < col_end) ++nk;
+  while (nk < kMaxColsPerLane && it.col0 + wid * 64 + kThreads * nk < col_end) ++nk;
   nk = __builtin_amdgcn_readfirstlane(nk);
   auto occ_index = [&](int k) {
     const int j = it.col0 + tid + kThreads * k;
@@ -444,6 +449,8 @@ __device__ void run_item(const UngappedArgs& A, const WorkItem it, Smem& S) {
   flush_hits(A, S);
 }
 
+constexpr int kPlainCols = 4096;  // item width of the PLAIN schedule
+
 template <bool F16>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
 void k_ungapped_plain(UngappedArgs A, int32_t key, int32_t n_row_tiles, int32_t n2) {
@@ -453,64 +460,103 @@ void k_ungapped_plain(UngappedArgs A, int32_t key, int32_t n_row_tiles, int32_t 
   WorkItem it;
   it.key = key;
   it.row0 = (int32_t)(blockIdx.x % n_row_tiles) * kTileRows;
-  it.col0 = (int32_t)(blockIdx.x / n_row_tiles) * kTileCols;
-  it.ncols = min(kTileCols, n2 - it.col0);
+  it.col0 = (int32_t)(blockIdx.x / n_row_tiles) * kPlainCols;
+  it.ncols = min(kPlainCols, n2 - it.col0);
   run_item<F16>(A, it, S);
 }
 
+// Workspace header of the BATCHED schedule: UngappedCounters at 0, queue
+// counters at 32 (kMaxQueues int32), both cleared by the first kernel.
+constexpr int kCtrOffset = 32;
+constexpr int kHeaderDwords = 16;
+static_assert(sizeof(UngappedCounters) <= kCtrOffset, "counter header");
+static_assert(kCtrOffset + 4 * kMaxQueues <= 4 * kHeaderDwords, "queue counters");
+
 template <bool F16>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
-void k_ungapped_persistent(UngappedArgs A, const WorkItem* __restrict__ items, const int32_t* __restrict__ n_items_p,
-                           const int32_t* __restrict__ overflow, int32_t* __restrict__ ctr) {
+void k_ungapped_persistent(UngappedArgs A, const WorkItem* __restrict__ items,
+                           const UngappedCounters* __restrict__ cnt, int32_t* __restrict__ ctr, int32_t n_queues) {
   __shared__ Smem S;
   smem_init<F16>(A, S);
-  const int n_items = __builtin_amdgcn_readfirstlane(*overflow ? 0 : *n_items_p);
-  // The item index is read back as a scalar so that the loop exit is uniform:
-  // with a per-lane exit the compiler may let lanes other than thread 0 reach
-  // the barrier below before thread 0 has fetched the next item.
-  for (;;) {
-    if (threadIdx.x == 0) S.item = atomicAdd(ctr, 1);
-    __syncthreads();
-    const int i = __builtin_amdgcn_readfirstlane(S.item);
-    if (i >= n_items) break;
-    run_item<F16>(A, items[i], S);
+  const int n_items = __builtin_amdgcn_readfirstlane(cnt->overflow ? 0 : cnt->n_items);
+  const int q0 = (int)(blockIdx.x % (unsigned)n_queues);  // workgroups are dealt to XCDs round robin
+  for (int j = 0; j < n_queues; ++j) {
+    const int q = (q0 + j) % n_queues;
+    const int beg = (int)((int64_t)n_items * q / n_queues), end = (int)((int64_t)n_items * (q + 1) / n_queues);
+    // The item index is read back as a scalar so that the loop exit is
+    // uniform: with a per-lane exit the compiler may let lanes other than
+    // thread 0 reach a barrier before thread 0 has fetched the next item.  The
+    // second barrier keeps thread 0 from overwriting S.item (next item or next
+    // queue) before every wavefront has read it.
+    for (;;) {
+      if (threadIdx.x == 0) S.item = atomicAdd(&ctr[q], 1);
+      __syncthreads();
+      const int i = __builtin_amdgcn_readfirstlane(S.item) + beg;
+      __syncthreads();
+      if (i >= end) break;
+      run_item<F16>(A, items[i], S);
+    }
   }
 }
 
 // ---------------------------------------------------------------- planning
-__device__ __forceinline__ int64_t items_of(int64_t n1, int64_t n2) {
+// Size classes by n2 and the item width of each, for the planning kernels.
+struct PlanShape {
+  int32_t min_n2[kClasses];
+  int32_t cols[kClasses];
+  uint32_t mask;  // classes that get items
+};
+
+__host__ __device__ __forceinline__ int64_t items_of(const PlanShape& P, int64_t n1, int64_t n2, int32_t* width) {
   if (n1 <= 0 || n2 <= 0) return 0;
-  return ((n1 + kTileRows - 1) / kTileRows) * ((n2 + kTileCols - 1) / kTileCols);
+  int c = 0;
+#pragma unroll
+  for (int i = 1; i < kClasses; ++i)
+    if (n2 >= P.min_n2[i]) c = i;
+  if (!((P.mask >> c) & 1u)) return 0;
+  *width = P.cols[c];
+  return ((n1 + kTileRows - 1) / kTileRows) * ((n2 + P.cols[c] - 1) / P.cols[c]);
 }
 
-__global__ void k_plan_count(const int64_t* __restrict__ a_off, const int64_t* __restrict__ b_off,
-                             int32_t* __restrict__ cnt, unsigned long long* __restrict__ n_ext) {
+__global__ void k_plan_count(const int64_t* __restrict__ a_off, const int64_t* __restrict__ b_off, PlanShape P,
+                             int32_t* __restrict__ keycnt, UngappedCounters* __restrict__ cnt) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= kNKeys) return;
   int64_t n1 = a_off[k + 1] - a_off[k], n2 = b_off[k + 1] - b_off[k];
-  cnt[k] = (int32_t)items_of(n1, n2);
-  if (n1 > 0 && n2 > 0) atomicAdd(n_ext, (unsigned long long)(n1 * n2));
+  int32_t w = 0;
+  const int64_t c = items_of(P, n1, n2, &w);
+  keycnt[k] = (int32_t)min(c, (int64_t)INT32_MAX);
+  if (c > 0) {
+    atomicAdd(&cnt->n_ext, (unsigned long long)(n1 * n2));
+    atomicAdd(&cnt->n_items64, (unsigned long long)c);
+  }
 }
 
-__global__ void k_plan_emit(const int64_t* __restrict__ a_off, const int64_t* __restrict__ b_off,
-                            const int32_t* __restrict__ item_off, const int32_t* __restrict__ total,
-                            int64_t max_items, WorkItem* __restrict__ items, int32_t* __restrict__ overflow) {
+__global__ void k_plan_emit(const int64_t* __restrict__ a_off, const int64_t* __restrict__ b_off, PlanShape P,
+                            const int32_t* __restrict__ item_off, UngappedCounters* __restrict__ cnt,
+                            int64_t max_items, const int32_t* __restrict__ err_a, const int32_t* __restrict__ err_b,
+                            WorkItem* __restrict__ items) {
   const int k = blockIdx.x;
-  if ((int64_t)*total > max_items) {
-    if (k == 0 && threadIdx.x == 0) *overflow = 1;
+  const unsigned long long n = cnt->n_items64;
+  const int flag = (n > (unsigned long long)max_items || n > (unsigned long long)INT32_MAX)
+                       ? 1
+                       : (((err_a && *err_a) || (err_b && *err_b)) ? 2 : 0);
+  if (flag) {
+    if (k == 0 && threadIdx.x == 0) cnt->overflow = flag;
     return;
   }
   int64_t n1 = a_off[k + 1] - a_off[k], n2 = b_off[k + 1] - b_off[k];
-  int cnt = (int)items_of(n1, n2);
-  if (cnt == 0) return;
-  int nrt = (int)((n1 + kTileRows - 1) / kTileRows);
-  for (int idx = threadIdx.x; idx < cnt; idx += blockDim.x) {
-    int rt = idx % nrt, ct = idx / nrt;
+  int32_t width = 0;
+  const int ni = (int)items_of(P, n1, n2, &width);
+  if (ni == 0) return;
+  const int nrt = (int)((n1 + kTileRows - 1) / kTileRows);
+  for (int idx = threadIdx.x; idx < ni; idx += blockDim.x) {
+    const int rt = idx % nrt, ct = idx / nrt;  // row tiles of one column range are adjacent
     WorkItem w;
     w.key = k;
     w.row0 = rt * kTileRows;
-    w.col0 = ct * kTileCols;
-    w.ncols = (int)min((int64_t)kTileCols, n2 - (int64_t)w.col0);
+    w.col0 = ct * width;
+    w.ncols = (int)min((int64_t)width, n2 - (int64_t)w.col0);
     items[item_off[k] + idx] = w;
   }
 }
@@ -521,54 +567,36 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
 }
 
 // ---------------------------------------------------------------- workspace
-// [0, 256): counters  n_hits u64 @0, n_ext u64 @8, item counter i32 @16,
-//           item total i32 @20, overflow flag i32 @24
+// [0, 256): UngappedCounters, queue counters
 // [256, ...): per-key item counts/offsets (int32[kNKeys]), scan scratch, items
 struct UngappedWs {
-  unsigned long long* n_hits;
-  unsigned long long* n_ext;
+  UngappedCounters* cnt;
   int32_t* ctr;
-  int32_t* total;
-  int32_t* overflow;
-  int32_t* cnt;
+  int32_t* keycnt;
   void* scan_tmp;
   WorkItem* items;
   int64_t max_items;
 };
 
-size_t ws_fixed_bytes() { return 256 + align_up(sizeof(int32_t) * kNKeys, 256) + scan_tmp_bytes(kNKeys); }
-
 UngappedWs carve(void* d_ws, size_t ws_bytes) {
   UngappedWs W;
   uint8_t* p = (uint8_t*)d_ws;
-  W.n_hits = (unsigned long long*)p;
-  W.n_ext = (unsigned long long*)(p + 8);
-  W.ctr = (int32_t*)(p + 16);
-  W.total = (int32_t*)(p + 20);
-  W.overflow = (int32_t*)(p + 24);
-  W.cnt = (int32_t*)(p + 256);
+  W.cnt = (UngappedCounters*)p;
+  W.ctr = (int32_t*)(p + kCtrOffset);
+  W.keycnt = (int32_t*)(p + 256);
   W.scan_tmp = p + 256 + align_up(sizeof(int32_t) * kNKeys, 256);
-  W.items = (WorkItem*)(p + ws_fixed_bytes());
-  W.max_items = ws_bytes > ws_fixed_bytes() ? (int64_t)((ws_bytes - ws_fixed_bytes()) / sizeof(WorkItem)) : 0;
+  W.items = (WorkItem*)(p + ungapped_ws_fixed_bytes());
+  W.max_items = ungapped_ws_max_items(ws_bytes);
   return W;
 }
 
-int read_key_offsets(const plast_index_t* x, std::vector<int64_t>& h, hipStream_t s) {
-  h.resize(kNKeys + 1);
-  PLAST_HIP(hipMemcpyAsync(h.data(), x->key_off, sizeof(int64_t) * (kNKeys + 1), hipMemcpyDeviceToHost, s));
-  PLAST_HIP(hipStreamSynchronize(s));
-  return PLAST_OK;
-}
-
-UngappedPlan host_plan(const std::vector<int64_t>& ha, const std::vector<int64_t>& hb) {
-  UngappedPlan P{0, 0};
-  for (int k = 0; k < kNKeys; ++k) {
-    int64_t n1 = ha[k + 1] - ha[k], n2 = hb[k + 1] - hb[k];
-    if (n1 > 0 && n2 > 0) {
-      P.n_ext += n1 * n2;
-      P.n_items += ((n1 + kTileRows - 1) / kTileRows) * ((n2 + kTileCols - 1) / kTileCols);
-    }
+PlanShape shape_of(const plast_tuning_t& t, uint32_t mask) {
+  PlanShape P;
+  for (int c = 0; c < kClasses; ++c) {
+    P.min_n2[c] = t.class_min_n2[c];
+    P.cols[c] = t.item_cols[c];
   }
+  P.mask = mask;
   return P;
 }
 
@@ -623,15 +651,114 @@ int persistent_grid() {
 
 }  // namespace
 
-int ungapped_ws_bytes_impl(const plast_index_t* a, const plast_index_t* b, int32_t mode, size_t* bytes,
-                           int64_t* n_ext, hipStream_t stream) {
-  std::vector<int64_t> ha, hb;
+void tuning_default(plast_tuning_t* t) {
+  const int32_t lo[kClasses] = {1, 2048, 8192, 32768};
+  for (int c = 0; c < kClasses; ++c) {
+    t->class_min_n2[c] = lo[c];
+    t->item_cols[c] = 4096;
+  }
+  t->xcd_queues = 1;
+  t->gapped_threads = 256;
+}
+
+int check_tuning(const plast_tuning_t* t) {
+  if (t->class_min_n2[0] != 1) return set_error(PLAST_E_ARG, "tuning: class_min_n2[0] must be 1");
+  for (int c = 0; c < kClasses; ++c) {
+    if (c > 0 && t->class_min_n2[c] <= t->class_min_n2[c - 1])
+      return set_error(PLAST_E_ARG, "tuning: class_min_n2 must be strictly ascending");
+    const int w = t->item_cols[c];
+    if (w < kThreads || w > kMaxItemCols || w % kThreads)
+      return set_error(PLAST_E_ARG, "tuning: item_cols[%d]=%d not a multiple of %d in [%d, %d]", c, w, kThreads,
+                       kThreads, kMaxItemCols);
+  }
+  if (t->xcd_queues != 1 && t->xcd_queues != kMaxQueues)
+    return set_error(PLAST_E_ARG, "tuning: xcd_queues must be 1 or %d", kMaxQueues);
+  if (t->gapped_threads != 128 && t->gapped_threads != 256 && t->gapped_threads != 512)
+    return set_error(PLAST_E_ARG, "tuning: gapped_threads must be 128, 256 or 512");
+  return PLAST_OK;
+}
+
+int ungapped_prepare() {
+  return (persistent_grid<true>() > 0 && persistent_grid<false>() > 0)
+             ? PLAST_OK
+             : set_error(PLAST_E_HIP, "cannot query device occupancy");
+}
+
+size_t ungapped_ws_fixed_bytes() { return 256 + align_up(sizeof(int32_t) * kNKeys, 256) + scan_tmp_bytes(kNKeys); }
+
+int64_t ungapped_ws_max_items(size_t ws_bytes) {
+  const size_t f = ungapped_ws_fixed_bytes();
+  return ws_bytes > f ? (int64_t)((ws_bytes - f) / sizeof(WorkItem)) : 0;
+}
+
+const void* ungapped_counters_dev(const void* d_ws) { return d_ws; }
+unsigned long long* ungapped_n_hits_dev(void* d_ws) { return &((UngappedCounters*)d_ws)->n_hits; }
+
+int read_key_offsets(const plast_index_t* x, int64_t* h, hipStream_t s) {
+  PLAST_HIP(hipMemcpyAsync(h, x->key_off, sizeof(int64_t) * (kNKeys + 1), hipMemcpyDeviceToHost, s));
+  PLAST_HIP(hipStreamSynchronize(s));
+  return PLAST_OK;
+}
+
+int64_t plan_items_host(const int64_t* ha, const int64_t* hb, const plast_tuning_t& t, uint32_t class_mask,
+                        int64_t* n_ext) {
+  const PlanShape P = shape_of(t, class_mask);
+  int64_t items = 0, ext = 0;
+  for (int k = 0; k < kNKeys; ++k) {
+    const int64_t n1 = ha[k + 1] - ha[k], n2 = hb[k + 1] - hb[k];
+    int32_t w = 0;
+    const int64_t c = items_of(P, n1, n2, &w);
+    if (c > 0) ext += n1 * n2;
+    items += c;
+  }
+  if (n_ext) *n_ext = ext;
+  return items;
+}
+
+int ungapped_ws_bytes_impl(const plast_index_t* a, const plast_index_t* b, int32_t mode, const plast_tuning_t& t,
+                           size_t* bytes, int64_t* n_ext, int64_t* n_items, hipStream_t stream) {
+  std::vector<int64_t> ha(kNKeys + 1), hb(kNKeys + 1);
   int rc;
-  if ((rc = read_key_offsets(a, ha, stream)) || (rc = read_key_offsets(b, hb, stream))) return rc;
-  UngappedPlan P = host_plan(ha, hb);
-  if (n_ext) *n_ext = P.n_ext;
-  *bytes = mode == PLAST_BATCHED ? ws_fixed_bytes() + sizeof(WorkItem) * (size_t)P.n_items : 256;
-  if (P.n_items > INT32_MAX) return set_error(PLAST_E_ARG, "too many work items");
+  if ((rc = read_key_offsets(a, ha.data(), stream)) || (rc = read_key_offsets(b, hb.data(), stream))) return rc;
+  const int64_t items = plan_items_host(ha.data(), hb.data(), t, ~0u, n_ext);
+  if (n_items) *n_items = items;
+  *bytes = mode == PLAST_BATCHED ? ungapped_ws_fixed_bytes() + sizeof(WorkItem) * (size_t)items : 256;
+  if (items > INT32_MAX) return set_error(PLAST_E_ARG, "too many work items");
+  return PLAST_OK;
+}
+
+int ungapped_enqueue_batched(const plast_index_t* a, const plast_index_t* b, const plast_ungapped_params_t* p,
+                             const plast_tuning_t& t, uint32_t class_mask, void* d_ws, size_t ws_bytes,
+                             plast_hit_t* d_hits, int64_t capacity, const int32_t* err_a, const int32_t* err_b,
+                             hipEvent_t ev0, hipEvent_t ev1, hipStream_t stream) {
+  if (ws_bytes < ungapped_ws_fixed_bytes())
+    return set_error(PLAST_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, ungapped_ws_fixed_bytes());
+  UngappedWs W = carve(d_ws, ws_bytes);
+  UngappedArgs A;
+  const bool f16 = fill_args(A, a, b, p, d_hits, capacity, &W.cnt->n_hits);
+  const int grid = f16 ? persistent_grid<true>() : persistent_grid<false>();
+  if (grid <= 0) return set_error(PLAST_E_HIP, "cannot query device occupancy");
+  const PlanShape P = shape_of(t, class_mask);
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, stream, (uint32_t*)d_ws, (int64_t)kHeaderDwords, 0u);
+  timing_mark(kStagePlan, false, stream);
+  hipLaunchKernelGGL(k_plan_count, dim3((kNKeys + 255) / 256), dim3(256), 0, stream, a->key_off, b->key_off, P,
+                     W.keycnt, W.cnt);
+  exclusive_scan_i32(W.keycnt, kNKeys, &W.cnt->n_items, W.scan_tmp, stream);
+  hipLaunchKernelGGL(k_plan_emit, dim3(kNKeys), dim3(256), 0, stream, a->key_off, b->key_off, P,
+                     (const int32_t*)W.keycnt, W.cnt, W.max_items, err_a, err_b, W.items);
+  timing_mark(kStagePlan, true, stream);
+  timing_mark(kStageUngapped, false, stream);
+  if (ev0) PLAST_HIP(hipEventRecord(ev0, stream));
+  if (f16)
+    hipLaunchKernelGGL(k_ungapped_persistent<true>, dim3(grid), dim3(kThreads), 0, stream, A,
+                       (const WorkItem*)W.items, (const UngappedCounters*)W.cnt, W.ctr, (int32_t)t.xcd_queues);
+  else
+    hipLaunchKernelGGL(k_ungapped_persistent<false>, dim3(grid), dim3(kThreads), 0, stream, A,
+                       (const WorkItem*)W.items, (const UngappedCounters*)W.cnt, W.ctr, (int32_t)t.xcd_queues);
+  if (ev1) PLAST_HIP(hipEventRecord(ev1, stream));
+  timing_mark(kStageUngapped, true, stream);
+  timing_launches(1);
+  PLAST_HIP(hipGetLastError());
   return PLAST_OK;
 }
 
@@ -639,15 +766,19 @@ int ungapped_extend_impl(const plast_index_t* a, const plast_index_t* b, const p
                          int32_t mode, void* d_ws, size_t ws_bytes, plast_hit_t* d_hits, int64_t capacity,
                          int64_t* h_n_hits, int64_t* h_n_ext, hipStream_t stream) {
   if (ws_bytes < 256) return set_error(PLAST_E_WORKSPACE, "workspace smaller than 256 bytes");
-  UngappedWs W = carve(d_ws, ws_bytes);
-  UngappedArgs A;
-  const bool f16 = fill_args(A, a, b, p, d_hits, capacity, W.n_hits);
-  unsigned long long h_cnt[2] = {0, 0};
+  plast_tuning_t T;
+  if (p->tuning)
+    T = *p->tuning;
+  else
+    tuning_default(&T);
+  UngappedCounters c{0, 0, 0, 0, 0};
 
   if (mode == PLAST_PLAIN) {
-    std::vector<int64_t> ha, hb;
+    UngappedArgs A;
+    const bool f16 = fill_args(A, a, b, p, d_hits, capacity, &((UngappedCounters*)d_ws)->n_hits);
+    std::vector<int64_t> ha(kNKeys + 1), hb(kNKeys + 1);
     int rc;
-    if ((rc = read_key_offsets(a, ha, stream)) || (rc = read_key_offsets(b, hb, stream))) return rc;
+    if ((rc = read_key_offsets(a, ha.data(), stream)) || (rc = read_key_offsets(b, hb.data(), stream))) return rc;
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, stream, (uint32_t*)d_ws, (int64_t)8, 0u);
     int64_t n_ext = 0, launches = 0;
     timing_mark(kStageUngapped, false, stream);
@@ -655,7 +786,7 @@ int ungapped_extend_impl(const plast_index_t* a, const plast_index_t* b, const p
       int64_t n1 = ha[k + 1] - ha[k], n2 = hb[k + 1] - hb[k];
       if (n1 <= 0 || n2 <= 0) continue;
       n_ext += n1 * n2;
-      int64_t nrt = (n1 + kTileRows - 1) / kTileRows, nct = (n2 + kTileCols - 1) / kTileCols;
+      int64_t nrt = (n1 + kTileRows - 1) / kTileRows, nct = (n2 + kPlainCols - 1) / kPlainCols;
       if (f16)
         hipLaunchKernelGGL(k_ungapped_plain<true>, dim3((unsigned)(nrt * nct)), dim3(kThreads), 0, stream, A, k,
                            (int32_t)nrt, (int32_t)n2);
@@ -667,42 +798,21 @@ int ungapped_extend_impl(const plast_index_t* a, const plast_index_t* b, const p
     timing_mark(kStageUngapped, true, stream);
     timing_launches(launches);
     PLAST_HIP(hipGetLastError());
-    PLAST_HIP(hipMemcpyAsync(h_cnt, W.n_hits, sizeof(unsigned long long), hipMemcpyDeviceToHost, stream));
+    PLAST_HIP(hipMemcpyAsync(&c.n_hits, d_ws, sizeof(unsigned long long), hipMemcpyDeviceToHost, stream));
     PLAST_HIP(hipStreamSynchronize(stream));
-    h_cnt[1] = (unsigned long long)n_ext;
+    c.n_ext = (unsigned long long)n_ext;
   } else {
-    if (ws_bytes < ws_fixed_bytes())
-      return set_error(PLAST_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, ws_fixed_bytes());
-    int grid = f16 ? persistent_grid<true>() : persistent_grid<false>();
-    if (grid <= 0) return set_error(PLAST_E_HIP, "cannot query device occupancy");
-    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, stream, (uint32_t*)d_ws, (int64_t)8, 0u);
-    timing_mark(kStagePlan, false, stream);
-    hipLaunchKernelGGL(k_plan_count, dim3((kNKeys + 255) / 256), dim3(256), 0, stream, a->key_off, b->key_off,
-                       W.cnt, W.n_ext);
-    exclusive_scan_i32(W.cnt, kNKeys, W.total, W.scan_tmp, stream);
-    hipLaunchKernelGGL(k_plan_emit, dim3(kNKeys), dim3(256), 0, stream, a->key_off, b->key_off,
-                       (const int32_t*)W.cnt, (const int32_t*)W.total, W.max_items, W.items, W.overflow);
-    timing_mark(kStagePlan, true, stream);
-    timing_mark(kStageUngapped, false, stream);
-    if (f16)
-      hipLaunchKernelGGL(k_ungapped_persistent<true>, dim3(grid), dim3(kThreads), 0, stream, A,
-                         (const WorkItem*)W.items, (const int32_t*)W.total, (const int32_t*)W.overflow, W.ctr);
-    else
-      hipLaunchKernelGGL(k_ungapped_persistent<false>, dim3(grid), dim3(kThreads), 0, stream, A,
-                         (const WorkItem*)W.items, (const int32_t*)W.total, (const int32_t*)W.overflow, W.ctr);
-    timing_mark(kStageUngapped, true, stream);
-    timing_launches(1);
-    PLAST_HIP(hipGetLastError());
-    int32_t ovf = 0;
-    PLAST_HIP(hipMemcpyAsync(h_cnt, W.n_hits, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, stream));
-    PLAST_HIP(hipMemcpyAsync(&ovf, W.overflow, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+    int rc = ungapped_enqueue_batched(a, b, p, T, ~0u, d_ws, ws_bytes, d_hits, capacity, nullptr, nullptr, nullptr,
+                                      nullptr, stream);
+    if (rc != PLAST_OK) return rc;
+    PLAST_HIP(hipMemcpyAsync(&c, d_ws, sizeof(c), hipMemcpyDeviceToHost, stream));
     PLAST_HIP(hipStreamSynchronize(stream));
-    if (ovf) return set_error(PLAST_E_WORKSPACE, "workspace too small for the work list");
+    if (c.overflow) return set_error(PLAST_E_WORKSPACE, "workspace too small for the work list");
   }
-  *h_n_hits = (int64_t)h_cnt[0];
-  if (h_n_ext) *h_n_ext = (int64_t)h_cnt[1];
-  if ((int64_t)h_cnt[0] > capacity)
-    return set_error(PLAST_E_CAPACITY, "%lld hits > capacity %lld", (long long)h_cnt[0], (long long)capacity);
+  *h_n_hits = (int64_t)c.n_hits;
+  if (h_n_ext) *h_n_ext = (int64_t)c.n_ext;
+  if ((int64_t)c.n_hits > capacity)
+    return set_error(PLAST_E_CAPACITY, "%lld hits > capacity %lld", (long long)c.n_hits, (long long)capacity);
   return PLAST_OK;
 }
 

@@ -303,6 +303,12 @@ def test_config1_full_size_plain_batched_and_sampled_keys(B):
     kp, sp = _sorted_by_pair(hp)
     assert np.array_equal(kb, kp) and np.array_equal(sb, sp)
     assert len(np.unique(kb)) == len(kb)          # no pair reported twice
+    _say("cfg1 batched, other launch shapes")
+    for t in ({"item_cols": [1024, 2048, 8192, 16384], "xcd_queues": 8}, {"item_cols": [16384] * 4}):
+        ht, n_ext_t = B.ungapped_extend(ia, ib, params.S1, mode="batched", tuning=t)
+        kt, st_ = _sorted_by_pair(ht.cpu().numpy())
+        assert n_ext_t == n_ext and np.array_equal(kt, kb) and np.array_equal(st_, sb), t
+        del ht
     idx1, idx2 = C.build_index(w.bank1), C.build_index(w.bank2)
     assert n_ext == O.n_extensions(idx1, idx2)
     # index parity at full size

@@ -40,14 +40,25 @@ int main(void) {
   printf("%zu %zu %zu %zu %zu\\n", sizeof(plast_index_t), offsetof(plast_index_t, n_words),
          offsetof(plast_index_t, scan_codes), sizeof(plast_ungapped_params_t), sizeof(plast_gapped_params_t));
   printf("%zu %d %d %d %d\\n", sizeof(plast_hit_t), PLAST_NKEYS, PLAST_PAD_CODE, PLAST_PAD_LEN, PLAST_NBR);
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(plast_tuning_t), offsetof(plast_tuning_t, xcd_queues),
+         sizeof(plast_tune_report_t), offsetof(plast_tune_report_t, class_ms),
+         offsetof(plast_tune_report_t, queue_ms), offsetof(plast_tune_report_t, gapped_ms), sizeof(plast_bank_t),
+         offsetof(plast_bank_t, n_padded), sizeof(plast_pipeline_result_t),
+         offsetof(plast_pipeline_result_t, n_words_b));
+  printf("%zu %zu %d %d\\n", offsetof(plast_ungapped_params_t, tuning), offsetof(plast_gapped_params_t, tuning),
+         PLAST_TUNE_CLASSES, PLAST_TUNE_WIDTHS);
   return 0;
 }
 """)
     exe = tmp_path / "layout"
     subprocess.check_call(["gcc", "-std=c99", "-I" + os.path.join(ROOT, "include"), str(prog), "-o", str(exe)])
-    a, b = subprocess.check_output([str(exe)], text=True).strip().splitlines()
-    a = [int(x) for x in a.split()]
-    b = [int(x) for x in b.split()]
+    a, b, c, d = subprocess.check_output([str(exe)], text=True).strip().splitlines()
+    a, b, c, d = ([int(x) for x in line.split()] for line in (a, b, c, d))
+    T, R, BD, PR = binding.Tuning, binding.TuneReport, binding.BankDesc, binding.PipelineResult
+    assert c == [ctypes.sizeof(T), T.xcd_queues.offset, ctypes.sizeof(R), R.class_ms.offset, R.queue_ms.offset,
+                 R.gapped_ms.offset, ctypes.sizeof(BD), BD.n_padded.offset, ctypes.sizeof(PR), PR.n_words_b.offset]
+    assert d == [binding.UngappedParams.tuning.offset, binding.GappedParams.tuning.offset, binding.TUNE_CLASSES,
+                 len(binding.TUNE_WIDTHS)]
     assert a == [ctypes.sizeof(binding.IndexView), binding.IndexView.n_words.offset,
                  binding.IndexView.scan_codes.offset, ctypes.sizeof(binding.UngappedParams),
                  ctypes.sizeof(binding.GappedParams)]
@@ -71,25 +82,92 @@ def test_strerror_and_argument_validation_without_gpu():
     fake = ctypes.c_void_p(0x1000)
     assert lib.plast_build_index(fake, fake, 1, 1000, fake, 1, fake, 1, ctypes.byref(view), None) == \
         binding.E_WORKSPACE
-    p = binding.UngappedParams(binding.NBR, 38, None)
+    p = binding.UngappedParams(binding.NBR, 38, None, None)
     n = ctypes.c_int64(0)
     assert lib.plast_ungapped_extend(None, None, ctypes.byref(p), 1, fake, 256, fake, 10, ctypes.byref(n), None,
                                      None) == binding.E_ARG
     v = binding.IndexView(fake.value, fake.value, 1, 1000, fake.value, fake.value, fake.value, fake.value, 10)
-    p_bad = binding.UngappedParams(7, 38, None)
+    p_bad = binding.UngappedParams(7, 38, None, None)
     assert lib.plast_ungapped_extend(ctypes.byref(v), ctypes.byref(v), ctypes.byref(p_bad), 1, fake, 256, fake, 10,
                                      ctypes.byref(n), None, None) == binding.E_ARG
     assert lib.plast_ungapped_extend(ctypes.byref(v), ctypes.byref(v), ctypes.byref(p), 7, fake, 256, fake, 10,
                                      ctypes.byref(n), None, None) == binding.E_ARG
-    g = binding.GappedParams(0, 16, 11, 1, 48, None)
+    g = binding.GappedParams(0, 16, 11, 1, 48, None, None)
     assert lib.plast_gapped_filter(ctypes.byref(v), ctypes.byref(v), fake, 5, ctypes.byref(g), fake, fake,
                                    None) == binding.E_ARG
-    g = binding.GappedParams(64, 17, 11, 1, 48, None)
+    g = binding.GappedParams(64, 17, 11, 1, 48, None, None)
     assert lib.plast_gapped_filter(ctypes.byref(v), ctypes.byref(v), fake, 5, ctypes.byref(g), fake, fake,
                                    None) == binding.E_ARG
-    g = binding.GappedParams(64, 16, 11, 1, 48, None)
+    g = binding.GappedParams(64, 16, 11, 1, 48, None, None)
     assert lib.plast_gapped_filter(ctypes.byref(v), ctypes.byref(v), fake, 0, ctypes.byref(g), fake, fake,
                                    None) == binding.OK
+
+
+def test_tuning_validation_without_gpu():
+    lib = binding.load()
+    t = binding.tuning_default()
+    assert list(t.class_min_n2) == [1, 2048, 8192, 32768] and list(t.item_cols) == [4096] * 4
+    assert (t.xcd_queues, t.gapped_threads) == (1, 256)
+    fake = ctypes.c_void_p(0x1000)
+    v = binding.IndexView(fake.value, fake.value, 1, 1000, fake.value, fake.value, fake.value, fake.value, 10)
+    n = ctypes.c_int64(0)
+
+    def extend_rc(tun):
+        p = binding.UngappedParams(binding.NBR, 38, None, ctypes.addressof(tun))
+        return lib.plast_ungapped_extend(ctypes.byref(v), ctypes.byref(v), ctypes.byref(p), 1, fake, 256, fake, 10,
+                                         ctypes.byref(n), None, None)
+
+    for field, value in (("item_cols", [4096, 1000, 4096, 4096]), ("item_cols", [4096, 4096, 4096, 32768]),
+                         ("class_min_n2", [0, 2048, 8192, 32768]), ("class_min_n2", [1, 2048, 2048, 32768]),
+                         ("xcd_queues", 4), ("gapped_threads", 64)):
+        bad = binding.Tuning.from_dict(t.as_dict())
+        if isinstance(value, list):
+            getattr(bad, field)[:] = value
+        else:
+            setattr(bad, field, value)
+        assert extend_rc(bad) == binding.E_ARG, (field, value)
+        assert b"tuning" in lib.plast_last_error()
+    g = binding.GappedParams(64, 16, 11, 1, 48, None, None)
+    bad = binding.Tuning.from_dict({"gapped_threads": 100})
+    g.tuning = ctypes.addressof(bad)
+    assert lib.plast_gapped_filter(ctypes.byref(v), ctypes.byref(v), fake, 5, ctypes.byref(g), fake, fake,
+                                   None) == binding.E_ARG
+
+
+def test_autotune_and_pipeline_validation_without_gpu():
+    lib = binding.load()
+    fake = ctypes.c_void_p(0x1000)
+    v = binding.IndexView(fake.value, fake.value, 1, 1000, fake.value, fake.value, fake.value, fake.value, 10)
+    u = binding.UngappedParams(binding.NBR, 38, None, None)
+    g = binding.GappedParams(64, 16, 11, 1, 48, None, None)
+    out, rep = binding.Tuning(), binding.TuneReport()
+    for reps in (0, 21):
+        assert lib.plast_autotune(ctypes.byref(v), ctypes.byref(v), ctypes.byref(u), ctypes.byref(g), reps, fake,
+                                  1 << 20, fake, 10, fake, fake, ctypes.byref(out), ctypes.byref(rep),
+                                  None) == binding.E_ARG
+    a = binding.BankDesc(fake.value, fake.value, 3, 1000)
+    b = binding.BankDesc(fake.value, fake.value, 30, 100000)
+    sz0, sz1 = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    assert lib.plast_pipeline_workspace_bytes(ctypes.byref(a), ctypes.byref(b), 0, ctypes.byref(sz0)) == binding.OK
+    assert lib.plast_pipeline_workspace_bytes(ctypes.byref(a), ctypes.byref(b), 1000, ctypes.byref(sz1)) == \
+        binding.OK
+    ia, wa = binding.index_bytes(1000, 3)
+    ib, wb = binding.index_bytes(100000, 30)
+    assert sz0.value >= ia + ib + max(wa, wb) and sz1.value - sz0.value >= 16 * 1000
+    assert lib.plast_pipeline_workspace_bytes(ctypes.byref(a), ctypes.byref(b), -1, ctypes.byref(sz0)) == \
+        binding.E_ARG
+    bad = binding.BankDesc(fake.value, fake.value, 3, 10)  # shorter than one separator run
+    assert lib.plast_pipeline_workspace_bytes(ctypes.byref(bad), ctypes.byref(b), 0, ctypes.byref(sz0)) == \
+        binding.E_ARG
+    h = ctypes.c_void_p(0)
+    odd = ctypes.c_void_p(0x1010)
+    assert lib.plast_pipeline_create(ctypes.byref(a), ctypes.byref(b), ctypes.byref(u), ctypes.byref(g), 10, odd,
+                                     1 << 30, fake, 10, fake, fake, ctypes.byref(h)) == binding.E_ARG  # misaligned
+    ws = ctypes.c_void_p(0x10000)
+    assert lib.plast_pipeline_create(ctypes.byref(a), ctypes.byref(b), ctypes.byref(u), ctypes.byref(g), 10, ws,
+                                     256, fake, 10, fake, fake, ctypes.byref(h)) == binding.E_WORKSPACE
+    assert lib.plast_pipeline_launch(None, None) == binding.E_ARG
+    assert lib.plast_pipeline_destroy(None) == binding.OK
 
 
 def test_product_code_never_touches_the_oracle():
