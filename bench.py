@@ -78,8 +78,10 @@ def copy_calibration(torch, dev):
 
 
 def pair_keys_device(torch, hits):
+    """Sorted 64-bit pair keys and their scores (positions < 2^11, bank-2
+    sequence ids < 2^19, bank-1 ids < 2^22)."""
     h = hits.to(torch.int64)
-    k = (((h[:, 0] << 11) | h[:, 1]) << 28) | (h[:, 2] << 11) | h[:, 3]
+    k = (((h[:, 0] << 11) | h[:, 1]) << 30) | (h[:, 2] << 11) | h[:, 3]
     k, o = torch.sort(k)
     return k, h[o, 4]
 
@@ -145,6 +147,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 256 MiB device copy (counter scaling for rocprofv3 --pmc runs)")
     ap.add_argument("--no-autotune", action="store_true", help="use the built-in launch shapes")
+    ap.add_argument("--tuning", default=None,
+                    help="launch shapes as JSON (plast_tuning_t fields); skips the autotuner")
     ap.add_argument("--tune-reps", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -177,7 +181,9 @@ def main():
     ia = B.build_index(ca, sa, workspace=ws_idx, out_buf=buf_a)
     ib = B.build_index(cb, sb, workspace=ws_idx, out_buf=buf_b)
     tuning, tune_report, tune_s = None, None, 0.0
-    if not args.no_autotune:
+    if args.tuning:
+        tuning = B.Tuning.from_dict(json.loads(args.tuning))
+    elif not args.no_autotune:
         log("autotuning launch shapes")
         t1 = time.perf_counter()
         tuning, tune_report = B.autotune(ia, ib, params.S1, params.S2, reps=args.tune_reps)

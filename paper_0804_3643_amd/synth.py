@@ -26,8 +26,15 @@ Workload recipe (the paper's banks, Annex 1, are not available)
   replaces a bank2 sequence;
 * low-complexity repeats (skewed configuration): 5% of the sequences of each
   bank receive one run of length U[100, 400] (clamped to the sequence) drawn
-  uniformly from one of three small alphabets of 2, 3 and 4 letters; the pool is
-  drawn once per seed.
+  uniformly from one of three small alphabets of 2, 3 and 4 letters.  Each
+  bank has its own pool of three alphabets, and the two pools share no letter
+  (18 distinct letters, drawn once per seed): the words of a bank-1 run and of
+  a bank-2 run then differ in their first letter, so they never share a seed
+  key.  With one shared pool every pair of same-alphabet runs sharing a key
+  scores above S1 (about 1.5e10 hits, 300 GB of hit records), which no single
+  device holds; with disjoint pools the buckets stay just as skewed (each
+  run's words pile into a few keys of its own bank) and a repeat window is only
+  paired with ordinary windows of the other bank.
 
 Random streams: ``numpy.random.SeedSequence(651300 + cfg).spawn(6)`` gives the
 independent streams (lengths, residues, plant choice, mutation, indels,
@@ -173,6 +180,7 @@ class Workload:
     bank2: Bank
     plants: list
     description: str
+    repeat_pools: tuple = ()  # per bank, the alphabets its repeat runs are drawn from
 
 
 @dataclasses.dataclass(frozen=True)
@@ -274,9 +282,14 @@ def make_workload(cfg: int, plants: bool = True, scale: float = 1.0) -> Workload
     seqs = _split(flat, lens)
     s1, s2 = seqs[:n1], seqs[n1:]
     if spec.repeats:
-        pool = [r_rep.choice(20, size=k, replace=False) for k in (2, 3, 4)]
-        _add_repeats(s1, r_rep, pool)
-        _add_repeats(s2, r_rep, pool)
+        letters = r_rep.permutation(20)
+        pool1 = [letters[0:2], letters[2:5], letters[5:9]]
+        pool2 = [letters[9:11], letters[11:14], letters[14:18]]
+        _add_repeats(s1, r_rep, pool1)
+        _add_repeats(s2, r_rep, pool2)
+        pools = (pool1, pool2)
+    else:
+        pools = ()
     planted = []
     n_pl = min(spec.n_plants, n1, n2) if plants else 0
     if n_pl:
@@ -289,7 +302,7 @@ def make_workload(cfg: int, plants: bool = True, scale: float = 1.0) -> Workload
             hom, colmap, ident = _mutate(s1[src[k]], float(ids[k]), r_mut, r_indel, subst)
             s2[dst[k]] = hom
             planted.append(Plant(int(src[k]), int(dst[k]), float(ids[k]), ident, colmap))
-    return Workload(cfg, Bank.from_seqs(s1), Bank.from_seqs(s2), planted, spec.description)
+    return Workload(cfg, Bank.from_seqs(s1), Bank.from_seqs(s2), planted, spec.description, pools)
 
 
 def random_bank(rng, n, lo=1, hi=60, alphabet_size=20) -> Bank:

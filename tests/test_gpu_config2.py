@@ -1,0 +1,93 @@
+"""Full-size skewed configuration 2 (20,000 x 300,000 proteins, 5% carrying
+low-complexity repeats) on the GPU: index parity, the number of extensions,
+PLAIN == BATCHED == other launch shapes == graph replay, and the hits and gapped
+scores of sampled keys (heaviest, lightest, random) against the oracle."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import coracle as C
+from oracle import plast_oracle as O
+from paper_0804_3643_amd import params, synth
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+
+def _say(msg):
+    print("[gpu-test] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+def _pair_sorted(h):
+    """Device-sorted 64-bit pair keys and scores: 11-bit positions, bank-2 ids < 2^19."""
+    h = h.to(torch.int64)
+    k = (((h[:, 0] << 11) | h[:, 1]) << 30) | (h[:, 2] << 11) | h[:, 3]
+    k, o = torch.sort(k)
+    return k, h[o, 4]
+
+
+@pytest.mark.timeout(900)
+def test_config2_full_size():
+    from paper_0804_3643_amd import binding as B
+    B.load()
+    _say("cfg2 generate")
+    w = synth.make_workload(2)
+    assert w.bank1.lengths.max() < 2048 and w.bank2.lengths.max() < 2048 and w.bank2.n_seqs < (1 << 19)
+    idx1, idx2 = C.build_index(w.bank1), C.build_index(w.bank2)
+    n2 = np.diff(idx2[0])
+    assert n2.max() > 1000 * n2[n2 > 0].min()           # buckets skewed over 3 orders of magnitude
+    _say("cfg2 index")
+    ca, sa = B.bank_to_device(w.bank1, "cuda")
+    cb, sb = B.bank_to_device(w.bank2, "cuda")
+    ia, ib = B.build_index(ca, sa), B.build_index(cb, sb)
+    for ix, ref in ((ia, idx1), (ib, idx2)):
+        assert np.array_equal(ix.key_off().cpu().numpy(), ref[0])
+        st = ix.seq_start.cpu().numpy()
+        occ_seq = ix.occ_seq().cpu().numpy().astype(np.int64)
+        assert np.array_equal(occ_seq, ref[1])
+        assert np.array_equal(ix.occ().cpu().numpy() - st[occ_seq], ref[2])
+    _say("cfg2 batched")
+    hb, n_ext = B.ungapped_extend(ia, ib, params.S1, mode="batched")
+    assert n_ext == O.n_extensions(idx1, idx2)
+    kb, sb_ = _pair_sorted(hb)
+    assert bool((kb[1:] != kb[:-1]).all())               # no pair twice
+    for t in ({"item_cols": [1024, 4096, 16384, 16384], "xcd_queues": 8}, None):
+        mode = "plain" if t is None else "batched"
+        _say("cfg2 %s %s" % (mode, t))
+        h, ne = B.ungapped_extend(ia, ib, params.S1, mode=mode, tuning=t)
+        k, s = _pair_sorted(h)
+        assert ne == n_ext and torch.equal(k, kb) and torch.equal(s, sb_), (mode, t)
+        del h, k, s
+    _say("cfg2 graph replay")
+    _, _, n_items = B.ungapped_workspace_bytes(ia, ib, "batched")
+    pl = B.Pipeline(ca, sa, cb, sb, params.S1, params.S2, n_items, hb.shape[0] + 1024)
+    pl.launch()
+    r = pl.result()
+    assert r["status"] == B.OK and r["n_ext"] == n_ext and r["n_hits"] == hb.shape[0], r
+    gh, gg, gp = pl.outputs(r["n_hits"])
+    k, s = _pair_sorted(gh)
+    assert torch.equal(k, kb) and torch.equal(s, sb_)
+    del k, s
+    # sampled keys against the oracle: 2 heaviest, 4 lightest, 10 random
+    work = np.diff(idx1[0]) * n2
+    nz = np.nonzero(work)[0]
+    order = nz[np.argsort(work[nz])]
+    rng = np.random.default_rng(2)
+    keys = np.unique(np.concatenate([order[-2:], order[:4], rng.choice(nz, 10, replace=False)])).astype(np.int32)
+    _say("cfg2 oracle on %d sampled keys (%.3g extensions)" % (len(keys), work[keys].sum()))
+    ref, _ = C.ungapped_hits(w.bank1, w.bank2, params.S1, keys=keys, idx1=idx1, idx2=idx2)
+    hh = gh.cpu().numpy().astype(np.int64)
+    c = w.bank1.codes
+    q = w.bank1.seq_start[hh[:, 0]] + hh[:, 1]
+    hk = O.seed_key(c[q].astype(np.int64), c[q + 1].astype(np.int64), c[q + 2].astype(np.int64),
+                    c[q + 3].astype(np.int64))
+    sel = np.isin(hk, keys)
+    assert np.array_equal(O.canonical(hh[sel]), ref)
+    _say("cfg2 gapped scores of the sampled hits (%d)" % int(sel.sum()))
+    g_ref = C.gapped_scores(w.bank1, w.bank2, hh[sel])
+    assert np.array_equal(gg.cpu().numpy()[sel].astype(np.int64), g_ref)
+    assert np.array_equal(gp.cpu().numpy()[sel].astype(bool), g_ref >= params.S2)
+    pl.close()

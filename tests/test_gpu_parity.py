@@ -271,7 +271,8 @@ def test_gapped_sequence_ends_and_bad_records(B):
 
 def _pair_keys(h):
     h = np.asarray(h, dtype=np.int64)
-    return (((h[:, 0] << 11) | h[:, 1]) << 28) | (h[:, 2] << 11) | h[:, 3]
+    # 11-bit positions, bank-2 sequence ids below 2^19: 56 bits in all
+    return (((h[:, 0] << 11) | h[:, 1]) << 30) | (h[:, 2] << 11) | h[:, 3]
 
 
 def _sorted_by_pair(h):

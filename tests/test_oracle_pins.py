@@ -372,3 +372,26 @@ def test_generator_deterministic_and_identity():
     L = np.concatenate([w1.bank1.lengths, w1.bank2.lengths])
     assert 50 <= L.min() and L.max() <= 1000 + 5 * 10  # homologs may grow by insertions
     assert 270 < L.mean() < 320
+
+
+def test_skewed_generator_repeats():
+    """Configuration 2 at a fifth of its size: 5% of each bank's sequences carry
+    a 2-4-letter run, each bank's heaviest buckets come from its own runs, and
+    the runs of the two banks never share a seed key (disjoint alphabets)."""
+    w = synth.make_workload(2, plants=False, scale=0.2)
+    pools = [np.concatenate(p) for p in w.repeat_pools]
+    assert [len(a) for p in w.repeat_pools for a in p] == [2, 3, 4, 2, 3, 4]
+    assert len(np.unique(np.concatenate(pools))) == 18   # no letter shared: runs of both banks never share a key
+    for b, bank in enumerate((w.bank1, w.bank2)):
+        low = 0
+        for i in range(bank.n_seqs):
+            s = bank.codes[bank.seq_start[i]:bank.seq_start[i + 1] - synth.PAD_LEN]
+            assert len(s) >= 50
+            # runs are >= 50 letters long, so one of these 40-letter windows lies inside
+            runs = [x for x in np.lib.stride_tricks.sliding_window_view(s, 40)[::10] if len(np.unique(x)) <= 4]
+            low += bool(runs)
+            for x in runs:  # a run window is (nearly) all letters of its own bank's pool
+                assert np.isin(x, pools[b]).mean() >= 0.9 and np.isin(x, pools[1 - b]).mean() <= 0.1
+        assert abs(low - round(0.05 * bank.n_seqs)) <= 2
+    n2 = np.diff(C.build_index(w.bank2)[0])
+    assert n2.max() > 15 * np.median(n2[n2 > 0])
