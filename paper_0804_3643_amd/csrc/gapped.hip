@@ -23,9 +23,23 @@
 // integers are exact in binary16, -inf marks cells outside the band or before
 // the anchor, and v_pk_maximum3_f16 takes H = max(diagonal, E, F) in one
 // instruction.  Letters are fetched from global memory one block of rows
-// ahead as aligned dwords (four letters per load).  Substitution scores come
-// from a dense binary16 table in LDS.  The workgroup size is a launch-shape
-// parameter (128, 256 or 512 threads).
+// ahead as aligned dwords (four letters per load).
+//
+// Fast-path arithmetic: every value of cell (i, j) is carried shifted by
+// (i + j) * extend.  The shift turns the Gotoh recurrences into
+//   H' = max(H'(i-1, j-1) + s + 2 extend, E', F'),
+//   E'(i, j+1) = max(E'(i, j), H'(i, j) - open),  F'(i+1, j) = max(F'(i, j), H'(i, j) - open),
+// one addition and two maxima fewer per cell; the 2 extend is folded into the
+// substitution table.  The best cell is recovered per anti-diagonal (all cells
+// of one anti-diagonal share the shift): an odd row folds each new cell together
+// with the cell two slots to its right in the row above (still in its register)
+// into that anti-diagonal's running maximum, and an anti-diagonal is unshifted
+// once no later row reaches it.
+// Scores come from a pair table in LDS: one 4-byte entry holds the scores of
+// an x letter against two consecutive y letters, i.e. of two neighbouring cells
+// of a row, so one lookup per side serves two cells.  The workgroup size is a
+// launch-shape parameter (128, 256 or 512 threads); each resident workgroup
+// builds the 37 KB table once and strides over the hits.
 #include "plast_internal.h"
 
 namespace plast {
@@ -163,16 +177,18 @@ __global__ __launch_bounds__(kGThreads) void k_gapped(GappedArgs G, const plast_
 typedef _Float16 gh2 __attribute__((ext_vector_type(2)));
 // Rows per unrolled block and register budget of the fast path: the fastest
 // of a sweep on MI355X (4 rows per block, up to 256 VGPRs, i.e. 2 wavefronts
-// per SIMD; replicated tables and 3 wavefronts per SIMD were not faster).
+// per SIMD; 3 wavefronts per SIMD and 2-row blocks were not faster).
 constexpr int kFBlock = 4;                      // rows per unrolled block (1..4)
 static_assert(kFBlock >= 1 && kFBlock <= 4, "rows per block");
-constexpr int kFY = kGCells + kFBlock - 1;      // y letters held for a block (36)
-constexpr int kTblDwords = (kNLet * kNLet + 1) / 2;
+constexpr int kFY = kGCells + kFBlock;          // y letters held for a block (37)
 constexpr uint32_t kWall8 = kPadCode * kScale;  // the separator letter serves as wall: it scores -inf
-// Table entry (x, y) is the binary16 at byte offset x * kRowBytes + y * kEntry.
-constexpr uint32_t kEntry = 2;
-constexpr uint32_t kRowBytes = kNLet * kEntry;
-static_assert(kNLet * kRowBytes < 65536, "table offsets must fit 16 bits");
+// Pair table: dword (x * 21 + y1) * 21 + y2 holds the binary16 scores of x
+// against y1 (low half) and against y2 (high half), so one 4-byte lookup
+// serves two neighbouring cells of a row (y1 and y2 are consecutive y letters).
+constexpr int kPairRow = kNLet * kNLet;         // dwords per x letter (441)
+constexpr int kPairDwords = kNLet * kPairRow;   // 9261 (37 KB of LDS)
+constexpr uint32_t kXRowBytes = 4 * kPairRow;
+static_assert(kPairDwords * 4 < 65536, "table offsets must fit 16 bits");
 
 __device__ __forceinline__ gh2 gmax3(gh2 a, gh2 b, gh2 c) {
   uint32_t r;
@@ -212,11 +228,11 @@ struct GLetters {
     for (int r = 0; r < n; ++r) {
       const uint32_t sr = i0 + r <= lxR ? byte_of(r4, r) : kWall8;
       const uint32_t sl = i0 + r <= lxL ? byte_of(l4, 3 - r) : kWall8;
-      xbR[r] = (sr / kScale) * kRowBytes;
-      xbL[r] = (sl / kScale) * kRowBytes;
+      xbR[r] = (sr / kScale) * kXRowBytes;
+      xbL[r] = (sl / kScale) * kXRowBytes;
     }
   }
-  // y indices k0 .. k0+3 of both extensions: packed table column offsets
+  // y indices k0 .. k0+3 of both extensions: packed letters (R low, L high)
   __device__ __forceinline__ void ycols(int k0, uint32_t (&y)[4]) const {
     const uint32_t r4 = load4(B, qb + k0);          // byte t: y_R index k0 + t
     const uint32_t l4 = load4(B, qb - 4 - k0);      // byte 3 - t: y_L index k0 + t
@@ -225,10 +241,15 @@ struct GLetters {
       const int k = k0 + t;
       const uint32_t sr = (k >= 0 && k < lyR) ? byte_of(r4, t) : kWall8;
       const uint32_t sl = (k >= 0 && k < lyL) ? byte_of(l4, 3 - t) : kWall8;
-      y[t] = (sr / kScale) * kEntry | (((sl / kScale) * kEntry) << 16);
+      y[t] = (sr / kScale) | ((sl / kScale) << 16);
     }
   }
 };
+
+// Packed pair-table offsets of the letter pairs (a, b), R and L halves.
+__device__ __forceinline__ uint32_t pair_off(uint32_t a, uint32_t b) {
+  return (a * (uint32_t)(kNLet * 4) + b * 4u) & 0xffffu | ((((a >> 16) * (uint32_t)(kNLet * 4) + (b >> 16) * 4u)) << 16);
+}
 
 __device__ __forceinline__ void gapped_hit_f16(const GappedArgs& G, const uint32_t* tbl,
                                                const plast_hit_t* __restrict__ hits, int64_t h, int64_t n_hits,
@@ -258,70 +279,143 @@ __device__ __forceinline__ void gapped_hit_f16(const GappedArgs& G, const uint32
 
   const _Float16 ninf = -__builtin_inff16();
   const gh2 NEG = {ninf, ninf};
-  const _Float16 oe = (_Float16)(G.gap_open + G.gap_extend), ex = (_Float16)G.gap_extend;
-  const gh2 OE = {oe, oe}, EX = {ex, ex};
+  // Values are carried shifted by (i + j) * extend (see the kernel comment):
+  // the table holds s + 2 * extend, and both gap recurrences lose their
+  // per-cell extension term.
+  const _Float16 op = (_Float16)G.gap_open, ex = (_Float16)G.gap_extend;
+  const gh2 OP = {op, op};
   gh2 H[kGCells], F[kGCells];
-  uint32_t Y[kFY];
-  // row 0: H(0, j) = 0 at j = 0, -(open + j * extend) for 0 < j <= 16; F holds F(1, j)
+  // YY[k]: packed pair-table offsets of the letters at y indices i0 + k - 17 and
+  // i0 + k - 16 for the block at row i0; ylast: packed letters at y index i0 + 19
+  uint32_t YY[kFY - 1];
+  uint32_t ylast;
+  // row 0 (shifted): H(0, 0) = 0, H(0, j) + j * extend = -open for 0 < j <= 16; F holds F(1, j)
 #pragma unroll
   for (int d = 0; d < kGCells; ++d) {
     const int j = d - kGMaxBand;
-    const _Float16 v = j < 0 ? ninf : (j == 0 ? (_Float16)0 : (_Float16)(-(G.gap_open + j * G.gap_extend)));
+    const _Float16 v = j < 0 ? ninf : (j == 0 ? (_Float16)0 : -op);
     H[d] = gh2{v, v};
-    F[d] = H[d] - OE;
+    F[d] = H[d] - OP;
   }
-  // letters under the band of the first block (rows 1..4): Y[k] = y index k - 16
+  // letters under the band of the first block (rows 1..4): y indices -16 .. 20
+  {
+    uint32_t prev = 0;
 #pragma unroll
-  for (int g = 0; g < (kFY + 3) / 4; ++g) {
-    uint32_t y4[4];
-    L.ycols(4 * g - kGMaxBand, y4);
+    for (int g = 0; g < (kFY + 3) / 4; ++g) {
+      uint32_t y4[4];
+      L.ycols(4 * g - kGMaxBand, y4);
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
-      if (4 * g + t < kFY) Y[4 * g + t] = y4[t];
+      for (int t = 0; t < 4; ++t) {
+        const int k = 4 * g + t;
+        if (k > 0 && k < kFY) YY[k - 1] = pair_off(prev, y4[t]);
+        prev = y4[t];
+      }
+    }
+    ylast = 0;
+#pragma unroll
+    for (int g = 0; g < (kFY + 3) / 4; ++g) {
+      // the letter at position kFY - 1 of the first block (y index 20)
+      if (4 * g <= kFY - 1 && kFY - 1 < 4 * g + 4) {
+        uint32_t y4[4];
+        L.ycols(4 * g - kGMaxBand, y4);
+        ylast = y4[(kFY - 1) - 4 * g];
+      }
+    }
   }
   uint32_t xbR[kFBlock], xbL[kFBlock];
   L.xrows<kFBlock>(1, xbR, xbL);
-  gh2 best = {(_Float16)0, (_Float16)0};
+  gh2 best = {(_Float16)0, (_Float16)0};  // H(0, 0) = 0: the empty alignment
+  // best shifted value per anti-diagonal i + j = 2 i0 - 16 + t of the current block
+  constexpr int kAcc = 2 * (kFBlock - 1) + kGCells;  // 39
+  constexpr int kAccShift = 2 * kFBlock;             // anti-diagonals completed per block
+  gh2 acc[kAcc];
+#pragma unroll
+  for (int t = 0; t < kAcc; ++t) acc[t] = NEG;
+  int i0 = 1;
   const char* tb = (const char*)tbl;
-  for (int i0 = 1; __builtin_amdgcn_readfirstlane(__ballot(i0 <= rows) != 0); i0 += kFBlock) {
+  for (; __builtin_amdgcn_readfirstlane(__ballot(i0 <= rows) != 0); i0 += kFBlock) {
     // raw letters of the next block (x rows, and the y indices entering the band),
     // decoded after this block's rows
     const uint32_t nx4R = load4(L.A, L.qa + i0 + kFBlock - 1), nx4L = load4(L.A, L.qa - i0 - kFBlock - 3);
     const int k0 = i0 + kFY - kGMaxBand - 1;
     const uint32_t ny4R = load4(L.B, L.qb + k0), ny4L = load4(L.B, L.qb - 4 - k0);
+    // The block's cells in row-major order of cell pairs (2p, 2p + 1); the two
+    // table lookups of a pair (right side in A, left side in B) are issued
+    // kAhead pairs before the pair is computed (they depend on letters only).
+    constexpr int kPairs = (kGCells + 1) / 2;
+    constexpr int kSeq = kFBlock * kPairs;
+    constexpr int kAhead = 3;
+    uint32_t A[kSeq], B[kSeq];
+    auto issue = [&](int q) {
+      const int r = q / kPairs, p = q % kPairs;
+      const uint32_t yy = YY[2 * p + r];
+      A[q] = *(const uint32_t*)(tb + xbR[r] + (yy & 0xffffu));
+      B[q] = *(const uint32_t*)(tb + xbL[r] + (yy >> 16));
+    };
 #pragma unroll
-    for (int r = 0; r < kFBlock; ++r) {
-      gh2 e = NEG, hprev = NEG;
+    for (int q = 0; q < kAhead; ++q) issue(q);
+    gh2 e = NEG;
 #pragma unroll
-      for (int d = 0; d < kGCells; ++d) {
-        const uint32_t y = Y[d + r];
-        const _Float16 scR = *(const _Float16*)(tb + xbR[r] + (y & 0xffffu));
-        const _Float16 scL = *(const _Float16*)(tb + xbL[r] + (y >> 16));
-        const gh2 diag = H[d] + gh2{scR, scL};
-        const gh2 f = d + 1 < kGCells ? F[d + 1] : NEG;
-        const gh2 hh = gmax3(diag, e, f);
-        if (d & 1) best = gmax3(best, hprev, hh);
-        else if (d == kGCells - 1) best = gmax(best, hh);
-        hprev = hh;
-        const gh2 ho = hh - OE;
-        e = gmax(e - EX, ho);
-        F[d] = gmax(f - EX, ho);
-        H[d] = hh;
+    for (int q = 0; q < kSeq; ++q) {
+      if (q + kAhead < kSeq) issue(q + kAhead);
+      const int r = q / kPairs, p = q % kPairs;
+      if (p == 0) e = NEG;
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const int d = 2 * p + c;
+        if (d < kGCells) {
+          const gh2 sc = __builtin_bit_cast(gh2, __builtin_amdgcn_perm(B[q], A[q], c ? 0x07060302u : 0x05040100u));
+          const gh2 diag = H[d] + sc;
+          const gh2 f = d + 1 < kGCells ? F[d + 1] : NEG;
+          const gh2 hh = gmax3(diag, e, f);
+          // cell (i0 + r, d) lies on anti-diagonal 2 i0 - 16 + (2 r + d); in an odd
+          // row it shares it with cell d + 2 of the row above, still in H[d + 2]
+          const int t = 2 * r + d;
+          if (r & 1)
+            acc[t] = d + 2 < kGCells ? gmax3(acc[t], hh, H[d + 2]) : gmax(acc[t], hh);
+          else if (d < 2)
+            acc[t] = gmax(acc[t], hh);
+          const gh2 ho = hh - OP;
+          e = gmax(e, ho);
+          F[d] = gmax(f, ho);
+          H[d] = hh;
+        }
       }
     }
+    // anti-diagonals below 2 (i0 + 4) - 16 are complete: unshift and fold into best
+    {
+      const _Float16 base = (_Float16)(2 * i0 - kGMaxBand);
 #pragma unroll
-    for (int k = 0; k + kFBlock < kFY; ++k) Y[k] = Y[k + kFBlock];
+      for (int t = 0; t < kAccShift; ++t) {
+        const _Float16 o = (base + (_Float16)t) * ex;
+        best = gmax(best, acc[t] - gh2{o, o});
+      }
+#pragma unroll
+      for (int t = 0; t < kAcc; ++t) acc[t] = t + kAccShift < kAcc ? acc[t + kAccShift] : NEG;
+    }
+#pragma unroll
+    for (int k = 0; k + kFBlock < kFY - 1; ++k) YY[k] = YY[k + kFBlock];
     const int i1 = i0 + kFBlock;
 #pragma unroll
     for (int t = 0; t < kFBlock; ++t) {
       const int k = k0 + t;
       const uint32_t sr = (k >= 0 && k < L.lyR) ? byte_of(ny4R, t) : kWall8;
       const uint32_t sl = (k >= 0 && k < L.lyL) ? byte_of(ny4L, 3 - t) : kWall8;
-      Y[kFY - kFBlock + t] = (sr / kScale) * kEntry | (((sl / kScale) * kEntry) << 16);
+      const uint32_t y = (sr / kScale) | ((sl / kScale) << 16);
+      YY[kFY - 1 - kFBlock + t] = pair_off(ylast, y);
+      ylast = y;
       const uint32_t xr = i1 + t <= L.lxR ? byte_of(nx4R, t) : kWall8;
       const uint32_t xl = i1 + t <= L.lxL ? byte_of(nx4L, 3 - t) : kWall8;
-      xbR[t] = (xr / kScale) * kRowBytes;
-      xbL[t] = (xl / kScale) * kRowBytes;
+      xbR[t] = (xr / kScale) * kXRowBytes;
+      xbL[t] = (xl / kScale) * kXRowBytes;
+    }
+  }
+  {
+    const _Float16 base = (_Float16)(2 * i0 - kGMaxBand);
+#pragma unroll
+    for (int t = 0; t < kAcc; ++t) {
+      const _Float16 o = (base + (_Float16)t) * ex;
+      best = gmax(best, acc[t] - gh2{o, o});
     }
   }
   if (live) {
@@ -336,10 +430,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2)))
 void k_gapped_f16(GappedArgs G, const plast_hit_t* __restrict__ hits, int64_t n_hits,
                   const unsigned long long* __restrict__ n_dev, int32_t* __restrict__ gscore,
                   uint8_t* __restrict__ pass) {
-  __shared__ uint32_t tbl[kTblDwords];  // filled once per workgroup
-  for (int i = threadIdx.x; i < kTblDwords; i += NT) {
-    const uint32_t lo = G.tbl16[2 * i], hi = 2 * i + 1 < kNLet * kNLet ? G.tbl16[2 * i + 1] : 0;
-    tbl[i] = lo | (hi << 16);
+  __shared__ uint32_t tbl[kPairDwords];  // filled once per workgroup
+  for (int i = threadIdx.x; i < kPairDwords; i += NT) {
+    const int x = i / kPairRow, y1 = (i / kNLet) % kNLet, y2 = i % kNLet;
+    tbl[i] = (uint32_t)G.tbl16[x * kNLet + y1] | ((uint32_t)G.tbl16[x * kNLet + y2] << 16);
   }
   if (n_dev) n_hits = min(n_hits, (int64_t)*n_dev);
   __syncthreads();
@@ -348,16 +442,42 @@ void k_gapped_f16(GappedArgs G, const plast_hit_t* __restrict__ hits, int64_t n_
     gapped_hit_f16(G, tbl, hits, h, n_hits, gscore, pass);
 }
 
+// Workgroups of k_gapped_f16<NT> resident on the device at once (0 on error).
+template <int NT>
+int64_t fast_resident() {
+  static int64_t cached = 0;
+  if (!cached) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_gapped_f16<NT>, NT, 0) != hipSuccess)
+      return 0;
+    cached = (int64_t)cus * (per > 0 ? per : 1);
+  }
+  return cached;
+}
+
+// The grid is at most one resident wave of workgroups: each workgroup builds
+// the 37 KB pair table once and then strides over the hits.
 template <int NT>
 int launch_fast(const GappedArgs& G, const plast_hit_t* d_hits, int64_t n_hits, const unsigned long long* d_n,
                 int32_t* d_gscore, uint8_t* d_pass, hipStream_t stream) {
-  const int64_t grid = (n_hits + NT - 1) / NT;
+  const int64_t resident = fast_resident<NT>();
+  if (resident <= 0) return set_error(PLAST_E_HIP, "cannot query device occupancy");
+  const int64_t need = (n_hits + NT - 1) / NT;
+  const int64_t grid = need < resident ? need : resident;
   hipLaunchKernelGGL(k_gapped_f16<NT>, dim3((unsigned)grid), dim3(NT), 0, stream, G, d_hits, n_hits, d_n, d_gscore,
                      d_pass);
   return PLAST_OK;
 }
 
 }  // namespace
+
+int gapped_prepare() {
+  return (fast_resident<128>() > 0 && fast_resident<256>() > 0 && fast_resident<512>() > 0)
+             ? PLAST_OK
+             : set_error(PLAST_E_HIP, "cannot query device occupancy");
+}
 
 int gapped_filter_impl(const plast_index_t* a, const plast_index_t* b, const plast_hit_t* d_hits, int64_t n_hits,
                        const unsigned long long* d_n, const plast_gapped_params_t* g, int32_t* d_gscore,
@@ -390,21 +510,21 @@ int gapped_filter_impl(const plast_index_t* a, const plast_index_t* b, const pla
   const uint16_t ninf16 = 0xFC00;  // binary16 -inf
   for (int x = 0; x < kNLet; ++x)
     for (int y = 0; y < kNLet; ++y)
-      G.tbl16[x * kNLet + y] = (x < 20 && y < 20) ? __builtin_bit_cast(uint16_t, (_Float16)m[x * 20 + y]) : ninf16;
-  // Every finite DP value lies within [-(64 |M| + 3 (open + extend) + 130 extend), 64 |M|]:
-  // integers of that range are exact in binary16 when the bound stays below 2048.
+      G.tbl16[x * kNLet + y] =
+          (x < 20 && y < 20) ? __builtin_bit_cast(uint16_t, (_Float16)(m[x * 20 + y] + 2 * g->gap_extend)) : ninf16;
+  // Every finite DP value lies within [-(64 |M| + 3 (open + extend) + 130 extend), 64 |M|],
+  // and the fast path adds (i + j) * extend <= 150 extend to it: integers of that
+  // range are exact in binary16 when the bound stays below 2048.
   const bool fast = g->band == kGMaxBand && g->window <= kGMaxWin &&
-                    64 * maxabs + 3 * (g->gap_open + g->gap_extend) + 130 * g->gap_extend <= 2000;
+                    64 * maxabs + 3 * (g->gap_open + g->gap_extend) + 280 * g->gap_extend <= 2000;
   const int threads = g->tuning ? g->tuning->gapped_threads : 256;
   if (n_hits <= 0) return PLAST_OK;
   timing_mark(kStageGapped, false, stream);
   if (fast) {
-    if (threads == 128)
-      launch_fast<128>(G, d_hits, n_hits, d_n, d_gscore, d_pass, stream);
-    else if (threads == 512)
-      launch_fast<512>(G, d_hits, n_hits, d_n, d_gscore, d_pass, stream);
-    else
-      launch_fast<256>(G, d_hits, n_hits, d_n, d_gscore, d_pass, stream);
+    const int rc = threads == 128   ? launch_fast<128>(G, d_hits, n_hits, d_n, d_gscore, d_pass, stream)
+                   : threads == 512 ? launch_fast<512>(G, d_hits, n_hits, d_n, d_gscore, d_pass, stream)
+                                    : launch_fast<256>(G, d_hits, n_hits, d_n, d_gscore, d_pass, stream);
+    if (rc != PLAST_OK) return rc;
   } else {
     unsigned blocks = (unsigned)((n_hits + kGThreads - 1) / kGThreads);
     if (g->band == kGMaxBand)

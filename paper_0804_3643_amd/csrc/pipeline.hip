@@ -81,6 +81,7 @@ int pipeline_create_impl(const plast_bank_t* a, const plast_bank_t* b, const pla
   else
     tuning_default(&T);
   int rc = ungapped_prepare();
+  if (rc == PLAST_OK) rc = gapped_prepare();
   if (rc != PLAST_OK) return rc;
   plast_pipeline* P = new (std::nothrow) plast_pipeline;
   if (!P) return set_error(PLAST_E_ARG, "out of host memory");

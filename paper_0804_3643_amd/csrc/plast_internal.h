@@ -155,6 +155,7 @@ int autotune_impl(const plast_index_t* a, const plast_index_t* b, const plast_un
                   plast_tune_report_t* report, hipStream_t stream);
 // Occupancy queries of the persistent kernels, made once before any graph capture.
 int ungapped_prepare();
+int gapped_prepare();
 
 size_t pipeline_ws_bytes(const plast_bank_t* a, const plast_bank_t* b, int64_t max_items);
 int pipeline_create_impl(const plast_bank_t* a, const plast_bank_t* b, const plast_ungapped_params_t* p,
