@@ -296,6 +296,43 @@ int plast_pipeline_result(plast_pipeline_t* pl, plast_pipeline_result_t* out, vo
 int plast_pipeline_index(const plast_pipeline_t* pl, int32_t which, plast_index_t* out);
 int plast_pipeline_destroy(plast_pipeline_t* pl);
 
+/*
+ * Query search against a resident index, enqueued with no host synchronisation
+ * (the serving path: many query banks against one bank kept in HBM, several
+ * searches in flight on different streams).  One call enqueues, on `stream`:
+ * stage 0 for query bank a, the BATCHED work list and persistent extension
+ * kernel against the prebuilt index b (plast_build_index), the gapped filter
+ * with the hit count read from device memory, and, when d_matches is not NULL,
+ * a compaction of the hits that pass the gapped filter into d_matches (order
+ * unspecified).  Checks that the eager calls make on the host are device flags
+ * here, read back by plast_search_result.
+ * d_ws (plast_search_workspace_bytes, 256-byte aligned) holds bank a's index,
+ * the build scratch, the work list (max_items items) and the counters; it must
+ * stay untouched until plast_search_result has returned.  Searches that share
+ * a workspace or output buffers must not overlap.
+ */
+typedef struct {
+  int32_t seq1, pos1, seq2, pos2, score, gscore;  /* a hit that passes the gapped filter */
+} plast_match_t;
+
+/* Only a's sizes are read (its pointers may be NULL). */
+int plast_search_workspace_bytes(const plast_bank_t* a, int64_t max_items, size_t* bytes);
+/* d_seg_first (may be NULL; needs d_matches): n_seg + 1 ascending sequence ids
+ * of bank a, d_seg_first[0] = 0 and d_seg_first[n_seg] = a's n_seqs, cutting a
+ * into segments (one per request of a batch; n_seg <= 65536).  The matches are then written
+ * grouped by segment: segment s owns d_matches[d_seg_off[s] .. d_seg_off[s+1]),
+ * order inside a segment unspecified.  d_seg_off is device scratch of
+ * 2 (n_seg + 1) int64; its first n_seg + 1 entries are the offsets. */
+int plast_search_enqueue(const plast_bank_t* a, const plast_index_t* b, const plast_ungapped_params_t* p,
+                         const plast_gapped_params_t* g, int64_t max_items, void* d_ws, size_t ws_bytes,
+                         plast_hit_t* d_hits, int64_t capacity, int32_t* d_gscore, uint8_t* d_pass,
+                         plast_match_t* d_matches, const int32_t* d_seg_first, int32_t n_seg, int64_t* d_seg_off,
+                         void* stream);
+/* Waits for `stream` and reads the status and counts of the last search
+ * enqueued with this workspace (n_words_b is b's count as given).  *n_matches
+ * (may be NULL) receives the number of matches written. */
+int plast_search_result(const void* d_ws, plast_pipeline_result_t* out, int64_t* n_matches, void* stream);
+
 const char* plast_strerror(int code);
 const char* plast_last_error(void);
 

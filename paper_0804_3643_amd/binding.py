@@ -27,7 +27,8 @@ OK, E_ARG, E_ALPHABET, E_CAPACITY, E_WORKSPACE, E_HIP, E_LAYOUT = 0, -1, -2, -3,
 EXPORTS = ("plast_index_bytes", "plast_build_index", "plast_ungapped_workspace_bytes", "plast_ungapped_extend",
            "plast_gapped_filter", "plast_timing_enable", "plast_timing_read", "plast_tuning_default",
            "plast_autotune", "plast_pipeline_workspace_bytes", "plast_pipeline_create", "plast_pipeline_launch",
-           "plast_pipeline_result", "plast_pipeline_index", "plast_pipeline_destroy", "plast_strerror",
+           "plast_pipeline_result", "plast_pipeline_index", "plast_pipeline_destroy",
+           "plast_search_workspace_bytes", "plast_search_enqueue", "plast_search_result", "plast_strerror",
            "plast_last_error")
 
 TUNE_CLASSES = 4
@@ -100,6 +101,11 @@ class BankDesc(ctypes.Structure):
                 ("n_padded", ctypes.c_int64)]
 
 
+class MatchRec(ctypes.Structure):
+    _fields_ = [("seq1", ctypes.c_int32), ("pos1", ctypes.c_int32), ("seq2", ctypes.c_int32),
+                ("pos2", ctypes.c_int32), ("score", ctypes.c_int32), ("gscore", ctypes.c_int32)]
+
+
 class PipelineResult(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("n_items", ctypes.c_int32), ("n_hits", ctypes.c_int64),
                 ("n_ext", ctypes.c_int64), ("n_words_a", ctypes.c_int64), ("n_words_b", ctypes.c_int64)]
@@ -140,6 +146,10 @@ def load():
         lib.plast_pipeline_result.argtypes = [P, ctypes.POINTER(PipelineResult), P]
         lib.plast_pipeline_index.argtypes = [P, i32, IV]
         lib.plast_pipeline_destroy.argtypes = [P]
+        lib.plast_search_workspace_bytes.argtypes = [BD, i64, ctypes.POINTER(sz)]
+        lib.plast_search_enqueue.argtypes = [BD, IV, ctypes.POINTER(UngappedParams), ctypes.POINTER(GappedParams),
+                                             i64, P, sz, P, i64, P, P, P, P, i32, P, P]
+        lib.plast_search_result.argtypes = [P, ctypes.POINTER(PipelineResult), ctypes.POINTER(i64), P]
         for f in EXPORTS[:-2]:
             getattr(lib, f).restype = ctypes.c_int
         lib.plast_strerror.argtypes = [ctypes.c_int]
@@ -446,3 +456,58 @@ def timing_read():
     _check(load().plast_timing_read(ctypes.byref(t)), "plast_timing_read")
     return {"index_ms": t.index_ms, "plan_ms": t.plan_ms, "ungapped_ms": t.ungapped_ms, "gapped_ms": t.gapped_ms,
             "ungapped_launches": int(t.ungapped_launches)}
+
+
+class Searcher:
+    """One query-versus-resident search slot (``plast_search_*``): device
+    buffers for a query bank of up to ``max_padded`` codes / ``max_seqs``
+    sequences, a work list of ``max_items`` items and ``capacity`` hits, all
+    allocated once.  ``enqueue`` only enqueues on ``stream``; ``result`` waits
+    for it.  Matches (hits passing the gapped filter, with both scores) are
+    written to ``self.matches`` as int32[n, 6]."""
+
+    def __init__(self, resident, max_padded, max_seqs, max_items, capacity, s1, s2, matrix=None, tuning=None,
+                 window=64, band=16, gap_open=11, gap_extend=1):
+        dev = resident.codes.device
+        self.resident = resident
+        self.max_padded, self.max_seqs = int(max_padded), int(max_seqs)
+        self.max_items, self.capacity = int(max_items), int(capacity)
+        self.codes = torch.empty(self.max_padded, dtype=torch.uint8, device=dev)
+        self.starts = torch.empty(self.max_seqs + 1, dtype=torch.int64, device=dev)
+        big = BankDesc(0, 0, self.max_seqs, self.max_padded)
+        sz = ctypes.c_size_t(0)
+        _check(load().plast_search_workspace_bytes(ctypes.byref(big), self.max_items, ctypes.byref(sz)),
+               "plast_search_workspace_bytes")
+        self.ws = _alloc(sz.value, dev)
+        self.hits = torch.empty((max(self.capacity, 1), 5), dtype=torch.int32, device=dev)
+        self.gscore = torch.empty(max(self.capacity, 1), dtype=torch.int32, device=dev)
+        self.passed = torch.empty(max(self.capacity, 1), dtype=torch.uint8, device=dev)
+        self.matches = torch.empty((max(self.capacity, 1), 6), dtype=torch.int32, device=dev)
+        self.seg_first = torch.empty(self.max_seqs + 2, dtype=torch.int32, device=dev)
+        self.seg_off = torch.empty(2 * (self.max_seqs + 2), dtype=torch.int64, device=dev)
+        self._mat, mp = _matrix_ptr(matrix)
+        self._tun, tp = _tuning(tuning)
+        self.u = UngappedParams(NBR, int(s1), mp, tp)
+        self.g = GappedParams(int(window), int(band), int(gap_open), int(gap_extend), int(s2), mp, tp)
+
+    def enqueue(self, n_padded, n_seqs, n_seg=0, stream=None):
+        """Search the query bank already in ``self.codes[:n_padded]`` /
+        ``self.starts[:n_seqs + 1]`` (padded layout) against the resident index.
+        With ``n_seg`` > 0, ``self.seg_first[:n_seg + 1]`` cuts the bank into
+        segments and the matches come out grouped by segment (offsets in
+        ``self.seg_off[:n_seg + 1]``)."""
+        assert 0 < n_padded <= self.max_padded and 0 <= n_seqs <= self.max_seqs and 0 <= n_seg <= n_seqs + 1
+        a = BankDesc(self.codes.data_ptr(), self.starts.data_ptr(), int(n_seqs), int(n_padded))
+        seg = _ptr(self.seg_first) if n_seg > 0 else ctypes.c_void_p(0)
+        _check(load().plast_search_enqueue(ctypes.byref(a), ctypes.byref(self.resident.view), ctypes.byref(self.u),
+                                           ctypes.byref(self.g), self.max_items, _ptr(self.ws), self.ws.numel(),
+                                           _ptr(self.hits), self.capacity, _ptr(self.gscore), _ptr(self.passed),
+                                           _ptr(self.matches), seg, int(n_seg), _ptr(self.seg_off),
+                                           _stream(stream)), "plast_search_enqueue")
+
+    def result(self, stream=None):
+        r, nm = PipelineResult(), ctypes.c_int64(0)
+        _check(load().plast_search_result(_ptr(self.ws), ctypes.byref(r), ctypes.byref(nm), _stream(stream)),
+               "plast_search_result")
+        return {"status": int(r.status), "n_items": int(r.n_items), "n_hits": int(r.n_hits), "n_ext": int(r.n_ext),
+                "n_words_a": int(r.n_words_a), "n_matches": int(nm.value)}

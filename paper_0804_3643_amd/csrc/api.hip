@@ -225,10 +225,16 @@ static int check_gparams(const plast_gapped_params_t* g) {
   return tuning_or_default(g->tuning, &t);
 }
 
-static int check_bank(const plast_bank_t* x, const char* name) {
-  if (!x || !x->codes || !x->seq_start) return set_error(PLAST_E_ARG, "%s: null bank pointer", name);
+// Sizes only (workspace queries); check_bank also wants the device pointers.
+static int check_bank_sizes(const plast_bank_t* x, const char* name) {
+  if (!x) return set_error(PLAST_E_ARG, "%s: null bank", name);
   size_t ib = 0, wb = 0;
   return plast_index_bytes(x->n_padded, x->n_seqs, &ib, &wb);
+}
+
+static int check_bank(const plast_bank_t* x, const char* name) {
+  if (!x || !x->codes || !x->seq_start) return set_error(PLAST_E_ARG, "%s: null bank pointer", name);
+  return check_bank_sizes(x, name);
 }
 
 int plast_ungapped_extend(const plast_index_t* a, const plast_index_t* b, const plast_ungapped_params_t* p,
@@ -277,7 +283,7 @@ int plast_autotune(const plast_index_t* a, const plast_index_t* b, const plast_u
 int plast_pipeline_workspace_bytes(const plast_bank_t* a, const plast_bank_t* b, int64_t max_items, size_t* bytes) {
   g_last_error[0] = 0;
   int rc;
-  if ((rc = check_bank(a, "a")) || (rc = check_bank(b, "b"))) return rc;
+  if ((rc = check_bank_sizes(a, "a")) || (rc = check_bank_sizes(b, "b"))) return rc;
   if (!bytes || max_items < 0 || max_items > INT32_MAX)
     return set_error(PLAST_E_ARG, "null output pointer or max_items outside [0, 2^31)");
   *bytes = pipeline_ws_bytes(a, b, max_items);
@@ -323,6 +329,43 @@ int plast_pipeline_destroy(plast_pipeline_t* pl) {
   g_last_error[0] = 0;
   if (!pl) return PLAST_OK;
   return pipeline_destroy_impl(pl);
+}
+
+int plast_search_workspace_bytes(const plast_bank_t* a, int64_t max_items, size_t* bytes) {
+  g_last_error[0] = 0;
+  int rc;
+  if ((rc = check_bank_sizes(a, "a"))) return rc;
+  if (!bytes || max_items < 0 || max_items > INT32_MAX)
+    return set_error(PLAST_E_ARG, "null output pointer or max_items outside [0, 2^31)");
+  *bytes = search_ws_bytes(a, max_items);
+  return PLAST_OK;
+}
+
+int plast_search_enqueue(const plast_bank_t* a, const plast_index_t* b, const plast_ungapped_params_t* p,
+                         const plast_gapped_params_t* g, int64_t max_items, void* d_ws, size_t ws_bytes,
+                         plast_hit_t* d_hits, int64_t capacity, int32_t* d_gscore, uint8_t* d_pass,
+                         plast_match_t* d_matches, const int32_t* d_seg_first, int32_t n_seg, int64_t* d_seg_off,
+                         void* stream) {
+  g_last_error[0] = 0;
+  int rc;
+  if ((rc = check_bank(a, "a")) || (rc = check_index(b, "b")) || (rc = check_uparams(p)) || (rc = check_gparams(g)))
+    return rc;
+  if (!d_ws || capacity < 0 || (capacity > 0 && (!d_hits || !d_gscore || !d_pass)) || max_items < 0 ||
+      max_items > INT32_MAX)
+    return set_error(PLAST_E_ARG, "null pointer, negative capacity or max_items outside [0, 2^31)");
+  if ((uintptr_t)d_ws & 255) return set_error(PLAST_E_ARG, "workspace must be 256-byte aligned");
+  if (ws_bytes < search_ws_bytes(a, max_items))
+    return set_error(PLAST_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, search_ws_bytes(a, max_items));
+  if (d_seg_first && (!d_matches || !d_seg_off || n_seg < 1 || n_seg > a->n_seqs + 1 || n_seg > 65536))
+    return set_error(PLAST_E_ARG, "segments need matches, offsets and 1 <= n_seg <= min(n_seqs + 1, 65536)");
+  return search_enqueue_impl(a, b, p, g, max_items, d_ws, d_hits, capacity, d_gscore, d_pass, d_matches,
+                             d_seg_first, d_seg_first ? n_seg : 0, d_seg_off, (hipStream_t)stream);
+}
+
+int plast_search_result(const void* d_ws, plast_pipeline_result_t* out, int64_t* n_matches, void* stream) {
+  g_last_error[0] = 0;
+  if (!d_ws || !out) return set_error(PLAST_E_ARG, "null pointer");
+  return search_result_impl(d_ws, out, n_matches, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -178,6 +178,269 @@ int pipeline_destroy_impl(plast_pipeline_t* pl) {
   return PLAST_OK;
 }
 
+// ---------------------------------------------------------------- query search (serving)
+namespace {
+
+// [0, 256): SearchHeader; then the ungapped workspace (its counters at a fixed
+// offset, so plast_search_result needs no sizes), bank a's index, build scratch.
+struct SearchHeader {
+  int32_t err[2];             // bank a: error bits, words
+  unsigned long long n_match;
+  int64_t capacity;           // hit capacity of the search, for the status
+  int64_t n_words_b;
+};
+static_assert(sizeof(SearchHeader) <= 256, "search header");
+constexpr size_t kSearchUws = 256;
+
+struct SearchLayout {
+  size_t uws, idx_a, build, total;
+};
+
+SearchLayout search_layout(const plast_bank_t* a, int64_t max_items) {
+  SearchLayout L;
+  size_t off = kSearchUws;
+  L.uws = off;
+  off = align_up(off + ungapped_ws_fixed_bytes() + sizeof(WorkItem) * (size_t)max_items, 256);
+  L.idx_a = off;
+  off = align_up(off + index_layout(a->n_padded).total, 256);
+  L.build = off;
+  off = align_up(off + index_ws_bytes(a->n_padded), 256);
+  L.total = off;
+  return L;
+}
+
+__global__ void k_search_header(SearchHeader* h, int64_t capacity, int64_t n_words_b) {
+  if (threadIdx.x == 0) {
+    h->n_match = 0ull;
+    h->capacity = capacity;
+    h->n_words_b = n_words_b;
+  }
+}
+
+constexpr int kCompactThreads = 256;
+constexpr int kCompactBlocks = 1024;
+
+// Hits with pass[i] set, among the first min(*n_dev, cap), appended to out in
+// wavefront-sized groups (one atomic per wavefront).
+__global__ __launch_bounds__(kCompactThreads) void k_compact_matches(
+    const plast_hit_t* __restrict__ hits, const int32_t* __restrict__ gscore, const uint8_t* __restrict__ pass,
+    const unsigned long long* __restrict__ n_dev, int64_t cap, plast_match_t* __restrict__ out,
+    unsigned long long* __restrict__ n_out) {
+  const int64_t n = min((int64_t)*n_dev, cap);
+  const int lane = __lane_id();
+  for (int64_t base = (int64_t)blockIdx.x * kCompactThreads; base < n; base += (int64_t)gridDim.x * kCompactThreads) {
+    const int64_t i = base + threadIdx.x;
+    const bool take = i < n && pass[i];
+    const unsigned long long m = __ballot(take);
+    if (!m) continue;
+    const int leader = __ffsll((long long)m) - 1;
+    unsigned long long b = 0;
+    if (lane == leader) b = atomicAdd(n_out, (unsigned long long)__popcll(m));
+    b = __shfl(b, leader);
+    if (take) {
+      const plast_hit_t h = hits[i];
+      plast_match_t o;
+      o.seq1 = h.seq1;
+      o.pos1 = h.pos1;
+      o.seq2 = h.seq2;
+      o.pos2 = h.pos2;
+      o.score = h.score;
+      o.gscore = gscore[i];
+      out[b + __popcll(m & ((1ull << lane) - 1ull))] = o;
+    }
+  }
+}
+
+// Segment of query sequence q: the s with seg_first[s] <= q < seg_first[s + 1].
+__device__ __forceinline__ int segment_of(const int32_t* __restrict__ seg_first, int n_seg, int q) {
+  int lo = 0, hi = n_seg - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (seg_first[mid] <= q) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Lanes of the wavefront with the same segment id (valid lanes only), from one
+// ballot per id bit.
+__device__ __forceinline__ unsigned long long segment_peers(int seg, bool valid) {
+  unsigned long long peers = __ballot(valid);
+#pragma unroll
+  for (int b = 0; b < 16; ++b) {
+    const int bit = (seg >> b) & 1;
+    const unsigned long long m = __ballot(bit);
+    peers &= bit ? m : ~m;
+  }
+  return peers;
+}
+
+// Pass 1: matches per segment (off[0 .. n_seg) must be zero); one atomic per
+// (wavefront, segment).
+__global__ __launch_bounds__(kCompactThreads) void k_segment_count(
+    const plast_hit_t* __restrict__ hits, const uint8_t* __restrict__ pass, const unsigned long long* __restrict__ n_dev,
+    int64_t cap, const int32_t* __restrict__ seg_first, int n_seg, unsigned long long* __restrict__ cnt) {
+  const int64_t n = min((int64_t)*n_dev, cap);
+  const int lane = __lane_id();
+  for (int64_t base = (int64_t)blockIdx.x * kCompactThreads; base < n; base += (int64_t)gridDim.x * kCompactThreads) {
+    const int64_t i = base + threadIdx.x;
+    const bool take = i < n && pass[i];
+    if (!__ballot(take)) continue;
+    const int seg = take ? segment_of(seg_first, n_seg, hits[i].seq1) : 0;
+    const unsigned long long peers = segment_peers(seg, take);
+    if (take && lane == __ffsll((long long)peers) - 1) atomicAdd(&cnt[seg], (unsigned long long)__popcll(peers));
+  }
+}
+
+// Exclusive scan of the n_seg counts (one workgroup): off[0..n_seg], the write
+// cursors cur[s] = off[s], and the total in *n_out.
+__global__ __launch_bounds__(256) void k_segment_scan(unsigned long long* __restrict__ off, int n_seg,
+                                                      unsigned long long* __restrict__ cur,
+                                                      unsigned long long* __restrict__ n_out) {
+  __shared__ unsigned long long carry;
+  __shared__ unsigned long long part[256];
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int base = 0; base < n_seg; base += 256) {
+    const int s = base + threadIdx.x;
+    const unsigned long long v = s < n_seg ? off[s] : 0ull;
+    part[threadIdx.x] = v;
+    __syncthreads();
+    for (int d = 1; d < 256; d <<= 1) {  // inclusive Hillis-Steele scan
+      const unsigned long long t = threadIdx.x >= d ? part[threadIdx.x - d] : 0ull;
+      __syncthreads();
+      part[threadIdx.x] += t;
+      __syncthreads();
+    }
+    const unsigned long long excl = carry + part[threadIdx.x] - v;
+    if (s < n_seg) {
+      off[s] = excl;
+      cur[s] = excl;
+    }
+    __syncthreads();
+    if (threadIdx.x == 255) carry += part[255];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    off[n_seg] = carry;
+    *n_out = carry;
+  }
+}
+
+// Pass 2: each passing hit to its segment's next slot; one atomic per
+// (wavefront, segment), lanes ranked inside their group.
+__global__ __launch_bounds__(kCompactThreads) void k_segment_scatter(
+    const plast_hit_t* __restrict__ hits, const int32_t* __restrict__ gscore, const uint8_t* __restrict__ pass,
+    const unsigned long long* __restrict__ n_dev, int64_t cap, const int32_t* __restrict__ seg_first, int n_seg,
+    unsigned long long* __restrict__ cur, plast_match_t* __restrict__ out) {
+  const int64_t n = min((int64_t)*n_dev, cap);
+  const int lane = __lane_id();
+  for (int64_t base = (int64_t)blockIdx.x * kCompactThreads; base < n; base += (int64_t)gridDim.x * kCompactThreads) {
+    const int64_t i = base + threadIdx.x;
+    const bool take = i < n && pass[i];
+    if (!__ballot(take)) continue;
+    plast_hit_t h = {0, 0, 0, 0, 0};
+    if (take) h = hits[i];
+    const int seg = take ? segment_of(seg_first, n_seg, h.seq1) : 0;
+    const unsigned long long peers = segment_peers(seg, take);
+    const int leader = take ? __ffsll((long long)peers) - 1 : 0;
+    unsigned long long at = 0;
+    if (take && lane == leader) at = atomicAdd(&cur[seg], (unsigned long long)__popcll(peers));
+    at = __shfl(at, leader);
+    if (take) {
+      plast_match_t o;
+      o.seq1 = h.seq1;
+      o.pos1 = h.pos1;
+      o.seq2 = h.seq2;
+      o.pos2 = h.pos2;
+      o.score = h.score;
+      o.gscore = gscore[i];
+      out[at + __popcll(peers & ((1ull << lane) - 1ull))] = o;
+    }
+  }
+}
+
+__global__ void k_zero_u64(unsigned long long* __restrict__ p, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0ull;
+}
+
+}  // namespace
+
+size_t search_ws_bytes(const plast_bank_t* a, int64_t max_items) { return search_layout(a, max_items).total; }
+
+int search_enqueue_impl(const plast_bank_t* a, const plast_index_t* b, const plast_ungapped_params_t* p,
+                        const plast_gapped_params_t* g, int64_t max_items, void* d_ws, plast_hit_t* d_hits,
+                        int64_t capacity, int32_t* d_gscore, uint8_t* d_pass, plast_match_t* d_matches,
+                        const int32_t* d_seg_first, int32_t n_seg, int64_t* d_seg_off, hipStream_t s) {
+  const SearchLayout L = search_layout(a, max_items);
+  plast_tuning_t T;
+  if (p->tuning)
+    T = *p->tuning;
+  else
+    tuning_default(&T);
+  uint8_t* base = (uint8_t*)d_ws;
+  SearchHeader* hdr = (SearchHeader*)base;
+  plast_index_t va;
+  hipLaunchKernelGGL(k_search_header, dim3(1), dim3(64), 0, s, hdr, capacity, b->n_words);
+  int rc = index_enqueue(a->codes, a->seq_start, a->n_seqs, a->n_padded, base + L.idx_a, base + L.build, hdr->err,
+                         &va, s);
+  if (rc != PLAST_OK) return rc;
+  void* uws = base + L.uws;
+  rc = ungapped_enqueue_batched(&va, b, p, T, ~0u, uws, L.idx_a - L.uws, d_hits, capacity, hdr->err, nullptr, nullptr,
+                                nullptr, s);
+  if (rc != PLAST_OK) return rc;
+  if (capacity > 0) {
+    rc = gapped_filter_impl(&va, b, d_hits, capacity, ungapped_n_hits_dev(uws), g, d_gscore, d_pass, s);
+    if (rc != PLAST_OK) return rc;
+    const int64_t blocks = min((int64_t)kCompactBlocks, (capacity + kCompactThreads - 1) / kCompactThreads);
+    const unsigned long long* nh = ungapped_n_hits_dev(uws);
+    if (d_matches && d_seg_first) {
+      unsigned long long* off = (unsigned long long*)d_seg_off;
+      unsigned long long* cur = off + (n_seg + 1);
+      hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(256), 0, s, off, n_seg + 1);
+      hipLaunchKernelGGL(k_segment_count, dim3((unsigned)blocks), dim3(kCompactThreads), 0, s,
+                         (const plast_hit_t*)d_hits, (const uint8_t*)d_pass, nh, capacity, d_seg_first, (int)n_seg,
+                         off);
+      hipLaunchKernelGGL(k_segment_scan, dim3(1), dim3(256), 0, s, off, (int)n_seg, cur, &hdr->n_match);
+      hipLaunchKernelGGL(k_segment_scatter, dim3((unsigned)blocks), dim3(kCompactThreads), 0, s,
+                         (const plast_hit_t*)d_hits, (const int32_t*)d_gscore, (const uint8_t*)d_pass, nh, capacity,
+                         d_seg_first, (int)n_seg, cur, d_matches);
+    } else if (d_matches) {
+      hipLaunchKernelGGL(k_compact_matches, dim3((unsigned)blocks), dim3(kCompactThreads), 0, s,
+                         (const plast_hit_t*)d_hits, (const int32_t*)d_gscore, (const uint8_t*)d_pass, nh, capacity,
+                         d_matches, &hdr->n_match);
+    }
+  }
+  PLAST_HIP(hipGetLastError());
+  return PLAST_OK;
+}
+
+int search_result_impl(const void* d_ws, plast_pipeline_result_t* out, int64_t* n_matches, hipStream_t s) {
+  SearchHeader h;
+  UngappedCounters c{0, 0, 0, 0, 0};
+  PLAST_HIP(hipMemcpyAsync(&h, d_ws, sizeof(h), hipMemcpyDeviceToHost, s));
+  PLAST_HIP(hipMemcpyAsync(&c, ungapped_counters_dev((const uint8_t*)d_ws + kSearchUws), sizeof(c),
+                           hipMemcpyDeviceToHost, s));
+  PLAST_HIP(hipStreamSynchronize(s));
+  const int64_t capacity = h.capacity;
+  out->n_items = c.n_items;
+  out->n_hits = (int64_t)c.n_hits;
+  out->n_ext = (int64_t)c.n_ext;
+  out->n_words_a = h.err[1];
+  out->n_words_b = h.n_words_b;
+  if (h.err[0] & 1)
+    out->status = PLAST_E_LAYOUT;
+  else if (h.err[0] & 2)
+    out->status = PLAST_E_ALPHABET;
+  else if (c.overflow)
+    out->status = PLAST_E_WORKSPACE;
+  else if ((int64_t)c.n_hits > capacity)
+    out->status = PLAST_E_CAPACITY;
+  else
+    out->status = PLAST_OK;
+  if (n_matches) *n_matches = (int64_t)h.n_match;
+  return PLAST_OK;
+}
+
 // ---------------------------------------------------------------- autotuner
 namespace {
 

@@ -166,4 +166,11 @@ int pipeline_result_impl(plast_pipeline_t* pl, plast_pipeline_result_t* out, hip
 int pipeline_index_impl(const plast_pipeline_t* pl, int32_t which, plast_index_t* out);
 int pipeline_destroy_impl(plast_pipeline_t* pl);
 
+size_t search_ws_bytes(const plast_bank_t* a, int64_t max_items);
+int search_enqueue_impl(const plast_bank_t* a, const plast_index_t* b, const plast_ungapped_params_t* p,
+                        const plast_gapped_params_t* g, int64_t max_items, void* d_ws, plast_hit_t* d_hits,
+                        int64_t capacity, int32_t* d_gscore, uint8_t* d_pass, plast_match_t* d_matches,
+                        const int32_t* d_seg_first, int32_t n_seg, int64_t* d_seg_off, hipStream_t s);
+int search_result_impl(const void* d_ws, plast_pipeline_result_t* out, int64_t* n_matches, hipStream_t s);
+
 }  // namespace plast

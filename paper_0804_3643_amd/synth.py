@@ -151,6 +151,20 @@ class Bank:
         return Bank(codes, seq_start)
 
     @staticmethod
+    def from_flat(flat, lens) -> "Bank":
+        """Bank from concatenated residues ``flat`` and sequence lengths ``lens``."""
+        lens = np.asarray(lens, dtype=np.int64)
+        n = len(lens)
+        seq_start = np.empty(n + 1, dtype=np.int64)
+        seq_start[0] = PAD_LEN
+        seq_start[1:] = PAD_LEN + np.cumsum(lens + PAD_LEN)
+        codes = np.full(int(seq_start[-1]), PAD_CODE, dtype=np.uint8)
+        # residue r of sequence i goes to seq_start[i] + r: shift each residue by PAD_LEN * (i + 1)
+        seq_of = np.repeat(np.arange(n, dtype=np.int64), lens)
+        codes[np.arange(int(lens.sum()), dtype=np.int64) + PAD_LEN * (seq_of + 1)] = flat
+        return Bank(codes, seq_start)
+
+    @staticmethod
     def from_strings(strs) -> "Bank":
         return Bank.from_seqs([encode(s) for s in strs])
 
@@ -248,6 +262,38 @@ def _mutate(src: np.ndarray, identity: float, rng_mut, rng_indel, subst):
     return out, colmap, ident
 
 
+def _mutate_vec(src: np.ndarray, identity: float, rng, cum):
+    """The mutation model of ``_mutate`` (BLOSUM62-conditional substitutions at
+    rate 1 - identity, indels at INDEL_RATE of length min(Geom(1/2), 5), half
+    insertions of background residues) drawn with vectorised numpy; used for
+    the many homologs of the serving workload."""
+    n = len(src)
+    out = src.copy()
+    mut = np.nonzero(rng.random(n) >= identity)[0]
+    if len(mut):
+        a = out[mut].astype(np.int64)
+        u = rng.random(len(mut)) * cum[a, -1]
+        b = np.minimum((cum[a] <= u[:, None]).sum(axis=1), 19)
+        b = np.where(b == a, (a + 1) % 20, b)
+        out[mut] = b.astype(np.uint8)
+    ev = np.nonzero(rng.random(n) < INDEL_RATE)[0]
+    if not len(ev):
+        return out
+    pieces, p = [], 0
+    for e in ev:
+        if e < p:
+            continue
+        length = min(int(rng.geometric(0.5)), 5)
+        pieces.append(out[p:e])
+        if rng.random() < 0.5:
+            pieces.append(rng.choice(20, size=length, p=BACKGROUND).astype(np.uint8))
+            p = e
+        else:
+            p = e + length
+    pieces.append(out[p:])
+    return np.concatenate(pieces)
+
+
 def _add_repeats(seqs, rng, pool):
     n = len(seqs)
     chosen = rng.choice(n, size=max(1, int(round(0.05 * n))), replace=False)
@@ -309,3 +355,51 @@ def random_bank(rng, n, lo=1, hi=60, alphabet_size=20) -> Bank:
     """Small random bank for tests: ``n`` sequences of length U[lo, hi]."""
     lens = rng.integers(lo, hi + 1, size=n)
     return Bank.from_seqs([rng.integers(0, alphabet_size, size=int(L)).astype(np.uint8) for L in lens])
+
+
+# --------------------------------------------------------------------------- serving workload
+
+@dataclasses.dataclass
+class ServingWorkload:
+    resident: Bank
+    requests: list      # query banks
+    homologs: list      # per request: (query sequence, resident sequence) of each planted homolog
+    description: str
+
+
+def make_serving(n_resident: int = 1_000_000, n_requests: int = 1000, max_query: int = 500,
+                 homolog_frac: float = 0.10, identity=(0.30, 0.60), scale: float = 1.0) -> ServingWorkload:
+    """Serving configuration: a resident bank of ``n_resident`` proteins with the
+    distributions of configuration 0, and ``n_requests`` query banks of
+    U{1..max_query} proteins each, ``homolog_frac`` of them (rounded) planted
+    homologs of random resident proteins (mutated as in ``make_workload``).
+    ``scale`` shrinks the resident bank.  Streams: SeedSequence(651304).spawn(6)."""
+    ss = np.random.SeedSequence(651300 + 4).spawn(6)
+    r_len, r_res, r_req, r_plant, r_mut, r_indel = [np.random.Generator(np.random.PCG64(s)) for s in ss]
+    n_res = max(1, int(round(n_resident * scale)))
+    lens = _lengths(r_len, n_res)
+    flat = r_res.choice(20, size=int(lens.sum()), p=BACKGROUND).astype(np.uint8)
+    resident = Bank.from_flat(flat, lens)
+    cum = np.cumsum(_substitution_probs(), axis=1)
+    requests, homologs = [], []
+    for _ in range(n_requests):
+        m = int(r_req.integers(1, max_query + 1))
+        ql = _lengths(r_req, m)
+        seqs = _split(r_req.choice(20, size=int(ql.sum()), p=BACKGROUND).astype(np.uint8), ql)
+        k = int(round(homolog_frac * m))
+        pl = []
+        if k:
+            slots = r_plant.choice(m, size=k, replace=False)
+            srcs = r_plant.choice(n_res, size=k, replace=False)
+            ids = r_plant.uniform(identity[0], identity[1], size=k)
+            for q, rs, idt in zip(slots, srcs, ids):
+                a, b = int(resident.seq_start[rs]), int(resident.seq_start[rs + 1]) - PAD_LEN
+                src = resident.codes[a:b]
+                hom = _mutate_vec(src, float(idt), r_mut, cum)
+                seqs[int(q)] = hom if len(hom) else src.copy()
+                pl.append((int(q), int(rs)))
+        requests.append(Bank.from_seqs(seqs))
+        homologs.append(pl)
+    return ServingWorkload(resident, requests, homologs,
+                           "serving: %d resident proteins, %d requests of 1-%d query proteins, %d%% planted homologs"
+                           % (n_res, n_requests, max_query, round(100 * homolog_frac)))

@@ -45,8 +45,8 @@ int main(void) {
          offsetof(plast_tune_report_t, queue_ms), offsetof(plast_tune_report_t, gapped_ms), sizeof(plast_bank_t),
          offsetof(plast_bank_t, n_padded), sizeof(plast_pipeline_result_t),
          offsetof(plast_pipeline_result_t, n_words_b));
-  printf("%zu %zu %d %d\\n", offsetof(plast_ungapped_params_t, tuning), offsetof(plast_gapped_params_t, tuning),
-         PLAST_TUNE_CLASSES, PLAST_TUNE_WIDTHS);
+  printf("%zu %zu %d %d %zu\\n", offsetof(plast_ungapped_params_t, tuning), offsetof(plast_gapped_params_t, tuning),
+         PLAST_TUNE_CLASSES, PLAST_TUNE_WIDTHS, sizeof(plast_match_t));
   return 0;
 }
 """)
@@ -58,7 +58,7 @@ int main(void) {
     assert c == [ctypes.sizeof(T), T.xcd_queues.offset, ctypes.sizeof(R), R.class_ms.offset, R.queue_ms.offset,
                  R.gapped_ms.offset, ctypes.sizeof(BD), BD.n_padded.offset, ctypes.sizeof(PR), PR.n_words_b.offset]
     assert d == [binding.UngappedParams.tuning.offset, binding.GappedParams.tuning.offset, binding.TUNE_CLASSES,
-                 len(binding.TUNE_WIDTHS)]
+                 len(binding.TUNE_WIDTHS), ctypes.sizeof(binding.MatchRec)]
     assert a == [ctypes.sizeof(binding.IndexView), binding.IndexView.n_words.offset,
                  binding.IndexView.scan_codes.offset, ctypes.sizeof(binding.UngappedParams),
                  ctypes.sizeof(binding.GappedParams)]
@@ -168,6 +168,26 @@ def test_autotune_and_pipeline_validation_without_gpu():
                                      256, fake, 10, fake, fake, ctypes.byref(h)) == binding.E_WORKSPACE
     assert lib.plast_pipeline_launch(None, None) == binding.E_ARG
     assert lib.plast_pipeline_destroy(None) == binding.OK
+    # query search against a resident index; the size query needs no pointers
+    sizes_only = binding.BankDesc(0, 0, 3, 1000)
+    assert lib.plast_search_workspace_bytes(ctypes.byref(sizes_only), 0, ctypes.byref(sz0)) == binding.OK
+    assert lib.plast_pipeline_workspace_bytes(ctypes.byref(sizes_only), ctypes.byref(sizes_only), 0,
+                                              ctypes.byref(sz1)) == binding.OK
+    assert lib.plast_search_workspace_bytes(ctypes.byref(a), 0, ctypes.byref(sz0)) == binding.OK
+    assert lib.plast_search_workspace_bytes(ctypes.byref(a), 1000, ctypes.byref(sz1)) == binding.OK
+    assert sz0.value >= ia + wa and sz1.value - sz0.value >= 16 * 1000
+    assert lib.plast_search_enqueue(ctypes.byref(a), ctypes.byref(v), ctypes.byref(u), ctypes.byref(g), 10, odd,
+                                    1 << 30, fake, 10, fake, fake, None, None, 0, None, None) == binding.E_ARG  # misaligned
+    assert lib.plast_search_enqueue(ctypes.byref(a), ctypes.byref(v), ctypes.byref(u), ctypes.byref(g), 10, ws,
+                                    256, fake, 10, fake, fake, None, None, 0, None, None) == binding.E_WORKSPACE
+    assert lib.plast_search_enqueue(ctypes.byref(a), None, ctypes.byref(u), ctypes.byref(g), 10, ws,
+                                    1 << 30, fake, 10, fake, fake, None, None, 0, None, None) == binding.E_ARG
+    # segments need the match buffer, the offsets and a sane count
+    assert lib.plast_search_enqueue(ctypes.byref(a), ctypes.byref(v), ctypes.byref(u), ctypes.byref(g), 10, ws,
+                                    1 << 30, fake, 10, fake, fake, None, fake, 2, fake, None) == binding.E_ARG
+    assert lib.plast_search_enqueue(ctypes.byref(a), ctypes.byref(v), ctypes.byref(u), ctypes.byref(g), 10, ws,
+                                    1 << 30, fake, 10, fake, fake, fake, fake, 5, fake, None) == binding.E_ARG
+    assert lib.plast_search_result(None, ctypes.byref(binding.PipelineResult()), None, None) == binding.E_ARG
 
 
 def test_product_code_never_touches_the_oracle():
