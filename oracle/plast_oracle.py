@@ -29,9 +29,15 @@ What is computed (paper section in brackets)
   each over at most G letters per sequence, cells restricted to |i - j| <= band;
   gapped score = best right + best left, pass iff >= S2.
 
-Readings where the paper is silent or garbled are listed in the design doc of the
-repository (seed table rows 1/4 missing I, row 3 class f = {F,Y,W}, N = 20,
->= S1, no X-drop, window G = 64, band 16, gap cost 11 + k).
+Readings taken where the paper is silent or garbled: the seed table's rows 1
+and 4 list every letter (I is missing in the text), row 3's class f is
+{F,Y,W}, N = 20, hits are score >= S1, no X-drop, gapped window G = 64, band
+16, a gap of length k costs 11 + k.
+* six-frame translation (Sec. 6, TPLAST-N; the paper gives no details): the
+  standard genetic code; frames 0..2 start at nucleotides 0..2 of the forward
+  strand, frames 3..5 at nucleotides 0..2 of the reverse complement; a
+  trailing partial codon is dropped; stop codons split a frame into fragments,
+  each fragment (non-empty) a protein sequence of its own.
 """
 from __future__ import annotations
 
@@ -375,3 +381,69 @@ def _gapped_vec(X, Y, lx, ly, window, band, gap_open, gap_extend, mat):
             best = np.where(exists, np.maximum(best, h), best)
         Hprev, Fprev = Hcur, Fcur
     return best
+
+
+# --------------------------------------------------------------------------- six-frame translation
+
+# Standard genetic code (NCBI translation table 1): amino acid of codon
+# b1 b2 b3 with bases in the order T C A G, first base slowest; '*' = stop.
+_CODE_TCAG = "FFLLSSSSYY**CC*WLLLLPPPPHHQQRRRRIIIMTTTTNNKKSSRRVVVVAAAADDEEGGGG"
+DNA = "ACGT"     # nucleotide codes 0..3
+STOP = -1
+
+
+def codon_table() -> np.ndarray:
+    """int[64], indexed by 16 b1 + 4 b2 + b3 with nucleotide codes (A0 C1 G2 T3):
+    the amino acid code in ALPHABET order, or STOP."""
+    tcag = "TCAG"
+    t = np.empty(64, dtype=np.int64)
+    for i1, b1 in enumerate(tcag):
+        for i2, b2 in enumerate(tcag):
+            for i3, b3 in enumerate(tcag):
+                aa = _CODE_TCAG[16 * i1 + 4 * i2 + i3]
+                t[16 * DNA.index(b1) + 4 * DNA.index(b2) + DNA.index(b3)] = STOP if aa == "*" else ALPHABET.index(aa)
+    return t
+
+
+CODONS = codon_table()
+
+
+def frame_codons(dna: np.ndarray, frame: int) -> np.ndarray:
+    """Amino acid codes (or STOP) of one reading frame of one sequence."""
+    s = np.asarray(dna, dtype=np.int64)
+    if frame >= 3:
+        s = (3 - s)[::-1]               # reverse complement
+    s = s[frame % 3:]
+    n = len(s) // 3                     # a trailing partial codon is dropped
+    c = s[:3 * n].reshape(n, 3)
+    return CODONS[16 * c[:, 0] + 4 * c[:, 1] + c[:, 2]]
+
+
+def translate6(dna_codes, dna_start):
+    """Fragments of all six frames of every sequence, in the order (sequence,
+    frame, position): (list of uint8 arrays, int64[n, 3] table of
+    (sequence, frame, offset of the fragment's first amino acid in its frame))."""
+    frags, table = [], []
+    for d in range(len(dna_start) - 1):
+        seq = dna_codes[int(dna_start[d]):int(dna_start[d + 1])]
+        for f in range(6):
+            aa = frame_codons(seq, f)
+            i, n = 0, len(aa)
+            while i < n:
+                if aa[i] == STOP:
+                    i += 1
+                    continue
+                j = i
+                while j < n and aa[j] != STOP:
+                    j += 1
+                frags.append(aa[i:j].astype(np.uint8))
+                table.append((d, f, i))
+                i = j
+    return frags, np.array(table, dtype=np.int64).reshape(-1, 3)
+
+
+def frame_position(dna_len: int, frame: int, aa_offset: int) -> int:
+    """Forward-strand coordinate of the first nucleotide of codon aa_offset of
+    a frame (for frames 3..5 the codon reads leftward from this nucleotide)."""
+    p = frame % 3 + 3 * aa_offset
+    return p if frame < 3 else dna_len - 1 - p

@@ -403,3 +403,99 @@ def make_serving(n_resident: int = 1_000_000, n_requests: int = 1000, max_query:
     return ServingWorkload(resident, requests, homologs,
                            "serving: %d resident proteins, %d requests of 1-%d query proteins, %d%% planted homologs"
                            % (n_res, n_requests, max_query, round(100 * homolog_frac)))
+
+
+# --------------------------------------------------------------------------- nucleotide banks (TPLAST-N)
+
+DNA_ALPHABET = "ACGT"  # codes 0..3; the complement of code c is 3 - c
+
+# Standard genetic code, written as the codons of each amino acid (for reverse
+# translation of planted homologs).
+_SYNONYMS = {
+    "A": "GCT GCC GCA GCG", "C": "TGT TGC", "D": "GAT GAC", "E": "GAA GAG", "F": "TTT TTC",
+    "G": "GGT GGC GGA GGG", "H": "CAT CAC", "I": "ATT ATC ATA", "K": "AAA AAG",
+    "L": "TTA TTG CTT CTC CTA CTG", "M": "ATG", "N": "AAT AAC", "P": "CCT CCC CCA CCG", "Q": "CAA CAG",
+    "R": "CGT CGC CGA CGG AGA AGG", "S": "TCT TCC TCA TCG AGT AGC", "T": "ACT ACC ACA ACG",
+    "V": "GTT GTC GTA GTG", "W": "TGG", "Y": "TAT TAC",
+}
+
+
+def synonym_codons():
+    """code (0..19) -> list of codons as int8[3] arrays of nucleotide codes."""
+    lut = {c: i for i, c in enumerate(DNA_ALPHABET)}
+    return [[np.array([lut[b] for b in cod], dtype=np.uint8) for cod in _SYNONYMS[a].split()] for a in ALPHABET]
+
+
+@dataclasses.dataclass
+class DnaBank:
+    codes: np.ndarray   # uint8 in 0..3, sequences concatenated
+    start: np.ndarray   # int64[n + 1]
+
+    @property
+    def n_seqs(self) -> int:
+        return int(self.start.shape[0] - 1)
+
+    def seq(self, i: int) -> np.ndarray:
+        return self.codes[int(self.start[i]):int(self.start[i + 1])]
+
+    @staticmethod
+    def from_seqs(seqs) -> "DnaBank":
+        lens = np.array([len(s) for s in seqs], dtype=np.int64)
+        start = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+        codes = np.concatenate([np.asarray(s, dtype=np.uint8) for s in seqs]) if len(seqs) else np.zeros(0, np.uint8)
+        return DnaBank(codes, start)
+
+
+@dataclasses.dataclass
+class DnaPlant:
+    protein: int   # bank-1 sequence
+    dna: int       # DNA sequence carrying the homolog
+    strand: int    # +1 or -1
+    offset: int    # first nucleotide of the coding region on the forward strand
+    n_codons: int
+
+
+@dataclasses.dataclass
+class TplastnWorkload:
+    bank1: Bank
+    dna: DnaBank
+    plants: list
+    description: str
+
+
+def make_tplastn(n_proteins: int = 5000, n_dna: int = 2000, dna_len=(50_000, 200_000), n_plants: int = 100,
+                 identity: float = 0.40, gc: float = 0.40, scale: float = 1.0) -> TplastnWorkload:
+    """Configuration 3: ``n_proteins`` proteins with configuration 0's
+    distributions against ``n_dna`` random DNA sequences of U[dna_len]
+    nucleotides (GC content ``gc``), carrying ``n_plants`` homologs of bank-1
+    proteins (mutated at ``identity`` as in ``make_workload``) reverse-translated
+    with uniformly chosen synonymous codons, each written over a random
+    position on a random strand.  ``scale`` shrinks the sequence counts.
+    Streams: SeedSequence(651303).spawn(6)."""
+    ss = np.random.SeedSequence(651300 + 3).spawn(6)
+    r_len, r_res, r_dna, r_plant, r_mut, r_indel = [np.random.Generator(np.random.PCG64(s)) for s in ss]
+    n1 = max(1, int(round(n_proteins * scale)))
+    nd = max(1, int(round(n_dna * scale)))
+    lens = _lengths(r_len, n1)
+    s1 = _split(r_res.choice(20, size=int(lens.sum()), p=BACKGROUND).astype(np.uint8), lens)
+    p_nt = np.array([(1 - gc) / 2, gc / 2, gc / 2, (1 - gc) / 2])  # A C G T
+    dl = r_dna.integers(dna_len[0], dna_len[1] + 1, size=nd)
+    dna = _split(r_dna.choice(4, size=int(dl.sum()), p=p_nt).astype(np.uint8), dl)
+    syn = synonym_codons()
+    subst = _substitution_probs()
+    plants = []
+    for k, src in enumerate(r_plant.choice(n1, size=min(n_plants, n1), replace=False)):
+        hom, _, _ = _mutate(s1[int(src)], identity, r_mut, r_indel, subst)
+        coding = np.concatenate([syn[a][int(r_plant.integers(len(syn[a])))] for a in hom]) if len(hom) else \
+            np.zeros(0, np.uint8)
+        d = int(r_plant.integers(nd))
+        if len(coding) == 0 or len(coding) > len(dna[d]):
+            continue
+        off = int(r_plant.integers(0, len(dna[d]) - len(coding) + 1))
+        strand = 1 if r_plant.random() < 0.5 else -1
+        dna[d][off:off + len(coding)] = coding if strand > 0 else (3 - coding)[::-1]
+        plants.append(DnaPlant(int(src), d, strand, off, len(hom)))
+    return TplastnWorkload(Bank.from_seqs(s1), DnaBank.from_seqs(dna), plants,
+                           "TPLAST-N: %d proteins vs %d DNA sequences of %d-%d nt (GC %.0f%%), %d planted homologs "
+                           "at %.0f%% identity" % (n1, nd, dna_len[0], dna_len[1], 100 * gc, len(plants),
+                                                   100 * identity))

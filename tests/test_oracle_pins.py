@@ -395,3 +395,74 @@ def test_skewed_generator_repeats():
         assert abs(low - round(0.05 * bank.n_seqs)) <= 2
     n2 = np.diff(C.build_index(w.bank2)[0])
     assert n2.max() > 15 * np.median(n2[n2 > 0])
+
+
+# ----------------------------------------------------------------------------- six-frame translation
+
+def _dna(s):
+    return np.array(["ACGT".index(c) for c in s], dtype=np.uint8)
+
+
+def test_codon_table_textbook_facts():
+    t = O.CODONS
+    stops = sorted("".join("ACGT"[(i >> k) & 3] for k in (4, 2, 0)) for i in np.nonzero(t == O.STOP)[0])
+    assert stops == ["TAA", "TAG", "TGA"]
+    code = lambda c: O.ALPHABET[t[16 * "ACGT".index(c[0]) + 4 * "ACGT".index(c[1]) + "ACGT".index(c[2])]]
+    assert code("ATG") == "M" and code("TGG") == "W" and code("TTT") == "F" and code("GGG") == "G"
+    deg = {a: int((t == i).sum()) for i, a in enumerate(O.ALPHABET)}
+    assert deg == {**{a: 2 for a in "CDEFHKNQY"}, "L": 6, "S": 6, "R": 6, "A": 4, "G": 4, "P": 4, "T": 4, "V": 4,
+                   "I": 3, "M": 1, "W": 1}
+
+
+def test_codon_table_agrees_with_generator_transcription():
+    """The generator's reverse-translation table (typed separately, per amino
+    acid) and the oracle's code (typed as the TCAG string) describe the same
+    61 sense codons."""
+    syn = synth.synonym_codons()
+    seen = set()
+    for a, cods in enumerate(syn):
+        for c in cods:
+            idx = 16 * int(c[0]) + 4 * int(c[1]) + int(c[2])
+            assert O.CODONS[idx] == a
+            seen.add(idx)
+    assert len(seen) == 61 and all(O.CODONS[i] == O.STOP for i in set(range(64)) - seen)
+
+
+def test_translate6_hand_example():
+    frags, table = O.translate6(_dna("ATGGCCTAAGGG"), np.array([0, 12]))
+    got = [("".join(O.ALPHABET[x] for x in f), tuple(r)) for f, r in zip(frags, table)]
+    # frame 0: ATG GCC TAA GGG = M A * G; frame 1: TGG CCT AAG = W P K; frame 2: GGC CTA AGG = G L R;
+    # reverse complement CCCTTAGGCCAT: frame 3 CCC TTA GGC CAT = P L G H; frame 4 CCT TAG GCC = P * A;
+    # frame 5 CTT AGG CCA = L R P
+    assert got == [("MA", (0, 0, 0)), ("G", (0, 0, 3)), ("WPK", (0, 1, 0)), ("GLR", (0, 2, 0)),
+                   ("PLGH", (0, 3, 0)), ("P", (0, 4, 0)), ("A", (0, 4, 2)), ("LRP", (0, 5, 0))]
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_reverse_translation_round_trip_and_frame_coordinates(seed):
+    """A protein reverse-translated with random synonymous codons and written at
+    offset o on either strand of random DNA comes back, in the frame and at the
+    amino-acid offset the coordinates predict, inside one fragment."""
+    rng = np.random.default_rng(seed)
+    syn = synth.synonym_codons()
+    for strand in (1, -1):
+        prot = rng.integers(0, 20, size=int(rng.integers(5, 60))).astype(np.uint8)
+        coding = np.concatenate([syn[a][int(rng.integers(len(syn[a])))] for a in prot])
+        assert np.array_equal(O.frame_codons(coding, 0), prot)
+        L = int(rng.integers(len(coding) + 10, len(coding) + 400))
+        dna = rng.integers(0, 4, size=L).astype(np.uint8)
+        o = int(rng.integers(0, L - len(coding) + 1))
+        dna[o:o + len(coding)] = coding if strand > 0 else (3 - coding)[::-1]
+        frags, table = O.translate6(dna, np.array([0, L]))
+        if strand > 0:
+            frame, start = o % 3, o
+        else:
+            start = L - (o + len(coding))
+            frame = 3 + start % 3
+        aa0 = (start - frame % 3) // 3
+        hit = [k for k, (d, f, a) in enumerate(table) if f == frame and a <= aa0 < a + len(frags[k])]
+        assert len(hit) == 1
+        k = hit[0]
+        assert np.array_equal(frags[k][aa0 - table[k][2]:aa0 - table[k][2] + len(prot)], prot)
+        first_nt = O.frame_position(L, frame, aa0)
+        assert first_nt == (o if strand > 0 else o + len(coding) - 1)
