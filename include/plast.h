@@ -333,6 +333,33 @@ int plast_search_enqueue(const plast_bank_t* a, const plast_index_t* b, const pl
  * (may be NULL) receives the number of matches written. */
 int plast_search_result(const void* d_ws, plast_pipeline_result_t* out, int64_t* n_matches, void* stream);
 
+/*
+ * TPLAST-N (Sec. 6: a protein bank against the six translated frames of a
+ * nucleotide bank), the translation on the device.  Frames 0..2 read the
+ * forward strand from nucleotide 0, 1 or 2, frames 3..5 the reverse complement
+ * the same way; a trailing partial codon is dropped; the standard genetic code
+ * maps codons to residues or stops, and stops cut every frame into fragments.
+ * The output is a protein bank in the padded layout (plast_build_index input)
+ * whose sequences are the non-empty fragments in the order (DNA sequence,
+ * frame, position), and d_frag[3 j .. 3 j + 2] = (DNA sequence, frame, offset
+ * of fragment j's first residue within its frame) for mapping hits back.
+ * Nucleotide codes are A 0, C 1, G 2, T 3; d_dna_start has n_dna + 1 ascending
+ * offsets into d_dna with d_dna_start[n_dna] = n_nt.
+ * Two calls: plast_translate_count enqueues the counting pass and synchronises,
+ * returning the fragment count and the padded length (so the caller can size
+ * the outputs: n_padded codes, n_frags + 1 starts, 3 n_frags fragment words);
+ * plast_translate_write then enqueues the writing pass with the same workspace
+ * (plast_translate_ws_bytes, 256-byte aligned).
+ * Errors: PLAST_E_ARG, PLAST_E_LAYOUT (offsets), PLAST_E_ALPHABET (a code > 3),
+ * PLAST_E_WORKSPACE, PLAST_E_HIP.
+ */
+int plast_translate_ws_bytes(int32_t n_dna, size_t* bytes);
+int plast_translate_count(const uint8_t* d_dna, const int64_t* d_dna_start, int32_t n_dna, int64_t n_nt, void* d_ws,
+                          size_t ws_bytes, int64_t* h_n_frags, int64_t* h_n_padded, void* stream);
+int plast_translate_write(const uint8_t* d_dna, const int64_t* d_dna_start, int32_t n_dna, int64_t n_nt, void* d_ws,
+                          size_t ws_bytes, uint8_t* d_codes, int64_t n_padded, int64_t* d_seq_start, int32_t* d_frag,
+                          int64_t n_frags, void* stream);
+
 const char* plast_strerror(int code);
 const char* plast_last_error(void);
 

@@ -28,7 +28,8 @@ EXPORTS = ("plast_index_bytes", "plast_build_index", "plast_ungapped_workspace_b
            "plast_gapped_filter", "plast_timing_enable", "plast_timing_read", "plast_tuning_default",
            "plast_autotune", "plast_pipeline_workspace_bytes", "plast_pipeline_create", "plast_pipeline_launch",
            "plast_pipeline_result", "plast_pipeline_index", "plast_pipeline_destroy",
-           "plast_search_workspace_bytes", "plast_search_enqueue", "plast_search_result", "plast_strerror",
+           "plast_search_workspace_bytes", "plast_search_enqueue", "plast_search_result",
+           "plast_translate_ws_bytes", "plast_translate_count", "plast_translate_write", "plast_strerror",
            "plast_last_error")
 
 TUNE_CLASSES = 4
@@ -150,6 +151,9 @@ def load():
         lib.plast_search_enqueue.argtypes = [BD, IV, ctypes.POINTER(UngappedParams), ctypes.POINTER(GappedParams),
                                              i64, P, sz, P, i64, P, P, P, P, i32, P, P]
         lib.plast_search_result.argtypes = [P, ctypes.POINTER(PipelineResult), ctypes.POINTER(i64), P]
+        lib.plast_translate_ws_bytes.argtypes = [i32, ctypes.POINTER(sz)]
+        lib.plast_translate_count.argtypes = [P, P, i32, i64, P, sz, ctypes.POINTER(i64), ctypes.POINTER(i64), P]
+        lib.plast_translate_write.argtypes = [P, P, i32, i64, P, sz, P, i64, P, P, i64, P]
         for f in EXPORTS[:-2]:
             getattr(lib, f).restype = ctypes.c_int
         lib.plast_strerror.argtypes = [ctypes.c_int]
@@ -511,3 +515,48 @@ class Searcher:
                "plast_search_result")
         return {"status": int(r.status), "n_items": int(r.n_items), "n_hits": int(r.n_hits), "n_ext": int(r.n_ext),
                 "n_words_a": int(r.n_words_a), "n_matches": int(nm.value)}
+
+
+def dna_to_device(dna, device="cuda"):
+    """Copy a nucleotide bank (numpy ``codes`` in 0..3, ``start``) to the device."""
+    codes = torch.from_numpy(np.ascontiguousarray(dna.codes, dtype=np.uint8)).to(device)
+    start = torch.from_numpy(np.ascontiguousarray(dna.start, dtype=np.int64)).to(device)
+    return codes, start
+
+
+class Translator:
+    """Six-frame translation of a device nucleotide bank (``plast_translate_*``):
+    ``run`` returns (codes uint8, seq_start int64, frag int32[n, 3]) device
+    tensors of the fragment bank; the workspace is kept for repeated calls."""
+
+    def __init__(self, dna_codes, dna_start):
+        self.dna, self.start = dna_codes, dna_start
+        self.n_dna = dna_start.numel() - 1
+        sz = ctypes.c_size_t(0)
+        _check(load().plast_translate_ws_bytes(self.n_dna, ctypes.byref(sz)), "plast_translate_ws_bytes")
+        self.ws = _alloc(sz.value, dna_codes.device)
+        self.out = None
+
+    def count(self, stream=None):
+        nf, npad = ctypes.c_int64(0), ctypes.c_int64(0)
+        _check(load().plast_translate_count(_ptr(self.dna), _ptr(self.start), self.n_dna, self.dna.numel(),
+                                            _ptr(self.ws), self.ws.numel(), ctypes.byref(nf), ctypes.byref(npad),
+                                            _stream(stream)), "plast_translate_count")
+        return nf.value, npad.value
+
+    def run(self, stream=None):
+        n_frags, n_padded = self.count(stream)
+        dev = self.dna.device
+        if self.out is None or self.out[0].numel() != n_padded or self.out[1].numel() != n_frags + 1:
+            self.out = (torch.empty(n_padded, dtype=torch.uint8, device=dev),
+                        torch.empty(n_frags + 1, dtype=torch.int64, device=dev),
+                        torch.empty((max(n_frags, 1), 3), dtype=torch.int32, device=dev))
+        codes, starts, frag = self.out
+        _check(load().plast_translate_write(_ptr(self.dna), _ptr(self.start), self.n_dna, self.dna.numel(),
+                                            _ptr(self.ws), self.ws.numel(), _ptr(codes), n_padded, _ptr(starts),
+                                            _ptr(frag), n_frags, _stream(stream)), "plast_translate_write")
+        return codes, starts, frag[:n_frags]
+
+
+def translate(dna_codes, dna_start, stream=None):
+    return Translator(dna_codes, dna_start).run(stream)

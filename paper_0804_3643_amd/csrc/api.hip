@@ -368,4 +368,42 @@ int plast_search_result(const void* d_ws, plast_pipeline_result_t* out, int64_t*
   return search_result_impl(d_ws, out, n_matches, (hipStream_t)stream);
 }
 
+int plast_translate_ws_bytes(int32_t n_dna, size_t* bytes) {
+  g_last_error[0] = 0;
+  if (!bytes || n_dna < 0 || n_dna > (1 << 28)) return set_error(PLAST_E_ARG, "null output or n_dna out of range");
+  *bytes = translate_ws_bytes(n_dna);
+  return PLAST_OK;
+}
+
+static int check_translate(const uint8_t* d_dna, const int64_t* d_dna_start, int32_t n_dna, int64_t n_nt, void* d_ws,
+                           size_t ws_bytes) {
+  if (!d_dna_start || !d_ws || (n_nt > 0 && !d_dna)) return set_error(PLAST_E_ARG, "null pointer");
+  if (n_dna < 0 || n_dna > (1 << 28) || n_nt < 0) return set_error(PLAST_E_ARG, "bad sizes");
+  if ((uintptr_t)d_ws & 255) return set_error(PLAST_E_ARG, "workspace must be 256-byte aligned");
+  if (ws_bytes < translate_ws_bytes(n_dna))
+    return set_error(PLAST_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, translate_ws_bytes(n_dna));
+  return PLAST_OK;
+}
+
+int plast_translate_count(const uint8_t* d_dna, const int64_t* d_dna_start, int32_t n_dna, int64_t n_nt, void* d_ws,
+                          size_t ws_bytes, int64_t* h_n_frags, int64_t* h_n_padded, void* stream) {
+  g_last_error[0] = 0;
+  int rc;
+  if ((rc = check_translate(d_dna, d_dna_start, n_dna, n_nt, d_ws, ws_bytes))) return rc;
+  if (!h_n_frags || !h_n_padded) return set_error(PLAST_E_ARG, "null output pointer");
+  return translate_count_impl(d_dna, d_dna_start, n_dna, n_nt, d_ws, h_n_frags, h_n_padded, (hipStream_t)stream);
+}
+
+int plast_translate_write(const uint8_t* d_dna, const int64_t* d_dna_start, int32_t n_dna, int64_t n_nt, void* d_ws,
+                          size_t ws_bytes, uint8_t* d_codes, int64_t n_padded, int64_t* d_seq_start, int32_t* d_frag,
+                          int64_t n_frags, void* stream) {
+  g_last_error[0] = 0;
+  int rc;
+  if ((rc = check_translate(d_dna, d_dna_start, n_dna, n_nt, d_ws, ws_bytes))) return rc;
+  if (!d_codes || !d_seq_start || (n_frags > 0 && !d_frag) || n_frags < 0 || n_padded < kPadLen * (n_frags + 1))
+    return set_error(PLAST_E_ARG, "null output or sizes not from plast_translate_count");
+  return translate_write_impl(d_dna, d_dna_start, n_dna, n_nt, d_ws, d_codes, n_padded, d_seq_start, d_frag, n_frags,
+                              (hipStream_t)stream);
+}
+
 }  // extern "C"

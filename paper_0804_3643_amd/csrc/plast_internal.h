@@ -173,4 +173,12 @@ int search_enqueue_impl(const plast_bank_t* a, const plast_index_t* b, const pla
                         const int32_t* d_seg_first, int32_t n_seg, int64_t* d_seg_off, hipStream_t s);
 int search_result_impl(const void* d_ws, plast_pipeline_result_t* out, int64_t* n_matches, hipStream_t s);
 
+// ---------------------------------------------------------------- six-frame translation
+size_t translate_ws_bytes(int32_t n_dna);
+int translate_count_impl(const uint8_t* d_dna, const int64_t* d_dna_start, int32_t n_dna, int64_t n_nt, void* d_ws,
+                         int64_t* h_n_frags, int64_t* h_n_padded, hipStream_t s);
+int translate_write_impl(const uint8_t* d_dna, const int64_t* d_dna_start, int32_t n_dna, int64_t n_nt, void* d_ws,
+                         uint8_t* d_codes, int64_t n_padded, int64_t* d_seq_start, int32_t* d_frag, int64_t n_frags,
+                         hipStream_t s);
+
 }  // namespace plast

@@ -198,3 +198,20 @@ def test_product_code_never_touches_the_oracle():
                 src = open(os.path.join(dirpath, f)).read()
                 assert not re.search(r"^\s*(from|import)\s+oracle", src, re.M), f
                 assert "plast_oracle" not in src and "coracle" not in src, f
+
+
+def test_translate_validation_without_gpu():
+    lib = binding.load()
+    sz = ctypes.c_size_t(0)
+    assert lib.plast_translate_ws_bytes(10, ctypes.byref(sz)) == binding.OK and sz.value >= 256 + 2 * 8 * 61
+    assert lib.plast_translate_ws_bytes(-1, ctypes.byref(sz)) == binding.E_ARG
+    fake, odd = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1010)
+    nf, npad = ctypes.c_int64(0), ctypes.c_int64(0)
+    assert lib.plast_translate_count(fake, None, 10, 100, fake, 1 << 20, ctypes.byref(nf), ctypes.byref(npad),
+                                     None) == binding.E_ARG
+    assert lib.plast_translate_count(fake, fake, 10, 100, odd, 1 << 20, ctypes.byref(nf), ctypes.byref(npad),
+                                     None) == binding.E_ARG
+    assert lib.plast_translate_count(fake, fake, 10, 100, fake, 16, ctypes.byref(nf), ctypes.byref(npad),
+                                     None) == binding.E_WORKSPACE
+    assert lib.plast_translate_write(fake, fake, 10, 100, fake, 1 << 20, fake, 10, fake, fake, 5,
+                                     None) == binding.E_ARG   # n_padded too small for 5 fragments
