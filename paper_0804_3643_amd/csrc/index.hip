@@ -1,7 +1,8 @@
 // Stage 0, bank indexing (Sec. 3.3.1): subset-seed key of every word, then a
 // stable counting sort by key into CSR form (key_off, occ, occ_seq).
 //
-// Layout: the bank is cut into contiguous position chunks, one wavefront each.
+// Layout: the bank is cut into contiguous position chunks (about 16K
+// positions, at most 16384 chunks), one wavefront each.
 // Pass 1 counts keys per chunk in LDS (8800 counters) and writes them key-major,
 // an exclusive scan over (key, chunk) gives every chunk its first slot in each
 // key's run, and pass 2 re-reads the chunk and scatters positions in order.
@@ -51,30 +52,50 @@ __global__ void k_layout_check(const int64_t* __restrict__ seq_start, int32_t n_
   if (bad) atomicOr(err, 1);
 }
 
-// Wavefront w checks the separator run before the first sequence (w == 0) or
-// sequence w-1 plus the run after it, and writes scan_codes for those bytes.
-__global__ void k_codes_check(const uint8_t* __restrict__ codes, const int64_t* __restrict__ seq_start,
-                              int32_t n_seqs, int64_t n_padded, uint8_t* __restrict__ scan,
-                              int64_t scan_len, int32_t* __restrict__ err) {
-  int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
-  int lane = lane_id();
-  if (w > n_seqs || (*err & 1)) return;  // no walk over a bad layout
+// Validation and scan codes, position-parallel (so that banks of many short
+// sequences, such as translated fragments, keep every lane busy).  Each
+// wavefront takes kCheckChunk consecutive positions of [0, scan_len): it finds
+// the sequence holding its first position by binary search, then walks its
+// positions in order.  Position p is a residue iff some sequence s has
+// seq_start[s] <= p < seq_start[s + 1] - kPadLen; every other position below
+// n_padded must hold the separator code, and the tail slack is set to it.
+constexpr int64_t kCheckChunk = 4096;
+
+__global__ __launch_bounds__(kChunkWave) void k_codes_check(const uint8_t* __restrict__ codes,
+                                                            const int64_t* __restrict__ seq_start, int32_t n_seqs,
+                                                            int64_t n_padded, uint8_t* __restrict__ scan,
+                                                            int64_t scan_len, int32_t* __restrict__ err) {
+  if (*err & 1) return;  // no walk over a bad layout
+  const int lane = lane_id();
+  const int64_t beg = (int64_t)blockIdx.x * kCheckChunk;
+  const int64_t end = min(beg + kCheckChunk, scan_len);
+  // s_cur: the last sequence with seq_start <= beg (-1 before the first one)
+  int lo = -1, hi = n_seqs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (seq_start[mid] <= beg) lo = mid; else hi = mid - 1;
+  }
+  int s_cur = lo;
   bool bad = false;
-  if (w == 0) {
-    for (int64_t p = lane; p < kPadLen; p += 64) {
-      uint8_t c = codes[p];
-      bad |= c != kPadCode;
-      scan[p] = (uint8_t)(kPadCode * kScale);
+  for (int64_t base = beg; base < end; base += 64) {
+    const int64_t p = base + lane;
+    // at most 4 sequence starts in a window (each sequence takes >= kPadLen
+    // positions): lanes 0..7 load the next 8 and every lane counts its own
+    const int64_t nxt = (lane < 8 && s_cur + 1 + lane < n_seqs) ? seq_start[s_cur + 1 + lane] : INT64_MAX;
+    int s = s_cur;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s += p >= __shfl(nxt, j) ? 1 : 0;
+    if (p < end) {
+      if (p < n_padded) {
+        const bool residue = s >= 0 && p < seq_start[s + 1] - kPadLen;
+        const uint8_t c = codes[p];
+        bad |= residue ? (c >= 20) : (c != kPadCode);
+        scan[p] = (uint8_t)((residue && c < 20 ? c : kPadCode) * kScale);
+      } else {
+        scan[p] = (uint8_t)(kPadCode * kScale);
+      }
     }
-    for (int64_t p = n_padded + lane; p < scan_len; p += 64) scan[p] = (uint8_t)(kPadCode * kScale);
-  } else {
-    int64_t beg = seq_start[w - 1], nxt = seq_start[w], end = nxt - kPadLen;
-    for (int64_t p = beg + lane; p < nxt; p += 64) {
-      uint8_t c = codes[p];
-      bool residue = p < end;
-      bad |= residue ? (c >= 20) : (c != kPadCode);
-      scan[p] = (uint8_t)((residue ? (c < 20 ? c : kPadCode) : kPadCode) * kScale);
-    }
+    s_cur = __shfl(s, 63);
   }
   if (bad) atomicOr(err, 2);
 }
@@ -88,8 +109,11 @@ __global__ __launch_bounds__(kChunkWave) void k_index_count(const uint8_t* __res
   __syncthreads();
   const int64_t beg = (int64_t)blockIdx.x * chunk;
   const int64_t end = min(beg + chunk, n_padded - (kSeed - 1));
+  // the next window's letters are loaded one window ahead
+  int key_next = beg < end ? word_key(codes, beg + lane, end, sc) : -1;
   for (int64_t base = beg; base < end; base += 64) {
-    int key = word_key(codes, base + lane, end, sc);
+    const int key = key_next;
+    key_next = word_key(codes, base + 64 + lane, end, sc);
     uint64_t peers = peers_of(key, key >= 0);
     if (key >= 0 && lane == 63 - __clzll(peers)) cnt[key] += __popcll(peers);
   }
@@ -118,11 +142,18 @@ __global__ __launch_bounds__(kChunkWave) void k_index_scatter(const uint8_t* __r
     if (seq_start[mid] <= beg) lo = mid; else hi = mid - 1;
   }
   int s_cur = lo;
+  int key_next = beg < end ? word_key(codes, beg + lane, end, sc) : -1;  // one window ahead
   for (int64_t base = beg; base < end; base += 64) {
     int64_t q = base + lane;
-    int key = word_key(codes, q, end, sc);
+    const int key = key_next;
+    key_next = word_key(codes, q + 64, end, sc);
+    // Every sequence takes at least kPadLen positions (its separator run), so
+    // a 64-position window meets at most 5 sequence starts: lanes 0..7 load the
+    // next 8 starts at once and every lane counts those at or before q.
+    const int64_t nxt = (lane < 8 && s_cur + 1 + lane < n_seqs) ? seq_start[s_cur + 1 + lane] : INT64_MAX;
     int s = s_cur;
-    while (s + 1 < n_seqs && q >= seq_start[s + 1]) ++s;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s += q >= __shfl(nxt, j) ? 1 : 0;
     uint64_t peers = peers_of(key, key >= 0);
     if (key >= 0) {
       int rank = __popcll(peers & ((1ull << lane) - 1ull));
@@ -254,9 +285,13 @@ IndexLayout index_layout(int64_t n_padded) {
   return L;
 }
 
+// About 16K positions per wavefront, up to 16384 wavefronts (the per-chunk key
+// counts then take 8800 x 16384 x 4 bytes of scratch at most).
+constexpr int64_t kMaxChunks = 16384;
+
 IndexChunks index_chunks(int64_t n_padded) {
   int64_t nch = (n_padded + 16383) / 16384;
-  nch = nch < 1 ? 1 : (nch > 2048 ? 2048 : nch);
+  nch = nch < 1 ? 1 : (nch > kMaxChunks ? kMaxChunks : nch);
   int64_t chunk = (n_padded + nch - 1) / nch;
   chunk = (chunk + 63) / 64 * 64;
   if (chunk < 64) chunk = 64;
@@ -297,9 +332,8 @@ int index_enqueue(const uint8_t* d_codes, const int64_t* d_seq_start, int32_t n_
   hipLaunchKernelGGL(k_clear2, dim3(1), dim3(64), 0, stream, d_err);
   hipLaunchKernelGGL(k_layout_check, dim3((unsigned)((n_seqs + 1 + 255) / 256)), dim3(256), 0, stream, d_seq_start,
                      n_seqs, n_padded, d_err);
-  int64_t waves = (int64_t)n_seqs + 1;
-  hipLaunchKernelGGL(k_codes_check, dim3((unsigned)((waves * 64 + 255) / 256)), dim3(256), 0, stream, d_codes,
-                     d_seq_start, n_seqs, n_padded, scan, scan_len, d_err);
+  hipLaunchKernelGGL(k_codes_check, dim3((unsigned)((scan_len + kCheckChunk - 1) / kCheckChunk)), dim3(kChunkWave), 0,
+                     stream, d_codes, d_seq_start, n_seqs, n_padded, scan, scan_len, d_err);
   // Counting and scattering read seq_start only as bounds of a search over
   // [0, n_seqs), so they stay in bounds after a layout error.
   hipLaunchKernelGGL(k_index_count, dim3((unsigned)C.nchunks), dim3(kChunkWave), 0, stream, d_codes, n_padded,

@@ -499,3 +499,55 @@ def make_tplastn(n_proteins: int = 5000, n_dna: int = 2000, dna_len=(50_000, 200
                            "TPLAST-N: %d proteins vs %d DNA sequences of %d-%d nt (GC %.0f%%), %d planted homologs "
                            "at %.0f%% identity" % (n1, nd, dna_len[0], dna_len[1], 100 * gc, len(plants),
                                                    100 * identity))
+
+
+@dataclasses.dataclass
+class PlastxWorkload:
+    dna1: DnaBank
+    dna2: DnaBank
+    plants: list        # (DnaPlant in dna1, DnaPlant in dna2) of each homolog pair
+    description: str
+
+
+def _plant_coding(seqs, prot, rng, syn, d):
+    coding = np.concatenate([syn[a][int(rng.integers(len(syn[a])))] for a in prot])
+    if len(coding) == 0 or len(coding) > len(seqs[d]):
+        return None
+    off = int(rng.integers(0, len(seqs[d]) - len(coding) + 1))
+    strand = 1 if rng.random() < 0.5 else -1
+    seqs[d][off:off + len(coding)] = coding if strand > 0 else (3 - coding)[::-1]
+    return DnaPlant(-1, d, strand, off, len(prot))
+
+
+def make_plastx(n_dna1: int = 200, n_dna2: int = 1000, dna_len=(20_000, 50_000), n_plants: int = 50,
+                identity: float = 0.40, gc: float = 0.40, scale: float = 1.0) -> PlastxWorkload:
+    """PLAST-X (both banks nucleotide): two random DNA banks (GC content
+    ``gc``) sharing ``n_plants`` homologous coding regions: a random protein
+    with configuration 0's length distribution, reverse-translated with random
+    synonymous codons into bank 1, and a copy mutated at ``identity``
+    reverse-translated into bank 2, each at a random offset on a random strand.
+    Streams: SeedSequence(651305).spawn(6)."""
+    ss = np.random.SeedSequence(651300 + 5).spawn(6)
+    r_len, r_res, r_dna, r_plant, r_mut, r_indel = [np.random.Generator(np.random.PCG64(s)) for s in ss]
+    n1, n2 = max(1, int(round(n_dna1 * scale))), max(1, int(round(n_dna2 * scale)))
+    p_nt = np.array([(1 - gc) / 2, gc / 2, gc / 2, (1 - gc) / 2])
+
+    def bank(n):
+        dl = r_dna.integers(dna_len[0], dna_len[1] + 1, size=n)
+        return _split(r_dna.choice(4, size=int(dl.sum()), p=p_nt).astype(np.uint8), dl)
+
+    d1, d2 = bank(n1), bank(n2)
+    syn = synonym_codons()
+    subst = _substitution_probs()
+    plants = []
+    for L in _lengths(r_len, n_plants):
+        prot = r_res.choice(20, size=int(L), p=BACKGROUND).astype(np.uint8)
+        hom, _, _ = _mutate(prot, identity, r_mut, r_indel, subst)
+        a = _plant_coding(d1, prot, r_plant, syn, int(r_plant.integers(n1)))
+        b = _plant_coding(d2, hom, r_plant, syn, int(r_plant.integers(n2)))
+        if a is not None and b is not None:
+            plants.append((a, b))
+    return PlastxWorkload(DnaBank.from_seqs(d1), DnaBank.from_seqs(d2), plants,
+                          "PLAST-X: %d x %d DNA sequences of %d-%d nt (GC %.0f%%), %d planted homologous coding "
+                          "regions at %.0f%% identity" % (n1, n2, dna_len[0], dna_len[1], 100 * gc, len(plants),
+                                                          100 * identity))

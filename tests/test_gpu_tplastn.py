@@ -100,3 +100,38 @@ def test_tplastn_search_matches_oracle_and_finds_plants(B):
                 found += 1
                 break
     assert found >= 0.9 * len(w.plants), (found, len(w.plants))
+
+
+def test_plastx_search_matches_oracle_and_finds_plants(B):
+    """PLAST-X: both banks translated on the device (6 x 6 frame pairs through
+    one search); hits and gapped scores equal the oracle's on the oracle's
+    translations, and planted homologous coding regions are found."""
+    _say("plastx small workload")
+    w = synth.make_plastx(scale=0.05, dna_len=(3000, 20000), n_plants=20)
+    ref1, t1 = _check_translation(B, w.dna1)
+    ref2, t2 = _check_translation(B, w.dna2)
+    c1, s1, _ = B.translate(*B.dna_to_device(w.dna1, "cuda"))
+    c2, s2, _ = B.translate(*B.dna_to_device(w.dna2, "cuda"))
+    ia, ib = B.build_index(c1, s1), B.build_index(c2, s2)
+    hits, n_ext = B.ungapped_extend(ia, ib, params.S1, mode="batched")
+    ref, ref_ext = C.ungapped_hits(ref1, ref2, params.S1)
+    assert n_ext == ref_ext and np.array_equal(B.canonical_hits(hits), ref)
+    gs, ps = B.gapped_filter(ia, ib, hits, params.S2)
+    h = hits.cpu().numpy().astype(np.int64)
+    assert np.array_equal(gs.cpu().numpy().astype(np.int64), C.gapped_scores(ref1, ref2, h))
+    passing = h[ps.cpu().numpy().astype(bool)]
+    L1 = np.diff(w.dna1.start)
+    L2 = np.diff(w.dna2.start)
+    found = 0
+    for a, b in w.plants:
+        for s1_, p1, s2_, p2, _ in passing:
+            d1, f1, o1 = t1[s1_]
+            d2, f2, o2 = t2[s2_]
+            if d1 != a.dna or d2 != b.dna or (f1 < 3) != (a.strand > 0) or (f2 < 3) != (b.strand > 0):
+                continue
+            n1 = O.frame_position(int(L1[d1]), int(f1), int(o1 + p1))
+            n2 = O.frame_position(int(L2[d2]), int(f2), int(o2 + p2))
+            if a.offset <= n1 < a.offset + 3 * a.n_codons and b.offset <= n2 < b.offset + 3 * b.n_codons:
+                found += 1
+                break
+    assert found >= 0.85 * len(w.plants), (found, len(w.plants))
