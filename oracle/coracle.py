@@ -44,6 +44,8 @@ def load():
                                      i32, P, i64, P]
         lib.orc_gapped.restype = None
         lib.orc_gapped.argtypes = [P, P, P, P, i32, P, i64, P, i32, i32, i32, i32, i32, P]
+        lib.orc_full_align.restype = i64
+        lib.orc_full_align.argtypes = [P, P, P, P, i32, P, P, P, i64, P, i32, i32, i32, P, P]
         _lib = lib
     return _lib
 
@@ -113,3 +115,26 @@ def gapped_scores(bank1, bank2, hits, window=O.GAP_WINDOW, band=O.GAP_BAND, gap_
     lib.orc_gapped(_ptr(c1), _ptr(st1), _ptr(c2), _ptr(st2), PAD, _ptr(h), len(h), _ptr(mat), int(window),
                    int(band), int(gap_open), int(gap_extend), int(nthreads or os.cpu_count() or 1), _ptr(g))
     return g.astype(np.int64)
+
+
+def full_alignments(bank1, bank2, hits, gscore, passed, gap_open=O.GAP_OPEN, gap_extend=O.GAP_EXTEND,
+                    matrix=O.BLOSUM62, nthreads=None):
+    """Stage 3.2, same contract as ``plast_oracle.full_alignments``: records
+    (int64, columns ALIGN_FIELDS, canonical order) and cover (int64[n])."""
+    lib = load()
+    c1, st1 = _bank_arrays(bank1)
+    c2, st2 = _bank_arrays(bank2)
+    h = np.ascontiguousarray(np.asarray(hits, dtype=np.int32).reshape(-1, 5))
+    g = np.ascontiguousarray(np.asarray(gscore, dtype=np.int32).reshape(-1))
+    ps = np.ascontiguousarray(np.asarray(passed).reshape(-1).astype(np.uint8))
+    n = len(h)
+    out = np.zeros((max(1, n), len(O.ALIGN_FIELDS)), dtype=np.int32)
+    cover = np.zeros(max(1, n), dtype=np.int32)
+    mat = _matrix(matrix)
+    m = lib.orc_full_align(_ptr(c1), _ptr(st1), _ptr(c2), _ptr(st2), PAD, _ptr(h), _ptr(g), _ptr(ps), n,
+                           _ptr(mat), int(gap_open), int(gap_extend), int(nthreads or os.cpu_count() or 1),
+                           _ptr(out), _ptr(cover))
+    rec = out[:m].astype(np.int64)
+    if m:
+        rec = rec[np.lexsort(rec.T[::-1])]
+    return rec, cover[:n].astype(np.int64)

@@ -302,3 +302,276 @@ void orc_gapped(const uint8_t* codes1, const int64_t* start1, const uint8_t* cod
   for (int t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
   free(th);
 }
+
+/* ------------------------------------------------------ full gapped alignment */
+
+/* Stage 3.2 (Sec. 3.3.4): the hits that pass S2 get a full gapped alignment;
+ * a list of the ungapped pieces (diagonal, first and one-past-last position in
+ * sequence 1) of the alignments already computed for a sequence pair lets a
+ * hit lying on one of them skip its own.
+ *
+ * One side: the anchored affine-gap recurrences of orc_gapped_side with no band
+ * and no window.  best = max over cells of H (H(0,0) = 0); the end cell is the
+ * first cell in row-major order with H == best.  Trace-back preferences: state
+ * H came from the diagonal if that gives H, else from E, else from F; state E
+ * (F) came from a gap opening if that gives its value, else from an extension. */
+
+typedef struct {
+  int* H;
+  int* E;
+  int* F;
+  size_t cap;
+  char* moves; /* from the end cell back to the anchor */
+  size_t mcap;
+} orc_dp_t;
+
+static void orc_dp_reserve(orc_dp_t* D, int lx, int ly) {
+  size_t need = (size_t)(lx + 1) * (size_t)(ly + 1);
+  if (need > D->cap) {
+    free(D->H);
+    free(D->E);
+    free(D->F);
+    D->H = (int*)malloc(sizeof(int) * need);
+    D->E = (int*)malloc(sizeof(int) * need);
+    D->F = (int*)malloc(sizeof(int) * need);
+    D->cap = need;
+  }
+  if ((size_t)(lx + ly + 1) > D->mcap) {
+    free(D->moves);
+    D->mcap = (size_t)(lx + ly + 1);
+    D->moves = (char*)malloc(D->mcap);
+  }
+}
+
+/* Returns best; *n_moves moves in D->moves, in order from the end cell back to
+ * the anchor ('D' pair, 'E' letter of y against a gap, 'F' letter of x). */
+static int orc_full_side(orc_dp_t* D, const uint8_t* x, int lx, int dx, const uint8_t* y, int ly, int dy,
+                         const int8_t* mat, int open, int ext, int* n_moves) {
+  orc_dp_reserve(D, lx, ly);
+  int W1 = ly + 1;
+  int *H = D->H, *E = D->E, *F = D->F;
+  int best = 0, bi = 0, bj = 0;
+  for (int i = 0; i <= lx; ++i) {
+    for (int j = 0; j <= ly; ++j) {
+      int c = i * W1 + j;
+      H[c] = E[c] = F[c] = ORC_NEG;
+      if (i == 0 && j == 0) {
+        H[c] = 0;
+        continue;
+      }
+      if (j >= 1) {
+        int e1 = E[c - 1] - ext, e2 = H[c - 1] - open - ext;
+        E[c] = e1 > e2 ? e1 : e2;
+      }
+      if (i >= 1) {
+        int f1 = F[c - W1] - ext, f2 = H[c - W1] - open - ext;
+        F[c] = f1 > f2 ? f1 : f2;
+      }
+      int h = ORC_NEG;
+      if (i >= 1 && j >= 1) h = H[c - W1 - 1] + mat[x[(i - 1) * dx] * 20 + y[(j - 1) * dy]];
+      if (E[c] > h) h = E[c];
+      if (F[c] > h) h = F[c];
+      if (h < ORC_NEG) h = ORC_NEG;
+      H[c] = h;
+      if (h > best) {
+        best = h;
+        bi = i;
+        bj = j;
+      }
+    }
+  }
+  int i = bi, j = bj, n = 0;
+  char state = 'H';
+  while (i > 0 || j > 0) {
+    int c = i * W1 + j;
+    if (state == 'H') {
+      if (i >= 1 && j >= 1 && H[c] == H[c - W1 - 1] + mat[x[(i - 1) * dx] * 20 + y[(j - 1) * dy]]) {
+        D->moves[n++] = 'D';
+        --i;
+        --j;
+        continue;
+      }
+      state = H[c] == E[c] ? 'E' : 'F';
+    } else if (state == 'E') {
+      D->moves[n++] = 'E';
+      state = E[c] == H[c - 1] - open - ext ? 'H' : 'E';
+      --j;
+    } else {
+      D->moves[n++] = 'F';
+      state = F[c] == H[c - W1] - open - ext ? 'H' : 'F';
+      --i;
+    }
+  }
+  *n_moves = n;
+  return best;
+}
+
+typedef struct {
+  int32_t diag, first, last, owner; /* pairs on diagonal diag at positions [first, last) of sequence 1 */
+} orc_piece_t;
+
+typedef struct {
+  const orc_bank_t *A, *B;
+  const int32_t* hits;
+  const int32_t* gscore;
+  const int64_t* order; /* passing hits sorted by (seq1, seq2, -gscore, pos1, pos2) */
+  const int64_t* group; /* group g = order[group[g] .. group[g + 1]) */
+  int64_t n_groups;
+  const int8_t* mat;
+  int32_t open, ext;
+  int32_t* out; /* 14 int32 per alignment */
+  int32_t* cover;
+  int64_t next, n_out;
+} orc_ajob_t;
+
+/* Walks one side's moves from the anchor outward (moves[] is stored end-first),
+ * appending pieces; step +1 pairs a[p1 + i] with b[p2 + j], step -1 pairs
+ * a[p1 - 1 - i] with b[p2 - 1 - j].  Adds identities, mismatches and gap
+ * openings to st[0..2]; returns the letters consumed in st[3] (x) and st[4] (y). */
+static void orc_side_walk(const uint8_t* a, int p1, const uint8_t* b, int p2, const char* moves, int n, int step,
+                          int32_t owner, orc_piece_t** pieces, int64_t* np, int64_t* pcap, int st[5]) {
+  int i = 0, j = 0, open_run = 0;
+  char prev = 0;
+  for (int k = n - 1; k >= 0; --k) {
+    char m = moves[k];
+    if (m == 'D') {
+      int pa = step > 0 ? p1 + i : p1 - 1 - i;
+      int pb = step > 0 ? p2 + j : p2 - 1 - j;
+      if (a[pa] == b[pb]) st[0]++;
+      else st[1]++;
+      if (!open_run) {
+        if (*np == *pcap) {
+          *pcap = *pcap ? 2 * *pcap : 64;
+          *pieces = (orc_piece_t*)realloc(*pieces, sizeof(orc_piece_t) * (size_t)*pcap);
+        }
+        orc_piece_t* q = &(*pieces)[(*np)++];
+        q->diag = pa - pb;
+        q->first = pa;
+        q->last = pa + 1;
+        q->owner = owner;
+        open_run = 1;
+      } else {
+        orc_piece_t* q = &(*pieces)[*np - 1];
+        if (step > 0) q->last = pa + 1;
+        else q->first = pa;
+      }
+      ++i;
+      ++j;
+    } else {
+      open_run = 0;
+      if (m != prev) st[2]++;
+      if (m == 'E') ++j;
+      else ++i;
+    }
+    prev = m;
+  }
+  st[3] = i;
+  st[4] = j;
+}
+
+static void* orc_aworker(void* arg) {
+  orc_ajob_t* J = (orc_ajob_t*)arg;
+  orc_dp_t D = {0};
+  orc_piece_t* pieces = NULL;
+  int64_t pcap = 0;
+  for (;;) {
+    int64_t g = __atomic_fetch_add(&J->next, 1, __ATOMIC_RELAXED);
+    if (g >= J->n_groups) break;
+    int64_t np = 0;
+    for (int64_t k = J->group[g]; k < J->group[g + 1]; ++k) {
+      int64_t h = J->order[k];
+      const int32_t* r = J->hits + 5 * h;
+      int32_t s1 = r[0], p1 = r[1], s2 = r[2], p2 = r[3];
+      int32_t owner = -1;
+      for (int64_t q = 0; q < np && owner < 0; ++q)
+        if (pieces[q].diag == p1 - p2 && pieces[q].first <= p1 && p1 < pieces[q].last) owner = pieces[q].owner;
+      if (owner >= 0) {
+        J->cover[h] = owner;
+        continue;
+      }
+      J->cover[h] = (int32_t)h;
+      const uint8_t* a = J->A->codes + J->A->seq_start[s1];
+      const uint8_t* b = J->B->codes + J->B->seq_start[s2];
+      int la = (int)orc_len(J->A->seq_start, J->A->pad, s1), lb = (int)orc_len(J->B->seq_start, J->B->pad, s2);
+      int nmR, nmL, stR[5] = {0}, stL[5] = {0};
+      int bR = orc_full_side(&D, a + p1, la - p1, 1, b + p2, lb - p2, 1, J->mat, J->open, J->ext, &nmR);
+      orc_side_walk(a, p1, b, p2, D.moves, nmR, +1, (int32_t)h, &pieces, &np, &pcap, stR);
+      int bL = orc_full_side(&D, a + p1 - 1, p1, -1, b + p2 - 1, p2, -1, J->mat, J->open, J->ext, &nmL);
+      orc_side_walk(a, p1, b, p2, D.moves, nmL, -1, (int32_t)h, &pieces, &np, &pcap, stL);
+      int64_t o = __atomic_fetch_add(&J->n_out, 1, __ATOMIC_RELAXED);
+      int32_t* w = J->out + 14 * o;
+      w[0] = s1;
+      w[1] = s2;
+      w[2] = p1;
+      w[3] = p2;
+      w[4] = p1 - stL[3];
+      w[5] = p1 + stR[3];
+      w[6] = p2 - stL[4];
+      w[7] = p2 + stR[4];
+      w[8] = bR + bL;
+      w[9] = nmR + nmL;
+      w[10] = stR[0] + stL[0];
+      w[11] = stR[1] + stL[1];
+      w[12] = stR[2] + stL[2];
+      w[13] = (int32_t)h;
+    }
+  }
+  free(D.H);
+  free(D.E);
+  free(D.F);
+  free(D.moves);
+  free(pieces);
+  return NULL;
+}
+
+static const int32_t* orc_sort_hits;
+static const int32_t* orc_sort_gscore;
+
+static int orc_cmp_hit(const void* pa, const void* pb) {
+  int64_t a = *(const int64_t*)pa, b = *(const int64_t*)pb;
+  const int32_t *x = orc_sort_hits + 5 * a, *y = orc_sort_hits + 5 * b;
+  if (x[0] != y[0]) return x[0] < y[0] ? -1 : 1;
+  if (x[2] != y[2]) return x[2] < y[2] ? -1 : 1;
+  if (orc_sort_gscore[a] != orc_sort_gscore[b]) return orc_sort_gscore[a] > orc_sort_gscore[b] ? -1 : 1;
+  if (x[1] != y[1]) return x[1] < y[1] ? -1 : 1;
+  if (x[3] != y[3]) return x[3] < y[3] ? -1 : 1;
+  return 0;
+}
+
+/* Full gapped alignments of the hits with pass[h] != 0.  out holds up to n
+ * records of 14 int32 (seq1, seq2, seed1, seed2, start1, end1, start2, end2,
+ * score, length, identities, mismatches, gap openings, hit), in no particular
+ * order; cover[h] = the hit whose alignment covers h (h itself when it computed
+ * one), -1 when h did not pass.  Returns the number of records. */
+int64_t orc_full_align(const uint8_t* codes1, const int64_t* start1, const uint8_t* codes2, const int64_t* start2,
+                       int32_t pad, const int32_t* hits, const int32_t* gscore, const uint8_t* pass, int64_t n,
+                       const int8_t* mat, int32_t open, int32_t ext, int32_t nthreads, int32_t* out,
+                       int32_t* cover) {
+  orc_bank_t A = {codes1, start1, 0, pad, 0, 0, 0};
+  orc_bank_t B = {codes2, start2, 0, pad, 0, 0, 0};
+  int64_t* order = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  int64_t m = 0;
+  for (int64_t h = 0; h < n; ++h) {
+    cover[h] = -1;
+    if (pass[h]) order[m++] = h;
+  }
+  orc_sort_hits = hits;
+  orc_sort_gscore = gscore;
+  qsort(order, (size_t)m, sizeof(int64_t), orc_cmp_hit);
+  int64_t* group = (int64_t*)malloc(sizeof(int64_t) * (size_t)(m + 1));
+  int64_t ng = 0;
+  for (int64_t k = 0; k < m; ++k) {
+    const int32_t *x = hits + 5 * order[k], *y = k ? hits + 5 * order[k - 1] : NULL;
+    if (!y || x[0] != y[0] || x[2] != y[2]) group[ng++] = k;
+  }
+  group[ng] = m;
+  orc_ajob_t J = {&A, &B, hits, gscore, order, group, ng, mat, open, ext, out, cover, 0, 0};
+  if (nthreads < 1) nthreads = 1;
+  pthread_t* th = (pthread_t*)malloc(sizeof(pthread_t) * nthreads);
+  for (int t = 0; t < nthreads; ++t) pthread_create(&th[t], NULL, orc_aworker, &J);
+  for (int t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
+  free(th);
+  free(order);
+  free(group);
+  return J.n_out;
+}

@@ -27,12 +27,20 @@ What is computed (paper section in brackets)
   either side of the seed): an anchored, banded affine-gap alignment rightward
   from the seed start and another leftward from the letters just before it,
   each over at most G letters per sequence, cells restricted to |i - j| <= band;
-  gapped score = best right + best left, pass iff >= S2.
+  gapped score = best right + best left, pass iff >= S2;
+* full gapped alignment (Sec. 3.3.4 stage 3.2 and its list of the ungapped
+  pieces of computed alignments): for the hits that pass S2, the same anchored
+  affine-gap recurrences with no band and no window, traced back; a hit lying
+  on a piece of an alignment already computed for its sequence pair is
+  covered and computes nothing.
 
 Readings taken where the paper is silent or garbled: the seed table's rows 1
 and 4 list every letter (I is missing in the text), row 3's class f is
 {F,Y,W}, N = 20, hits are score >= S1, no X-drop, gapped window G = 64, band
-16, a gap of length k costs 11 + k.
+16, a gap of length k costs 11 + k.  Stage 3.2 (the paper asks only for a
+standard dynamic-programming alignment): no X-drop, the survivors of one sequence pair
+in order of decreasing gapped score then seed position, end cell and path
+chosen by the fixed preferences given in :func:`full_side`.
 * six-frame translation (Sec. 6, TPLAST-N; the paper gives no details): the
   standard genetic code; frames 0..2 start at nucleotides 0..2 of the forward
   strand, frames 3..5 at nucleotides 0..2 of the reverse complement; a
@@ -381,6 +389,185 @@ def _gapped_vec(X, Y, lx, ly, window, band, gap_open, gap_extend, mat):
             best = np.where(exists, np.maximum(best, h), best)
         Hprev, Fprev = Hcur, Fcur
     return best
+
+
+# --------------------------------------------------------------------------- full gapped alignment (stage 3.2)
+
+def full_side(x, y, gap_open=GAP_OPEN, gap_extend=GAP_EXTEND, matrix=BLOSUM62):
+    """One-sided full gapped extension (Sec. 3.3.4, stage 3-2): the anchored
+    affine-gap recurrences of :func:`gapped_side` over the whole of x and y, with
+    no band and no window, plus the end cell and the path that reaches it.
+
+    Cell (i, j) covers the first i letters of x and the first j of y; H(0, 0) = 0.
+    best = max over all cells of H (so >= 0); the end cell is the first cell in
+    row-major order (smallest i, then smallest j) whose H equals best.
+    The path is traced back from the end cell with fixed preferences: a cell in
+    state H came from the diagonal if that gives H, else from E, else from F; a
+    cell in state E (or F) came from a gap opening (H of the left / upper cell
+    minus open + extend) if that gives its value, else from an extension.
+    Row 0 is one gap in x (state E) and column 0 one gap in y (state F).
+
+    Returns (best, (i_end, j_end), moves) with moves read from the anchor outward:
+    'D' pairs x[i] with y[j], 'E' puts y[j] against a gap, 'F' puts x[i] against a gap.
+    """
+    lx, ly = len(x), len(y)
+    NEG = -(1 << 40)
+    oe = gap_open + gap_extend
+    H = [[NEG] * (ly + 1) for _ in range(lx + 1)]
+    E = [[NEG] * (ly + 1) for _ in range(lx + 1)]
+    F = [[NEG] * (ly + 1) for _ in range(lx + 1)]
+    H[0][0] = 0
+    best, end = 0, (0, 0)
+    for i in range(lx + 1):
+        for j in range(ly + 1):
+            if i == 0 and j == 0:
+                continue
+            if j >= 1:
+                E[i][j] = max(E[i][j - 1] - gap_extend, H[i][j - 1] - oe)
+            if i >= 1:
+                F[i][j] = max(F[i - 1][j] - gap_extend, H[i - 1][j] - oe)
+            d = H[i - 1][j - 1] + int(matrix[x[i - 1], y[j - 1]]) if i >= 1 and j >= 1 else NEG
+            H[i][j] = max(d, E[i][j], F[i][j])
+            if H[i][j] > best:
+                best, end = H[i][j], (i, j)
+    moves = []
+    i, j = end
+    state = "H"
+    while i > 0 or j > 0:
+        if state == "H":
+            if i >= 1 and j >= 1 and H[i][j] == H[i - 1][j - 1] + int(matrix[x[i - 1], y[j - 1]]):
+                moves.append("D")
+                i, j = i - 1, j - 1
+                continue
+            state = "E" if H[i][j] == E[i][j] else "F"
+        elif state == "E":
+            moves.append("E")
+            state = "H" if E[i][j] == H[i][j - 1] - oe else "E"
+            j -= 1
+        else:
+            moves.append("F")
+            state = "H" if F[i][j] == H[i - 1][j] - oe else "F"
+            i -= 1
+    return best, end, moves[::-1]
+
+
+def path_score(x, y, moves, gap_open=GAP_OPEN, gap_extend=GAP_EXTEND, matrix=BLOSUM62):
+    """Score of an anchored path: substitution scores of its pairs minus, for each
+    run of k consecutive moves of one gap kind, gap_open + k * gap_extend."""
+    i = j = 0
+    s = 0
+    prev = None
+    for m in moves:
+        if m == "D":
+            s += int(matrix[x[i], y[j]])
+            i, j = i + 1, j + 1
+        else:
+            s -= gap_extend + (gap_open if m != prev else 0)
+            if m == "E":
+                j += 1
+            else:
+                i += 1
+        prev = m
+    return s
+
+
+ALIGN_FIELDS = ("seq1", "seq2", "seed1", "seed2", "start1", "end1", "start2", "end2", "score",
+                "length", "identities", "mismatches", "gap_opens", "match")
+
+
+def _side_walk(a, p1, b, p2, moves, step):
+    """Pairs, segments and counts of one side's path in sequence coordinates.
+    step = +1: the right side (pairs a[p1 + i], b[p2 + j]); -1: the left side
+    (pairs a[p1 - 1 - i], b[p2 - 1 - j]).  Segments are maximal runs of pairs,
+    as (diagonal p - q, first position in a, one past the last)."""
+    i = j = 0
+    segs, ident, mism, opens = [], 0, 0, 0
+    run = None
+    prev = None
+    for m in moves:
+        if m == "D":
+            pa = p1 + i if step > 0 else p1 - 1 - i
+            pb = p2 + j if step > 0 else p2 - 1 - j
+            if a[pa] == b[pb]:
+                ident += 1
+            else:
+                mism += 1
+            if run is None:
+                run = [pa - pb, pa, pa + 1]
+            if step > 0:
+                run[2] = pa + 1
+            else:
+                run[1] = pa
+            i, j = i + 1, j + 1
+        else:
+            if run is not None:
+                segs.append(tuple(run))
+                run = None
+            if m != prev:
+                opens += 1
+            if m == "E":
+                j += 1
+            else:
+                i += 1
+        prev = m
+    if run is not None:
+        segs.append(tuple(run))
+    return segs, ident, mism, opens, i, j
+
+
+def full_alignments(bank1, bank2, hits, gscore, passed, gap_open=GAP_OPEN, gap_extend=GAP_EXTEND,
+                    matrix=BLOSUM62):
+    """Stage 3.2 over the hits that passed the small gapped filter (Sec. 3.3.4:
+    full dynamic programming for the survivors of stage 3.1, and the list of the
+    ungapped pieces of the alignments already computed, kept per diagonal, that
+    lets a hit lying on one of them skip its own computation).
+
+    Reading: the surviving hits of one sequence pair are taken in order of
+    decreasing gapped score, then increasing seed position in bank1, then in
+    bank2.  A hit (p1, p2) is covered if an earlier alignment of the same pair
+    has a piece on diagonal p1 - p2 whose positions in bank1 include p1; a
+    covered hit computes nothing.  Otherwise its alignment is the left side
+    (letters before the seed, read backwards) joined to the right side (from the
+    seed start onwards), each from :func:`full_side` over the whole rest of the
+    two sequences.
+
+    Returns (records, cover): records is an int64 array with the columns of
+    ALIGN_FIELDS, one row per computed alignment, in canonical order (sorted by
+    its columns); cover[h] is the index of the hit whose alignment covers hit h
+    (h itself if it computed one), -1 for hits that did not pass.
+    """
+    A, B = sequences(bank1), sequences(bank2)
+    hits = np.asarray(hits, dtype=np.int64).reshape(-1, 5)
+    gscore = np.asarray(gscore, dtype=np.int64).reshape(-1)
+    passed = np.asarray(passed).reshape(-1).astype(bool)
+    n = len(hits)
+    cover = np.full(n, -1, dtype=np.int64)
+    groups = {}
+    for h in np.nonzero(passed)[0]:
+        groups.setdefault((int(hits[h, 0]), int(hits[h, 2])), []).append(int(h))
+    records = []
+    for (s1, s2), members in groups.items():
+        members.sort(key=lambda h: (-int(gscore[h]), int(hits[h, 1]), int(hits[h, 3])))
+        a, b = A[s1], B[s2]
+        pieces = []   # (diagonal, first, one past last, owning hit)
+        for h in members:
+            p1, p2 = int(hits[h, 1]), int(hits[h, 3])
+            owner = next((o for d, f, t, o in pieces if d == p1 - p2 and f <= p1 < t), None)
+            if owner is not None:
+                cover[h] = owner
+                continue
+            cover[h] = h
+            bR, _, mR = full_side(a[p1:], b[p2:], gap_open, gap_extend, matrix)
+            bL, _, mL = full_side(a[:p1][::-1], b[:p2][::-1], gap_open, gap_extend, matrix)
+            sR, iR, xR, oR, i_r, j_r = _side_walk(a, p1, b, p2, mR, +1)
+            sL, iL, xL, oL, i_l, j_l = _side_walk(a, p1, b, p2, mL, -1)
+            pieces.extend((d, f, t, h) for d, f, t in sR + sL)
+            records.append((s1, s2, p1, p2, p1 - i_l, p1 + i_r, p2 - j_l, p2 + j_r, bR + bL,
+                            len(mR) + len(mL), iR + iL, xR + xL, oR + oL, h))
+    rec = np.asarray(records, dtype=np.int64).reshape(-1, len(ALIGN_FIELDS))
+    if len(rec):
+        rec = rec[np.lexsort(rec.T[::-1])]
+    return rec, cover
 
 
 # --------------------------------------------------------------------------- six-frame translation
