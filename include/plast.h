@@ -7,7 +7,8 @@
  * of an occurrence in bank 1 and an occurrence in bank 2 gets a one-hit ungapped
  * extension on bounded neighbourhoods (Sec. 3.2, Sec. 3.3.3; score composition
  * of the GPU kernel in Annex 4) and survivors go through a small banded gapped
- * filter (Sec. 3.3.4 stage 3.1, Sec. 5.2.2).
+ * filter (Sec. 3.3.4 stage 3.1, Sec. 5.2.2); those that pass get a full gapped
+ * alignment (Sec. 3.3.4 stage 3.2).
  *
  * Conventions shared by every entry point
  *   - Device pointers ("d_") are HIP device memory owned by the caller; the
@@ -359,6 +360,64 @@ int plast_translate_count(const uint8_t* d_dna, const int64_t* d_dna_start, int3
 int plast_translate_write(const uint8_t* d_dna, const int64_t* d_dna_start, int32_t n_dna, int64_t n_nt, void* d_ws,
                           size_t ws_bytes, uint8_t* d_codes, int64_t n_padded, int64_t* d_seq_start, int32_t* d_frag,
                           int64_t n_frags, void* stream);
+
+/*
+ * Stage 3.2 (Sec. 3.3.4): full gapped alignment of the hits that passed the
+ * small gapped filter, with the list of ungapped pieces of the alignments
+ * already computed that lets a hit lying on one of them skip its own.
+ *
+ * A side of an alignment is the anchored affine-gap recurrence of the gapped
+ * filter with no band and no window, over the whole rest of both sequences:
+ * rightward from the seed start, leftward from the letters just before it.
+ * best = max over cells of H (H(0,0) = 0, so best >= 0); the end cell is the
+ * first cell in row-major order (rows: bank-a letters) holding best; the path
+ * is traced back preferring, for H, the diagonal, then E (a letter of b against
+ * a gap), then F; for E and F, a gap opening before an extension.  score =
+ * best right + best left.  Pieces are maximal runs of pairs: (diagonal
+ * pos1 - pos2, first and one-past-last position in sequence a).
+ * The passing hits of one sequence pair are taken in order of decreasing
+ * gapped score, then increasing pos1, then pos2; a hit is covered (computes
+ * nothing) when an earlier alignment of its pair has a piece on diagonal
+ * pos1 - pos2 whose positions include pos1.  Hits must be distinct.
+ */
+typedef struct {
+  int32_t seq1, seq2;        /* sequence ids in bank a, bank b */
+  int32_t seed1, seed2;      /* seed start (pos1, pos2) of the hit that produced it */
+  int32_t start1, end1;      /* aligned letters of seq1: [start1, end1) */
+  int32_t start2, end2;      /* aligned letters of seq2: [start2, end2) */
+  int32_t score;             /* raw score, best left + best right */
+  int32_t length;            /* alignment columns: pairs plus gap positions */
+  int32_t identities;        /* pairs of equal letters */
+  int32_t mismatches;        /* pairs of different letters */
+  int32_t gap_opens;         /* gap openings charged (one per run of one gap kind on each side) */
+  int32_t hit;               /* index of that hit in the input list */
+} plast_alignment_t;         /* 56 bytes; the tabular (-m 8 style) fields without E-values */
+
+typedef struct {
+  int32_t gap_open;          /* a gap of length k costs gap_open + k * gap_extend (11, 1) */
+  int32_t gap_extend;
+  int32_t max_len1;          /* longest sequence of bank a / bank b that a passing hit may lie in, */
+  int32_t max_len2;          /*   1..16384 each, with the LDS bound below */
+  int32_t n_waves;           /* alignment wavefronts (one workgroup each); 0 = as many as stay resident */
+  int32_t max_pieces;        /* capacity of one sequence pair's piece list, >= 16 */
+  const int8_t* matrix;      /* host, 20x20 row-major in code order; NULL = BLOSUM62 */
+} plast_align_params_t;
+
+/* Workspace for n_hits input hits; fails with PLAST_E_ARG when
+ * max_len1 + 9 max_len2 (about) exceeds the 160 KiB of LDS a workgroup may use. */
+int plast_align_workspace_bytes(int64_t n_hits, const plast_align_params_t* p, size_t* bytes);
+/* d_hits / d_gscore / d_pass: n_hits records as written by plast_ungapped_extend
+ * and plast_gapped_filter (only hits with d_pass != 0 are aligned).  Outputs:
+ * d_out (capacity n_hits records, caller memory) receives *h_n_out alignments
+ * in no particular order; d_cover[h] (n_hits int32) = the index of the hit
+ * whose alignment covers hit h (h itself when it computed one), -1 when h did
+ * not pass.  Synchronises the stream (twice: after the key pass and at the end).
+ * Errors: PLAST_E_ARG (bad parameters, a passing hit outside its banks or in a
+ * sequence longer than max_len), PLAST_E_WORKSPACE (workspace too small, or a
+ * pair needing more than max_pieces pieces), PLAST_E_HIP. */
+int plast_align(const plast_index_t* a, const plast_index_t* b, const plast_hit_t* d_hits, const int32_t* d_gscore,
+                const uint8_t* d_pass, int64_t n_hits, const plast_align_params_t* p, void* d_ws, size_t ws_bytes,
+                plast_alignment_t* d_out, int32_t* d_cover, int64_t* h_n_out, void* stream);
 
 const char* plast_strerror(int code);
 const char* plast_last_error(void);

@@ -29,8 +29,8 @@ EXPORTS = ("plast_index_bytes", "plast_build_index", "plast_ungapped_workspace_b
            "plast_autotune", "plast_pipeline_workspace_bytes", "plast_pipeline_create", "plast_pipeline_launch",
            "plast_pipeline_result", "plast_pipeline_index", "plast_pipeline_destroy",
            "plast_search_workspace_bytes", "plast_search_enqueue", "plast_search_result",
-           "plast_translate_ws_bytes", "plast_translate_count", "plast_translate_write", "plast_strerror",
-           "plast_last_error")
+           "plast_translate_ws_bytes", "plast_translate_count", "plast_translate_write",
+           "plast_align_workspace_bytes", "plast_align", "plast_strerror", "plast_last_error")
 
 TUNE_CLASSES = 4
 TUNE_WIDTHS = (1024, 2048, 4096, 8192, 16384)
@@ -107,6 +107,17 @@ class MatchRec(ctypes.Structure):
                 ("pos2", ctypes.c_int32), ("score", ctypes.c_int32), ("gscore", ctypes.c_int32)]
 
 
+class AlignParams(ctypes.Structure):
+    _fields_ = [("gap_open", ctypes.c_int32), ("gap_extend", ctypes.c_int32), ("max_len1", ctypes.c_int32),
+                ("max_len2", ctypes.c_int32), ("n_waves", ctypes.c_int32), ("max_pieces", ctypes.c_int32),
+                ("matrix", ctypes.c_void_p)]
+
+
+# columns of a plast_alignment_t record
+ALIGN_FIELDS = ("seq1", "seq2", "seed1", "seed2", "start1", "end1", "start2", "end2", "score", "length",
+                "identities", "mismatches", "gap_opens", "hit")
+
+
 class PipelineResult(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("n_items", ctypes.c_int32), ("n_hits", ctypes.c_int64),
                 ("n_ext", ctypes.c_int64), ("n_words_a", ctypes.c_int64), ("n_words_b", ctypes.c_int64)]
@@ -154,6 +165,9 @@ def load():
         lib.plast_translate_ws_bytes.argtypes = [i32, ctypes.POINTER(sz)]
         lib.plast_translate_count.argtypes = [P, P, i32, i64, P, sz, ctypes.POINTER(i64), ctypes.POINTER(i64), P]
         lib.plast_translate_write.argtypes = [P, P, i32, i64, P, sz, P, i64, P, P, i64, P]
+        AP = ctypes.POINTER(AlignParams)
+        lib.plast_align_workspace_bytes.argtypes = [i64, AP, ctypes.POINTER(sz)]
+        lib.plast_align.argtypes = [IV, IV, P, P, P, i64, AP, P, sz, P, P, ctypes.POINTER(i64), P]
         for f in EXPORTS[:-2]:
             getattr(lib, f).restype = ctypes.c_int
         lib.plast_strerror.argtypes = [ctypes.c_int]
@@ -560,3 +574,52 @@ class Translator:
 
 def translate(dna_codes, dna_start, stream=None):
     return Translator(dna_codes, dna_start).run(stream)
+
+
+def max_seq_len(ix):
+    """Longest sequence of an indexed bank (host read of its sequence offsets)."""
+    st = ix.seq_start.cpu().numpy()
+    return int((np.diff(st) - PAD_LEN).max(initial=1))
+
+
+def align_workspace_bytes(n_hits, params):
+    sz = ctypes.c_size_t(0)
+    _check(load().plast_align_workspace_bytes(int(n_hits), ctypes.byref(params), ctypes.byref(sz)),
+           "plast_align_workspace_bytes")
+    return int(sz.value)
+
+
+def align_params(ia, ib, gap_open=11, gap_extend=1, max_len1=None, max_len2=None, n_waves=0, max_pieces=4096,
+                 matrix=None):
+    """plast_align_params_t (and the matrix buffer it points to, to keep alive)."""
+    m, mp = _matrix_ptr(matrix)
+    p = AlignParams(int(gap_open), int(gap_extend), int(max_len1 if max_len1 else max_seq_len(ia)),
+                    int(max_len2 if max_len2 else max_seq_len(ib)), int(n_waves), int(max_pieces), mp)
+    return p, m
+
+
+def align(ia, ib, hits, gscore, passed, gap_open=11, gap_extend=1, max_len1=None, max_len2=None, n_waves=0,
+          max_pieces=4096, matrix=None, stream=None):
+    """Stage 3.2 (``plast_align``): full gapped alignments of the hits that
+    passed the gapped filter.  Returns (records int32[n_out, 14] with columns
+    ALIGN_FIELDS, in no particular order; cover int32[n_hits]) device tensors."""
+    n = hits.shape[0]
+    dev = ia.codes.device
+    p, m = align_params(ia, ib, gap_open, gap_extend, max_len1, max_len2, n_waves, max_pieces, matrix)
+    out = torch.empty((max(n, 1), len(ALIGN_FIELDS)), dtype=torch.int32, device=dev)
+    cover = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    ws = _alloc(align_workspace_bytes(n, p), dev)
+    n_out = ctypes.c_int64(0)
+    hp = hits if hits.is_contiguous() else hits.contiguous()
+    _check(load().plast_align(ctypes.byref(ia.view), ctypes.byref(ib.view), _ptr(hp), _ptr(gscore), _ptr(passed), n,
+                              ctypes.byref(p), _ptr(ws), ws.numel(), _ptr(out), _ptr(cover), ctypes.byref(n_out),
+                              _stream(stream)), "plast_align")
+    del m
+    return out[:n_out.value], cover[:n]
+
+
+def canonical_alignments(rec):
+    """Alignment records sorted lexicographically by their columns (int64 numpy)."""
+    r = rec.cpu().numpy().astype(np.int64) if isinstance(rec, torch.Tensor) else np.asarray(rec, np.int64)
+    r = r.reshape(-1, len(ALIGN_FIELDS))
+    return r[np.lexsort(r.T[::-1])] if len(r) else r

@@ -1,0 +1,604 @@
+// Stage 3.2 of Sec. 3.3.4: full gapped alignment of the hits that passed the
+// small gapped filter, with the per-pair list of ungapped pieces (diagonal,
+// first and one-past-last position in bank a) of the alignments already
+// computed, which lets a hit lying on one of them skip its own computation.
+//
+// Order of work.  The surviving hits of one sequence pair form a group, taken
+// in order of decreasing gapped score, then seed position in bank a, then in
+// bank b; a hit is covered when an earlier alignment of its group has a piece
+// on diagonal p1 - p2 holding p1.  Groups are independent, so one wavefront
+// takes a whole group at a time from a global counter and walks it in order.
+//
+// One side (rightward from the seed start, or leftward from the letters before
+// it) is the anchored affine-gap recurrence of stage 3.1 with no band and no
+// window: H(0,0) = 0, E from the left, F from above, H = max(diagonal, E, F),
+// a gap of k letters costing open + k * extend, best = max over cells of H, the
+// end cell the first in row-major order holding best.  A wavefront sweeps
+// strips of 64 rows (one row per lane) across the columns as a skewed front:
+// at step t lane r holds column t - r; H and F move one lane down per step
+// through a wavefront DPP shift, and the strip's last row waits in LDS for the
+// next strip.  Each cell leaves a 4-bit trace (source of H; whether E and F
+// opened) in a per-wavefront buffer; the trace-back then reads it through an
+// LDS window of 64 rows x 64 steps.
+//
+// Layout of the trace of a side: strip s, lane r and step u = j + r hold the
+// nibble (u & 7) of dword ((s * nu8 + (u >> 3)) * 64 + r), nu8 = (ly + 71) / 8,
+// so every eighth step the wavefront stores one coalesced 256-byte row.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+#include "plast_internal.h"
+
+namespace plast {
+namespace {
+
+constexpr int kANeg = -(1 << 28);
+constexpr int kSortTile = 4096;     // radix-sort elements per tile (one wavefront, 64 per lane)
+constexpr int kMatStride = 32;      // LDS matrix row stride (bytes)
+constexpr int kWalkDwords = 512;    // trace-back window: 8 dwords (64 steps) x 64 rows
+constexpr size_t kMaxLds = 160 * 1024;
+
+struct AlignHeader {
+  int32_t status;                 // bit 1: sequence longer than its max_len; 2: piece list full; 4: bad hit
+  int32_t sort_total;
+  unsigned long long n_pass;
+  unsigned long long n_groups;
+  unsigned long long next_group;
+  unsigned long long n_out;
+};
+
+struct Piece {
+  int32_t diag, first, last, owner;
+};
+
+struct AlignArgs {
+  const uint8_t* a_codes;
+  const int64_t* a_start;
+  const uint8_t* b_codes;
+  const int64_t* b_start;
+  int32_t a_nseq, b_nseq;
+  int32_t max_len1, max_len2;
+  int32_t gap_open, gap_extend;
+  int32_t max_pieces, pad_;
+  int8_t mat[20 * 20];
+};
+
+struct AlignLayout {
+  size_t hdr, hidx, klo, khi, perm0, perm1, counts, scan_tmp, heads, tb, pieces, total;
+  int64_t tiles;
+  size_t tb_words_per_wave;
+};
+
+int bits_for(int64_t v) {  // bits needed for values 0..v
+  int b = 0;
+  while (b < 63 && (v >> b) > 0) ++b;
+  return b;
+}
+
+int64_t tb_words(int max_len1, int max_len2) {
+  const int64_t strips = (max_len1 + 63) / 64;
+  const int64_t nu8 = (max_len2 + 71) / 8;
+  return strips * nu8 * 64;
+}
+
+AlignLayout align_layout(int64_t n, const plast_align_params_t& p, int64_t waves) {
+  AlignLayout L;
+  L.tiles = (n + kSortTile - 1) / kSortTile;
+  if (L.tiles == 0) L.tiles = 1;
+  size_t off = 0;
+  L.hdr = off;
+  off = align_up(off + sizeof(AlignHeader), 256);
+  L.hidx = off;
+  off = align_up(off + sizeof(int32_t) * (size_t)n, 256);
+  L.klo = off;
+  off = align_up(off + sizeof(uint64_t) * (size_t)n, 256);
+  L.khi = off;
+  off = align_up(off + sizeof(uint64_t) * (size_t)n, 256);
+  L.perm0 = off;
+  off = align_up(off + sizeof(int32_t) * (size_t)n, 256);
+  L.perm1 = off;
+  off = align_up(off + sizeof(int32_t) * (size_t)n, 256);
+  L.counts = off;
+  off = align_up(off + sizeof(int32_t) * 256 * (size_t)L.tiles, 256);
+  L.scan_tmp = off;
+  off = align_up(off + scan_tmp_bytes(256 * L.tiles), 256);
+  L.heads = off;
+  off = align_up(off + sizeof(int32_t) * (size_t)n, 256);
+  L.tb_words_per_wave = (size_t)tb_words(p.max_len1, p.max_len2);
+  L.tb = off;
+  off = align_up(off + sizeof(uint32_t) * L.tb_words_per_wave * (size_t)waves, 256);
+  L.pieces = off;
+  off = align_up(off + sizeof(Piece) * (size_t)p.max_pieces * (size_t)waves, 256);
+  L.total = off;
+  return L;
+}
+
+size_t align_lds_bytes(int max_len1, int max_len2) {
+  size_t b = 20 * kMatStride;
+  b += align_up((size_t)max_len1 + 64, 16);          // x letters
+  b += align_up((size_t)max_len2 + 64, 16);          // y letters (index = column)
+  b += sizeof(int2) * ((size_t)max_len2 + 1);        // H, F of the row above the strip
+  b += sizeof(uint32_t) * kWalkDwords;               // trace-back window
+  return b;
+}
+
+__device__ __forceinline__ int seq_len(const int64_t* start, int s) {
+  return (int)(start[s + 1] - start[s] - kPadLen);
+}
+
+// ------------------------------------------------------------------ keys and sort
+
+// Passing hits get a compact index c; their sort keys are (seq1, seq2) in khi
+// and (16383 - gscore, pos1, pos2) in klo, so ascending order is the group
+// order.  cover[] starts at -1 for every hit.
+__global__ __launch_bounds__(256) void k_align_keys(AlignArgs A, const plast_hit_t* hits, const int32_t* gscore,
+                                                    const uint8_t* pass, int64_t n, int bp1, int bp2, int b2,
+                                                    AlignHeader* hdr, int32_t* hidx, uint64_t* klo, uint64_t* khi,
+                                                    int32_t* cover) {
+  const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= n) return;
+  cover[h] = -1;
+  if (!pass[h]) return;
+  const plast_hit_t r = hits[h];
+  if (r.seq1 < 0 || r.seq1 >= A.a_nseq || r.seq2 < 0 || r.seq2 >= A.b_nseq) {
+    atomicOr(&hdr->status, 4);
+    return;
+  }
+  const int la = seq_len(A.a_start, r.seq1), lb = seq_len(A.b_start, r.seq2);
+  if (la > A.max_len1 || lb > A.max_len2) {
+    atomicOr(&hdr->status, 1);
+    return;
+  }
+  if (r.pos1 < 0 || r.pos1 >= la || r.pos2 < 0 || r.pos2 >= lb) {
+    atomicOr(&hdr->status, 4);
+    return;
+  }
+  int g = gscore[h];
+  g = g < 0 ? 0 : (g > 16383 ? 16383 : g);
+  const unsigned long long c = atomicAdd(&hdr->n_pass, 1ull);
+  hidx[c] = (int32_t)h;
+  klo[c] = ((uint64_t)(16383 - g) << (bp1 + bp2)) | ((uint64_t)r.pos1 << bp2) | (uint64_t)r.pos2;
+  khi[c] = ((uint64_t)r.seq1 << b2) | (uint64_t)r.seq2;
+}
+
+__global__ __launch_bounds__(64) void k_align_clear(AlignHeader* hdr) {
+  if (threadIdx.x == 0) *hdr = AlignHeader{0, 0, 0, 0, 0, 0};
+}
+
+__global__ __launch_bounds__(256) void k_iota(int32_t* perm, const AlignHeader* hdr) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < (int64_t)hdr->n_pass) perm[i] = (int32_t)i;
+}
+
+// Digit histogram of one tile (one wavefront, kSortTile elements in order).
+__global__ __launch_bounds__(64) void k_rs_count(const int32_t* perm, const uint64_t* key, int shift,
+                                                 const AlignHeader* hdr, int32_t* counts, int64_t tiles) {
+  __shared__ int32_t hist[256];
+  const int lane = threadIdx.x;
+  for (int d = lane; d < 256; d += 64) hist[d] = 0;
+  __syncthreads();
+  const int64_t m = (int64_t)hdr->n_pass;
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  for (int k = 0; k < kSortTile / 64; ++k) {
+    const int64_t i = base + k * 64 + lane;
+    if (i < m) atomicAdd(&hist[(int)((key[perm[i]] >> shift) & 255)], 1);
+  }
+  __syncthreads();
+  for (int d = lane; d < 256; d += 64) counts[(int64_t)d * tiles + blockIdx.x] = hist[d];
+}
+
+// Stable scatter: the tile's elements in order, ranked among equal digits of
+// the same 64-element round with ballots, after the earlier rounds' counts.
+__global__ __launch_bounds__(64) void k_rs_scatter(const int32_t* perm_in, const uint64_t* key, int shift,
+                                                   const AlignHeader* hdr, const int32_t* offsets, int64_t tiles,
+                                                   int32_t* perm_out) {
+  __shared__ int32_t run[256];
+  const int lane = threadIdx.x;
+  for (int d = lane; d < 256; d += 64) run[d] = offsets[(int64_t)d * tiles + blockIdx.x];
+  __syncthreads();
+  const int64_t m = (int64_t)hdr->n_pass;
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int k = 0; k < kSortTile / 64; ++k) {
+    const int64_t i = base + k * 64 + lane;
+    const bool valid = i < m;
+    const int32_t c = valid ? perm_in[i] : 0;
+    const int d = valid ? (int)((key[c] >> shift) & 255) : 0;
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const uint64_t ones = __ballot(valid && ((d >> b) & 1));
+      peers &= ((d >> b) & 1) ? ones : ~ones;
+    }
+    const int rank = __popcll(peers & below);
+    const int start = run[d];
+    __syncthreads();
+    if (valid) {
+      perm_out[start + rank] = c;
+      if (rank == 0) run[d] = start + __popcll(peers);
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void k_align_heads(const int32_t* perm, const uint64_t* khi, AlignHeader* hdr,
+                                                     int32_t* heads) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)hdr->n_pass) return;
+  if (i == 0 || khi[perm[i]] != khi[perm[i - 1]]) {
+    const unsigned long long g = atomicAdd(&hdr->n_groups, 1ull);
+    heads[g] = (int32_t)i;
+  }
+}
+
+// ------------------------------------------------------------------ alignment
+
+struct SideStats {
+  int best;
+  int i_end, j_end;     // letters of x and y the side consumes
+  int length, ident, mism, opens;
+};
+
+__device__ __forceinline__ int shr1(int old, int v) {
+  return __builtin_amdgcn_update_dpp(old, v, 0x138, 0xf, 0xf, false);  // wave_shr:1, lane 0 keeps old
+}
+
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// One side.  x (lx letters, step dx) runs down the rows, y (ly letters) across
+// the columns; dir = +1 (pairs a[p1 + i - 1], b[p2 + j - 1]) or -1 (pairs
+// a[p1 - i], b[p2 - j]).  Appends the side's pieces to P (count *np).
+__device__ __forceinline__ SideStats align_side(const AlignArgs& A, const uint8_t* x, int lx, int dx, const uint8_t* y, int ly,
+                                int dy, int dir, int p1, int p2, int owner, const int8_t* mat, uint8_t* xb,
+                                uint8_t* yb, int2* strip, uint32_t* walk, uint32_t* tb, Piece* P, int* np,
+                                int32_t* status) {
+  const int lane = threadIdx.x;
+  const int ge = A.gap_extend, oe = A.gap_open + A.gap_extend;
+  SideStats st = {0, 0, 0, 0, 0, 0, 0};
+  if (lx == 0 || ly == 0) return st;
+  for (int k = lane; k < lx; k += 64) xb[k] = x[(int64_t)k * dx];
+  for (int k = lane; k <= ly; k += 64) yb[k] = k ? y[(int64_t)(k - 1) * dy] : 0;
+  for (int k = lane; k <= ly; k += 64) strip[k] = make_int2(k ? -(oe + (k - 1) * ge) : 0, kANeg);
+  __syncthreads();
+
+  const int nu8 = (ly + 71) >> 3;
+  const int strips = (lx + 63) >> 6;
+  int best = 0, bpos = 0;
+  for (int s = 0; s < strips; ++s) {
+    const int i = s * 64 + lane + 1;
+    const bool rowv = i <= lx;
+    const int8_t* mrow = mat + (rowv ? xb[i - 1] : 0) * kMatStride;
+    const int bnd = -(oe + (i - 1) * ge);  // H(i, 0) = F(i, 0)
+    int hout = 0, fout = kANeg, yl = 0;    // passed one lane down each step
+    int hup = 0, hleft = bnd, eleft = kANeg;
+    uint32_t acc = 0;
+    uint32_t* tbs = tb + (size_t)s * nu8 * 64 + lane;
+    const int steps = ly + 64;
+    for (int t = 0; t < steps; ++t) {
+      const int tc = t < ly ? t : ly;
+      const int2 fd = strip[tc];
+      const int hdiag = hup;
+      hup = shr1(fd.x, hout);
+      const int fup = shr1(fd.y, fout);
+      yl = shr1((int)yb[tc], yl);
+      const int j = t - lane;
+      const int e1 = eleft - ge, e2 = hleft - oe;
+      const int e = max(e1, e2);
+      const int f1 = fup - ge, f2 = hup - oe;
+      const int f = max(f1, f2);
+      const int d = hdiag + (int)mrow[yl];
+      int h = max(max(d, e), f);
+      const uint32_t nib = (h == d ? 0u : (h == e ? 1u : 2u)) | (e2 >= e1 ? 4u : 0u) | (f2 >= f1 ? 8u : 0u);
+      acc |= nib << ((t & 7) * 4);
+      const bool valid = rowv && j >= 1 && j <= ly;
+      if (valid && h > best) {
+        best = h;
+        bpos = (i << 16) | j;
+      }
+      int fo = f, eo = e;
+      if (j == 0) {
+        h = bnd;
+        fo = bnd;
+        eo = kANeg;
+      }
+      hout = h;
+      fout = fo;
+      hleft = h;
+      eleft = eo;
+      if (lane == 63 && j >= 0 && j <= ly) strip[j] = make_int2(h, fo);
+      if ((t & 7) == 7 || t == steps - 1) {
+        tbs[(t >> 3) * 64] = acc;
+        acc = 0;
+      }
+    }
+    __syncthreads();
+  }
+
+  // best over the wavefront: largest value, then first cell in row-major order
+  for (int o = 32; o >= 1; o >>= 1) {
+    const int ob = __shfl_xor(best, o), op = __shfl_xor(bpos, o);
+    if (ob > best || (ob == best && op < bpos)) {
+      best = ob;
+      bpos = op;
+    }
+  }
+  best = uni(best);
+  bpos = uni(bpos);
+  st.best = best;
+  st.i_end = bpos >> 16;
+  st.j_end = bpos & 0xffff;
+
+  // trace-back, uniform across the wavefront
+  __threadfence();
+  int i = st.i_end, j = st.j_end;
+  int state = 0;           // 0: H, 1: E, 2: F
+  int prev = 0;            // last move: 0 none, 1 D, 2 E, 3 F
+  int run_a = -1, run_b = -1, run_diag = 0;  // current piece: positions in a (inclusive)
+  int blk_s = -1, blk_g0 = 0;
+  auto close_run = [&]() {
+    if (run_a >= 0) {
+      const int k = *np;
+      if (k < A.max_pieces) {
+        if (lane == 0) P[k] = Piece{run_diag, min(run_a, run_b), max(run_a, run_b) + 1, owner};
+        *np = k + 1;
+      } else if (lane == 0) {
+        atomicOr(status, 2);
+      }
+      run_a = -1;
+    }
+  };
+  while (i > 0 || j > 0) {
+    if (i == 0 || j == 0) {  // the rest is one gap along row 0 or column 0
+      const int mv = i == 0 ? 2 : 3;
+      close_run();
+      if (prev != mv) st.opens++;
+      st.length += i + j;
+      prev = mv;
+      break;
+    }
+    const int s = (i - 1) >> 6, r = (i - 1) & 63, u = j + r, g = u >> 3;
+    if (s != blk_s || g < blk_g0 || g >= blk_g0 + 8) {
+      blk_s = s;
+      blk_g0 = g - 7 > 0 ? g - 7 : 0;
+      const uint32_t* src = tb + ((size_t)s * nu8 + blk_g0) * 64;
+      for (int c = 0; c < 8; ++c)
+        if (blk_g0 + c < nu8) walk[c * 64 + lane] = src[c * 64 + lane];
+      __syncthreads();
+    }
+    const uint32_t nib = (walk[(g - blk_g0) * 64 + r] >> ((u & 7) * 4)) & 15u;
+    if (state == 0) {
+      const uint32_t src = nib & 3u;
+      if (src == 0) {
+        const int xa = xb[i - 1], yc = yb[j];
+        const int pa = dir > 0 ? p1 + i - 1 : p1 - i;
+        const int pb = dir > 0 ? p2 + j - 1 : p2 - j;
+        if (run_a < 0) {
+          run_a = pa;
+          run_diag = pa - pb;
+        }
+        run_b = pa;
+        if (xa == yc) st.ident++;
+        else st.mism++;
+        st.length++;
+        prev = 1;
+        --i;
+        --j;
+      } else {
+        state = (int)src;
+      }
+    } else if (state == 1) {
+      close_run();
+      if (prev != 2) st.opens++;
+      st.length++;
+      prev = 2;
+      state = (nib & 4u) ? 0 : 1;
+      --j;
+    } else {
+      close_run();
+      if (prev != 3) st.opens++;
+      st.length++;
+      prev = 3;
+      state = (nib & 8u) ? 0 : 2;
+      --i;
+    }
+  }
+  close_run();
+  __threadfence();
+  return st;
+}
+
+__global__ __launch_bounds__(64) void k_align(AlignArgs A, const plast_hit_t* hits, const int32_t* hidx,
+                                              const int32_t* perm, const uint64_t* khi, const int32_t* heads,
+                                              AlignHeader* hdr, uint32_t* tb_all, size_t tb_words, Piece* pieces_all,
+                                              plast_alignment_t* out, int32_t* cover) {
+  extern __shared__ __align__(16) uint8_t lds[];
+  int8_t* mat = (int8_t*)lds;
+  uint8_t* xb = lds + 20 * kMatStride;
+  uint8_t* yb = xb + ((A.max_len1 + 64 + 15) & ~15);
+  int2* strip = (int2*)(yb + ((A.max_len2 + 64 + 15) & ~15));
+  uint32_t* walk = (uint32_t*)(strip + A.max_len2 + 1);
+  const int lane = threadIdx.x;
+  for (int k = lane; k < 400; k += 64) mat[(k / 20) * kMatStride + k % 20] = A.mat[k];
+  __syncthreads();
+
+  uint32_t* tb = tb_all + (size_t)blockIdx.x * tb_words;
+  Piece* P = pieces_all + (size_t)blockIdx.x * A.max_pieces;
+  const int64_t m = (int64_t)hdr->n_pass;
+  const int64_t n_groups = (int64_t)hdr->n_groups;
+  for (;;) {
+    // fewer than 2^31 groups, and each wavefront overshoots the count once
+    unsigned long long gq = 0;
+    if (lane == 0) gq = atomicAdd(&hdr->next_group, 1ull);
+    const int g = uni((int)gq);
+    if (g >= n_groups) break;
+    const int64_t k0 = heads[g];
+    const uint64_t gkey = khi[perm[k0]];
+    int np = 0;
+    for (int64_t k = k0; k < m; ++k) {
+      const int32_t c = uni(perm[k]);
+      if (k > k0 && khi[c] != gkey) break;
+      const int32_t h = uni(hidx[c]);
+      const plast_hit_t r = hits[h];
+      const int s1 = uni(r.seq1), p1 = uni(r.pos1), s2 = uni(r.seq2), p2 = uni(r.pos2);
+      // covered by a piece of an earlier alignment of the group?
+      int owner = -1;
+      for (int q0 = 0; q0 < np; q0 += 64) {
+        const int q = q0 + lane;
+        bool on = false;
+        int own = 0;
+        if (q < np) {
+          const Piece pc = P[q];
+          on = pc.diag == p1 - p2 && pc.first <= p1 && p1 < pc.last;
+          own = pc.owner;
+        }
+        const uint64_t b = __ballot(on);
+        if (b) {
+          owner = __shfl(own, __ffsll((long long)b) - 1);
+          break;
+        }
+      }
+      owner = uni(owner);
+      if (owner >= 0) {
+        if (lane == 0) cover[h] = owner;
+        continue;
+      }
+      if (lane == 0) cover[h] = h;
+      const uint8_t* a = A.a_codes + A.a_start[s1];
+      const uint8_t* b = A.b_codes + A.b_start[s2];
+      const int la = seq_len(A.a_start, s1), lb = seq_len(A.b_start, s2);
+      const SideStats R = align_side(A, a + p1, la - p1, 1, b + p2, lb - p2, 1, +1, p1, p2, h, mat, xb, yb, strip,
+                                     walk, tb, P, &np, &hdr->status);
+      const SideStats L = align_side(A, a + p1 - 1, p1, -1, b + p2 - 1, p2, -1, -1, p1, p2, h, mat, xb, yb, strip,
+                                     walk, tb, P, &np, &hdr->status);
+      if (lane == 0) {
+        const unsigned long long o = atomicAdd(&hdr->n_out, 1ull);
+        plast_alignment_t rec;
+        rec.seq1 = s1;
+        rec.seq2 = s2;
+        rec.seed1 = p1;
+        rec.seed2 = p2;
+        rec.start1 = p1 - L.i_end;
+        rec.end1 = p1 + R.i_end;
+        rec.start2 = p2 - L.j_end;
+        rec.end2 = p2 + R.j_end;
+        rec.score = R.best + L.best;
+        rec.length = R.length + L.length;
+        rec.identities = R.ident + L.ident;
+        rec.mismatches = R.mism + L.mism;
+        rec.gap_opens = R.opens + L.opens;
+        rec.hit = h;
+        out[o] = rec;
+      }
+      __threadfence();
+    }
+  }
+}
+
+}  // namespace
+
+int align_default_waves(const plast_align_params_t& p, int64_t* waves) {
+  const size_t lds = align_lds_bytes(p.max_len1, p.max_len2);
+  if (lds > kMaxLds) return set_error(PLAST_E_ARG, "max_len1=%d, max_len2=%d need %zu bytes of LDS (limit %zu)",
+                                      p.max_len1, p.max_len2, lds, kMaxLds);
+  if (p.n_waves > 0) {
+    *waves = p.n_waves;
+    return PLAST_OK;
+  }
+  int dev = 0, cus = 0, per_cu = 0;
+  PLAST_HIP(hipGetDevice(&dev));
+  PLAST_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  PLAST_HIP(hipFuncSetAttribute((const void*)k_align, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  PLAST_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_align, 64, lds));
+  if (per_cu < 1) return set_error(PLAST_E_ARG, "alignment kernel does not fit a compute unit with %zu bytes of LDS", lds);
+  *waves = (int64_t)per_cu * cus;
+  return PLAST_OK;
+}
+
+size_t align_ws_bytes(int64_t n_hits, const plast_align_params_t& p, int64_t waves) {
+  return align_layout(n_hits, p, waves).total;
+}
+
+int align_impl(const plast_index_t* a, const plast_index_t* b, const plast_hit_t* d_hits, const int32_t* d_gscore,
+               const uint8_t* d_pass, int64_t n_hits, const plast_align_params_t* p, void* d_ws, size_t ws_bytes,
+               plast_alignment_t* d_out, int32_t* d_cover, int64_t* h_n_out, hipStream_t s) {
+  int64_t waves = 0;
+  int rc = align_default_waves(*p, &waves);
+  if (rc) return rc;
+  const AlignLayout L = align_layout(n_hits, *p, waves);
+  if (ws_bytes < L.total) return set_error(PLAST_E_WORKSPACE, "alignment workspace %zu < %zu bytes", ws_bytes, L.total);
+  uint8_t* ws = (uint8_t*)d_ws;
+  AlignHeader* hdr = (AlignHeader*)(ws + L.hdr);
+  int32_t* hidx = (int32_t*)(ws + L.hidx);
+  uint64_t* klo = (uint64_t*)(ws + L.klo);
+  uint64_t* khi = (uint64_t*)(ws + L.khi);
+  int32_t* perm[2] = {(int32_t*)(ws + L.perm0), (int32_t*)(ws + L.perm1)};
+  int32_t* counts = (int32_t*)(ws + L.counts);
+  int32_t* heads = (int32_t*)(ws + L.heads);
+  uint32_t* tb = (uint32_t*)(ws + L.tb);
+  Piece* pieces = (Piece*)(ws + L.pieces);
+
+  AlignArgs A;
+  A.a_codes = a->codes;
+  A.a_start = a->seq_start;
+  A.b_codes = b->codes;
+  A.b_start = b->seq_start;
+  A.a_nseq = a->n_seqs;
+  A.b_nseq = b->n_seqs;
+  A.max_len1 = p->max_len1;
+  A.max_len2 = p->max_len2;
+  A.gap_open = p->gap_open;
+  A.gap_extend = p->gap_extend;
+  A.max_pieces = p->max_pieces;
+  A.pad_ = 0;
+  if (p->matrix) {
+    for (int k = 0; k < 400; ++k) A.mat[k] = p->matrix[k];
+  } else {
+    blosum62_code_order(A.mat);
+  }
+
+  const int bp1 = bits_for(p->max_len1), bp2 = bits_for(p->max_len2);
+  const int b1 = bits_for(a->n_seqs), b2 = bits_for(b->n_seqs);
+  hipLaunchKernelGGL(k_align_clear, dim3(1), dim3(64), 0, s, hdr);
+  const unsigned nb = (unsigned)((n_hits + 255) / 256);
+  hipLaunchKernelGGL(k_align_keys, dim3(nb ? nb : 1), dim3(256), 0, s, A, d_hits, d_gscore, d_pass, n_hits, bp1, bp2,
+                     b2, hdr, hidx, klo, khi, d_cover);
+  AlignHeader h0;
+  PLAST_HIP(hipMemcpyAsync(&h0, hdr, sizeof(h0), hipMemcpyDeviceToHost, s));
+  PLAST_HIP(hipStreamSynchronize(s));
+  const int64_t m = (int64_t)h0.n_pass;
+  if (m > 0) {
+    const int64_t tiles = (m + kSortTile - 1) / kSortTile;
+    hipLaunchKernelGGL(k_iota, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, perm[0], hdr);
+    int cur = 0;
+    const int lo_bits = 14 + bp1 + bp2, hi_bits = b1 + b2;
+    for (int pass_key = 0; pass_key < 2; ++pass_key) {
+      const uint64_t* key = pass_key == 0 ? klo : khi;
+      const int nbits = pass_key == 0 ? lo_bits : hi_bits;
+      for (int shift = 0; shift < nbits; shift += 8) {
+        hipLaunchKernelGGL(k_rs_count, dim3((unsigned)tiles), dim3(64), 0, s, perm[cur], key, shift, hdr, counts,
+                           tiles);
+        exclusive_scan_i32(counts, 256 * tiles, &hdr->sort_total, ws + L.scan_tmp, s);
+        hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)tiles), dim3(64), 0, s, perm[cur], key, shift, hdr, counts,
+                           tiles, perm[cur ^ 1]);
+        cur ^= 1;
+      }
+    }
+    hipLaunchKernelGGL(k_align_heads, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, perm[cur], khi, hdr, heads);
+    const size_t lds = align_lds_bytes(p->max_len1, p->max_len2);
+    PLAST_HIP(hipFuncSetAttribute((const void*)k_align, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(k_align, dim3((unsigned)waves), dim3(64), lds, s, A, d_hits, hidx, perm[cur], khi, heads, hdr,
+                       tb, L.tb_words_per_wave, pieces, d_out, d_cover);
+    PLAST_HIP(hipGetLastError());
+    PLAST_HIP(hipMemcpyAsync(&h0, hdr, sizeof(h0), hipMemcpyDeviceToHost, s));
+    PLAST_HIP(hipStreamSynchronize(s));
+  }
+  *h_n_out = (int64_t)h0.n_out;
+  if (h0.status & 1) return set_error(PLAST_E_ARG, "a hit's sequence is longer than max_len1 / max_len2");
+  if (h0.status & 4) return set_error(PLAST_E_ARG, "a passing hit lies outside its banks");
+  if (h0.status & 2) return set_error(PLAST_E_WORKSPACE, "a sequence pair needs more than max_pieces=%d pieces",
+                                      p->max_pieces);
+  return PLAST_OK;
+}
+
+}  // namespace plast

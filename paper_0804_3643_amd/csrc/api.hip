@@ -406,4 +406,47 @@ int plast_translate_write(const uint8_t* d_dna, const int64_t* d_dna_start, int3
                               (hipStream_t)stream);
 }
 
+static int check_aparams(const plast_align_params_t* p) {
+  if (!p) return set_error(PLAST_E_ARG, "null alignment parameters");
+  if (p->gap_open < 0 || p->gap_extend < 1 || p->gap_open > 1000 || p->gap_extend > 1000)
+    return set_error(PLAST_E_ARG, "gap_open=%d, gap_extend=%d (need 0..1000 and 1..1000)", p->gap_open,
+                     p->gap_extend);
+  if (p->max_len1 < 1 || p->max_len1 > 16384 || p->max_len2 < 1 || p->max_len2 > 16384)
+    return set_error(PLAST_E_ARG, "max_len1=%d, max_len2=%d outside 1..16384", p->max_len1, p->max_len2);
+  if (p->n_waves < 0 || p->n_waves > (1 << 20)) return set_error(PLAST_E_ARG, "n_waves=%d", p->n_waves);
+  if (p->max_pieces < 16 || p->max_pieces > (1 << 24)) return set_error(PLAST_E_ARG, "max_pieces=%d", p->max_pieces);
+  if (p->matrix) {
+    for (int k = 0; k < 400; ++k)
+      if (p->matrix[k] < -100 || p->matrix[k] > 100) return set_error(PLAST_E_ARG, "matrix entry outside -100..100");
+  }
+  return PLAST_OK;
+}
+
+int plast_align_workspace_bytes(int64_t n_hits, const plast_align_params_t* p, size_t* bytes) {
+  g_last_error[0] = 0;
+  int rc;
+  if ((rc = check_aparams(p))) return rc;
+  if (!bytes || n_hits < 0 || n_hits > INT32_MAX) return set_error(PLAST_E_ARG, "null output or n_hits outside [0, 2^31)");
+  int64_t waves = 0;
+  if ((rc = align_default_waves(*p, &waves))) return rc;
+  *bytes = align_ws_bytes(n_hits, *p, waves);
+  return PLAST_OK;
+}
+
+int plast_align(const plast_index_t* a, const plast_index_t* b, const plast_hit_t* d_hits, const int32_t* d_gscore,
+                const uint8_t* d_pass, int64_t n_hits, const plast_align_params_t* p, void* d_ws, size_t ws_bytes,
+                plast_alignment_t* d_out, int32_t* d_cover, int64_t* h_n_out, void* stream) {
+  g_last_error[0] = 0;
+  int rc;
+  if ((rc = check_index(a, "a")) || (rc = check_index(b, "b")) || (rc = check_aparams(p))) return rc;
+  if (!h_n_out || n_hits < 0 || n_hits > INT32_MAX) return set_error(PLAST_E_ARG, "null count or n_hits outside [0, 2^31)");
+  *h_n_out = 0;
+  if (n_hits == 0) return PLAST_OK;
+  if (!d_hits || !d_gscore || !d_pass || !d_out || !d_cover || !d_ws)
+    return set_error(PLAST_E_ARG, "null device pointer");
+  if ((uintptr_t)d_ws & 255) return set_error(PLAST_E_ARG, "workspace must be 256-byte aligned");
+  return align_impl(a, b, d_hits, d_gscore, d_pass, n_hits, p, d_ws, ws_bytes, d_out, d_cover, h_n_out,
+                    (hipStream_t)stream);
+}
+
 }  // extern "C"

@@ -181,4 +181,12 @@ int translate_write_impl(const uint8_t* d_dna, const int64_t* d_dna_start, int32
                          uint8_t* d_codes, int64_t n_padded, int64_t* d_seq_start, int32_t* d_frag, int64_t n_frags,
                          hipStream_t s);
 
+// ---------------------------------------------------------------- stage 3.2
+// Wavefronts of the alignment kernel (p.n_waves, or as many as stay resident).
+int align_default_waves(const plast_align_params_t& p, int64_t* waves);
+size_t align_ws_bytes(int64_t n_hits, const plast_align_params_t& p, int64_t waves);
+int align_impl(const plast_index_t* a, const plast_index_t* b, const plast_hit_t* d_hits, const int32_t* d_gscore,
+               const uint8_t* d_pass, int64_t n_hits, const plast_align_params_t* p, void* d_ws, size_t ws_bytes,
+               plast_alignment_t* d_out, int32_t* d_cover, int64_t* h_n_out, hipStream_t s);
+
 }  // namespace plast

@@ -1,0 +1,152 @@
+"""GPU parity of stage 3.2 (full gapped alignment and the list of pieces of
+computed alignments, Sec. 3.3.4): plast_align through the C ABI against the C
+oracle on the same hits.  Integer work: the alignment records (canonical order)
+and the cover array must be identical."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import coracle as C
+from oracle import plast_oracle as O
+from paper_0804_3643_amd import params, synth
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+
+def _say(msg):
+    print("[gpu-test] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_0804_3643_amd import binding
+    binding.load()
+    return binding
+
+
+def _stage31(B, bank1, bank2, s1=params.S1, s2=params.S2):
+    ia = B.build_index(*B.bank_to_device(bank1, "cuda"))
+    ib = B.build_index(*B.bank_to_device(bank2, "cuda"))
+    hits, _ = B.ungapped_extend(ia, ib, s1, mode="batched")
+    gs, ps = B.gapped_filter(ia, ib, hits, s2)
+    return ia, ib, hits, gs, ps
+
+
+def _host(hits, gs, ps):
+    return (hits.cpu().numpy().astype(np.int64), gs.cpu().numpy().astype(np.int64),
+            ps.cpu().numpy().astype(bool))
+
+
+def _assert_parity(B, bank1, bank2, ia, ib, hits, gs, ps, gap_open=11, gap_extend=1, matrix=None, **kw):
+    rec, cov = B.align(ia, ib, hits, gs, ps, gap_open=gap_open, gap_extend=gap_extend, matrix=matrix, **kw)
+    torch.cuda.synchronize()
+    h, g, p = _host(hits, gs, ps)
+    ref, rcov = C.full_alignments(bank1, bank2, h, g, p, gap_open, gap_extend,
+                                  O.BLOSUM62 if matrix is None else matrix)
+    got = B.canonical_alignments(rec)
+    assert got.shape == ref.shape, (got.shape, ref.shape)
+    assert np.array_equal(got, ref)
+    assert np.array_equal(cov.cpu().numpy().astype(np.int64), rcov)
+    return got, rcov
+
+
+def test_align_config0_matches_oracle(B, cfg0):
+    _say("align cfg0: stage 3.1 on the GPU, then plast_align with resident waves, 1 wave and 3 waves")
+    ia, ib, hits, gs, ps = _stage31(B, cfg0.bank1, cfg0.bank2)
+    rec, cov = _assert_parity(B, cfg0.bank1, cfg0.bank2, ia, ib, hits, gs, ps)
+    assert len(rec) > 100 and (cov >= 0).sum() > len(rec)  # some hits are covered
+    for w in (1, 3):
+        _assert_parity(B, cfg0.bank1, cfg0.bank2, ia, ib, hits, gs, ps, n_waves=w)
+
+
+def _bank(seqs):
+    seqs = [np.asarray(s, dtype=np.uint8) for s in seqs]
+    return synth.Bank.from_flat(np.concatenate(seqs), [len(s) for s in seqs])
+
+
+def test_align_edge_cases(B):
+    """Identical pair (closed form), seeds at position 0 (empty left side),
+    4-letter sequences, a 3000-letter pair spanning 47 strips and many
+    trace windows, and planted copies with indels."""
+    rng = np.random.default_rng(21)
+    s = rng.integers(0, 20, 150)
+    long_a = rng.integers(0, 20, 3000)
+    long_b = long_a.copy()
+    long_b[rng.choice(3000, 900, replace=False)] = rng.integers(0, 20, 900)
+    indel = np.concatenate([s[:40], rng.integers(0, 20, 3), s[40:100], s[105:]])
+    bank1 = _bank([s, s[:4], long_a, s[30:], rng.integers(0, 20, 50)])
+    bank2 = _bank([s, indel, long_b, s[:4], s[30:90]])
+    _say("align edge cases")
+    ia, ib, hits, gs, ps = _stage31(B, bank1, bank2)
+    rec, cov = _assert_parity(B, bank1, bank2, ia, ib, hits, gs, ps)
+    h = hits.cpu().numpy()
+    F = {k: i for i, k in enumerate(O.ALIGN_FIELDS)}
+    assert ((h[:, 1] == 0) & ps.cpu().numpy().astype(bool)).any()  # a seed at position 0 passed
+    self_rec = rec[(rec[:, F["seq1"]] == 0) & (rec[:, F["seq2"]] == 0)]
+    assert (self_rec[:, F["score"]] == int(O.BLOSUM62[s, s].sum())).any()
+    assert (rec[:, F["end1"]] - rec[:, F["start1"]] > 1000).any()  # the long pair aligned end to end
+
+
+def test_align_other_gaps_and_matrix(B, cfg0):
+    _say("align cfg0 with gap 5 + 2k and a modified matrix")
+    ia, ib, hits, gs, ps = _stage31(B, cfg0.bank1, cfg0.bank2)
+    m = O.BLOSUM62.copy()
+    m[np.arange(20), np.arange(20)] += 2
+    m[0, 5] = m[5, 0] = 3
+    _assert_parity(B, cfg0.bank1, cfg0.bank2, ia, ib, hits, gs, ps, gap_open=5, gap_extend=2, matrix=m)
+
+
+def test_align_nothing_passes_and_errors(B, cfg0):
+    ia, ib, hits, gs, ps = _stage31(B, cfg0.bank1, cfg0.bank2)
+    _say("align with no passing hit")
+    none = torch.zeros_like(ps)
+    rec, cov = B.align(ia, ib, hits, gs, none)
+    assert rec.shape[0] == 0 and bool((cov == -1).all())
+    _say("align with max_len1 below the longest sequence")
+    with pytest.raises(B.PlastError) as e:
+        B.align(ia, ib, hits, gs, ps, max_len1=60)
+    assert e.value.code == B.E_ARG
+
+
+def test_align_config1_sampled_groups(B):
+    """Configuration 1 at full size through the same calls the benchmark times;
+    every hit's cover and every record checked for the invariants, and the
+    records and covers of 150 seeded random sequence pairs against the oracle."""
+    w = synth.make_workload(1)
+    _say("align cfg1: stage 3.1 on the GPU")
+    ia, ib, hits, gs, ps = _stage31(B, w.bank1, w.bank2)
+    idx = torch.nonzero(ps).flatten()
+    _say("align cfg1: plast_align over %d passing hits" % idx.numel())
+    rec, cov = B.align(ia, ib, hits, gs, ps)
+    torch.cuda.synchronize()
+    F = {k: i for i, k in enumerate(O.ALIGN_FIELDS)}
+    rec = B.canonical_alignments(rec)
+    cov_p = cov[idx].cpu().numpy().astype(np.int64)
+    idx_h = idx.cpu().numpy()
+    h = hits[idx].cpu().numpy().astype(np.int64)
+    g = gs[idx].cpu().numpy().astype(np.int64)
+    assert int((cov != -1).sum()) == idx.numel()
+    assert len(rec) == int((cov_p == idx_h).sum())
+    assert (rec[:, F["score"]] >= gs[torch.from_numpy(rec[:, F["hit"]]).cuda()].cpu().numpy()).all()
+    pairs = rec[:, F["identities"]] + rec[:, F["mismatches"]]
+    assert (rec[:, F["length"]] == rec[:, F["end1"]] - rec[:, F["start1"]] + rec[:, F["end2"]]
+            - rec[:, F["start2"]] - pairs).all()
+    # sampled sequence pairs against the oracle (groups are independent)
+    key = h[:, 0] * (1 << 20) + h[:, 2]
+    ukeys = np.unique(key)
+    pick = np.random.default_rng(5).choice(ukeys, size=min(150, len(ukeys)), replace=False)
+    sel = np.isin(key, pick)
+    _say("align cfg1: oracle on %d hits of %d sequence pairs" % (int(sel.sum()), len(pick)))
+    ref, rcov = C.full_alignments(w.bank1, w.bank2, h[sel], g[sel], np.ones(int(sel.sum()), bool))
+    # oracle indices are positions in the sampled list; map both sides to hit indices
+    hit_of = idx_h[sel]
+    ref[:, F["hit"]] = hit_of[ref[:, F["hit"]]]
+    ref = ref[np.lexsort(ref.T[::-1])]
+    rkey = rec[:, F["seq1"]] * (1 << 20) + rec[:, F["seq2"]]
+    got = rec[np.isin(rkey, pick)]
+    assert np.array_equal(got, ref)
+    assert np.array_equal(cov_p[sel], hit_of[rcov])

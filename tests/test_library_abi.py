@@ -215,3 +215,42 @@ def test_translate_validation_without_gpu():
                                      None) == binding.E_WORKSPACE
     assert lib.plast_translate_write(fake, fake, 10, 100, fake, 1 << 20, fake, 10, fake, fake, 5,
                                      None) == binding.E_ARG   # n_padded too small for 5 fragments
+
+
+def test_align_layout_and_validation_without_gpu(tmp_path):
+    prog = tmp_path / "alayout.c"
+    prog.write_text("""
+#include <stdio.h>
+#include <stddef.h>
+#include "plast.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu\\n", sizeof(plast_alignment_t), offsetof(plast_alignment_t, score),
+         offsetof(plast_alignment_t, hit), sizeof(plast_align_params_t), offsetof(plast_align_params_t, matrix));
+  return 0;
+}
+""")
+    exe = tmp_path / "alayout"
+    subprocess.check_call(["gcc", "-std=c99", "-I" + os.path.join(ROOT, "include"), str(prog), "-o", str(exe)])
+    got = [int(x) for x in subprocess.check_output([str(exe)], text=True).split()]
+    AP = binding.AlignParams
+    nf = len(binding.ALIGN_FIELDS)
+    assert got == [4 * nf, 4 * binding.ALIGN_FIELDS.index("score"), 4 * binding.ALIGN_FIELDS.index("hit"),
+                   ctypes.sizeof(AP), AP.matrix.offset]
+
+    lib = binding.load()
+    sz = ctypes.c_size_t(0)
+    ok = binding.AlignParams(11, 1, 1000, 1000, 64, 4096, None)
+    assert lib.plast_align_workspace_bytes(1000, ctypes.byref(ok), ctypes.byref(sz)) == binding.OK
+    # per wavefront: 16 strips x 133 dwords of 8 steps x 64 lanes of trace, 4096 pieces of 16 bytes
+    assert sz.value >= 64 * (16 * 133 * 64 * 4 + 4096 * 16)
+    for bad in (binding.AlignParams(11, 0, 1000, 1000, 64, 4096, None),        # extend < 1
+                binding.AlignParams(11, 1, 0, 1000, 64, 4096, None),           # max_len1 < 1
+                binding.AlignParams(11, 1, 1000, 20000, 64, 4096, None),       # max_len2 > 16384
+                binding.AlignParams(11, 1, 16384, 16384, 64, 4096, None),      # LDS bound
+                binding.AlignParams(11, 1, 1000, 1000, 64, 8, None)):          # max_pieces < 16
+        assert lib.plast_align_workspace_bytes(1000, ctypes.byref(bad), ctypes.byref(sz)) == binding.E_ARG
+    assert lib.plast_align_workspace_bytes(-1, ctypes.byref(ok), ctypes.byref(sz)) == binding.E_ARG
+    n_out = ctypes.c_int64(5)
+    iv = binding.IndexView()
+    assert lib.plast_align(ctypes.byref(iv), ctypes.byref(iv), None, None, None, 10, ctypes.byref(ok), None, 0,
+                           None, None, ctypes.byref(n_out), None) == binding.E_ARG
