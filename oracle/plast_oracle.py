@@ -472,7 +472,7 @@ def path_score(x, y, moves, gap_open=GAP_OPEN, gap_extend=GAP_EXTEND, matrix=BLO
 
 
 ALIGN_FIELDS = ("seq1", "seq2", "seed1", "seed2", "start1", "end1", "start2", "end2", "score",
-                "length", "identities", "mismatches", "gap_opens", "match")
+                "length", "identities", "mismatches", "gap_opens", "hit")
 
 
 def _side_walk(a, p1, b, p2, moves, step):

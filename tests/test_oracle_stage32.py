@@ -110,7 +110,7 @@ def test_stage32_records_are_consistent(cfg0_stage32):
     assert (cover[~ps] == -1).all() and (cover[ps] >= 0).all()
     assert len(rec) == int((cover == np.arange(len(h))).sum())
     # every computed alignment scores at least the banded, windowed filter score
-    assert (rec[:, F["score"]] >= g[rec[:, F["match"]]]).all()
+    assert (rec[:, F["score"]] >= g[rec[:, F["hit"]]]).all()
     pairs = rec[:, F["identities"]] + rec[:, F["mismatches"]]
     assert (rec[:, F["length"]] == (rec[:, F["end1"]] - rec[:, F["start1"]])
             + (rec[:, F["end2"]] - rec[:, F["start2"]]) - pairs).all()
@@ -201,7 +201,7 @@ def test_stage32_identical_pair_closed_form():
     assert main.any()
     first = int(np.nonzero(main)[0][0])
     owner = cover[first]
-    r = rec[rec[:, F["match"]] == owner][0]
+    r = rec[rec[:, F["hit"]] == owner][0]
     assert r[F["score"]] == int(M[s, s].sum())
     assert (r[F["start1"]], r[F["end1"]], r[F["start2"]], r[F["end2"]]) == (0, 120, 0, 120)
     assert r[F["identities"]] == 120 and r[F["gap_opens"]] == 0
