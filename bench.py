@@ -20,6 +20,10 @@ reported:
   * ``roofline`` for the dominant kernel (the persistent ungapped kernel):
     algorithmic int16 ALU operations (44 additions and 44 maxima per
     extension) per second against the packed-int16 VALU peak;
+  * ``stage32``: stage 3.2 (full gapped alignment, with the list of pieces of
+    computed alignments) over the hits that pass the filter, outside the step:
+    wall time of the call, DP cells per second, and the C oracle on a seeded
+    sample of sequence pairs checked against the GPU records;
   * ``cpu_baseline``: the CPU oracle (plain C, all allotted host threads) on a
     seeded sample of keys of the same workload, scaled to the whole job, and
     its hits compared with the GPU's for those keys.
@@ -133,6 +137,66 @@ def cpu_baseline(w, gpu_hits_host, n_ext_total, sample_ext, s1, s2):
                                                     n_ext_total, t_ung, len(ref), t_gap, n_ext_total)),
         "oracle_hits_equal_gpu_on_sample": equal, "n_gapped_pass_sample": int((g >= s2).sum()),
     }
+
+
+def run_stage32(B, torch, np, w, ia, ib, hits, gs, ps, reps, cpu):
+    """Stage 3.2 over the hits that passed the gapped filter: wall time of the
+    synchronous call (grouping sort, alignment kernel), alignments, covered
+    hits, DP cells (both sides of every computed alignment), and optionally the
+    C oracle on a seeded sample of sequence pairs, checked against the GPU."""
+    from oracle import coracle as C
+    from oracle import plast_oracle as O
+    n = hits.shape[0]
+    al = B.Aligner(ia, ib, n)
+    al.run(hits, gs, ps)
+    torch.cuda.synchronize()
+    walls = []
+    for _ in range(reps):
+        t1 = time.perf_counter()
+        rec, cov = al.run(hits, gs, ps)
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t1)
+    F = {k: i for i, k in enumerate(B.ALIGN_FIELDS)}
+    r = rec.cpu().numpy().astype(np.int64)
+    la = np.diff(w.bank1.seq_start) - B.PAD_LEN
+    lb = np.diff(w.bank2.seq_start) - B.PAD_LEN
+    s1, s2, p1, p2 = r[:, F["seq1"]], r[:, F["seq2"]], r[:, F["seed1"]], r[:, F["seed2"]]
+    cells = int(((la[s1] - p1) * (lb[s2] - p2) + p1 * p2).sum())
+    n_pass = int(ps.sum().item())
+    ms = 1e3 * float(np.min(walls))
+    out = {"passing_hits": n_pass, "alignments": len(r), "covered_hits": n_pass - len(r), "call_ms": ms,
+           "dp_cells": cells, "dp_cells_per_s": cells / (ms * 1e-3),
+           "mean_score": float(r[:, F["score"]].mean()) if len(r) else 0.0,
+           "call": "plast_align: key pass, radix sort by (seq1, seq2, -gscore, pos1, pos2), alignment kernel; "
+                   "wall time of the synchronous call, best of %d" % reps}
+    if cpu:
+        hh = hits.cpu().numpy().astype(np.int64)
+        gg = gs.cpu().numpy().astype(np.int64)
+        pp = ps.cpu().numpy().astype(bool)
+        idx = np.nonzero(pp)[0]
+        key = hh[idx, 0] * (1 << 20) + hh[idx, 2]
+        ukeys = np.unique(key)
+        pick = np.random.default_rng(7).choice(ukeys, size=min(len(ukeys), max(1, len(ukeys) // 50)), replace=False)
+        sel = idx[np.isin(key, pick)]
+        threads = min(16, os.cpu_count() or 1)
+        t1 = time.perf_counter()
+        ref, rcov = C.full_alignments(w.bank1, w.bank2, hh[sel], gg[sel], np.ones(len(sel), bool), nthreads=threads)
+        cpu_s = time.perf_counter() - t1
+        ref[:, F["hit"]] = sel[ref[:, F["hit"]]]
+        ref = ref[np.lexsort(ref.T[::-1])]
+        rk = r[:, F["seq1"]] * (1 << 20) + r[:, F["seq2"]]
+        got = r[np.isin(rk, pick)]
+        got = got[np.lexsort(got.T[::-1])]
+        cov_h = cov.cpu().numpy().astype(np.int64)
+        same = bool(np.array_equal(got, ref) and np.array_equal(cov_h[sel], sel[rcov]))
+        rs1, rs2, rp1, rp2 = ref[:, F["seq1"]], ref[:, F["seq2"]], ref[:, F["seed1"]], ref[:, F["seed2"]]
+        rcells = int(((la[rs1] - rp1) * (lb[rs2] - rp2) + rp1 * rp2).sum())
+        out["oracle_equals_gpu_on_sample_pairs"] = same
+        out["cpu_oracle"] = {"dp_cells_per_s": rcells / max(cpu_s, 1e-9), "cores": threads, "kind": "oracle",
+                             "sample": "plain C oracle, %d threads, on %d seeded random sequence pairs (%d passing "
+                                       "hits, %d alignments, %d DP cells) in %.2f s" % (
+                                           threads, len(pick), len(sel), len(ref), rcells, cpu_s)}
+    return out
 
 
 def run_serving(args):
@@ -342,6 +406,8 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=1000)
     ap.add_argument("--serving-scale", type=float, default=1.0, help="resident bank size factor (1 = 1M proteins)")
     ap.add_argument("--serving-slots", type=int, default=3)
+    ap.add_argument("--no-stage32", dest="stage32", action="store_false",
+                    help="skip stage 3.2 (full gapped alignment of the passing hits, reported apart from the step)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the hot path is single-GPU); "
@@ -454,6 +520,9 @@ def main():
                "tuning": tuning.as_dict() if tuning is not None else None,
                "note": "profiling run (--plain-reps 0): plain schedule, wall times and baselines skipped",
                "stages_device_ms": {k: float(np.mean(v)) for k, v in stage_ms.items()}}
+        if args.stage32:
+            log("stage 3.2")
+            out["stage32"] = run_stage32(B, torch, np, w, ia, ib, hits, gbuf[:n_hits], pbuf[:n_hits], 1, False)
         if args.copy_calibration:
             copy_calibration(torch, dev)
         print(json.dumps(out), flush=True)
@@ -504,6 +573,15 @@ def main():
     if args.copy_calibration:
         copy_calibration(torch, dev)
 
+    stage32 = None
+    if args.stage32:
+        log("stage 3.2 (full gapped alignment of the passing hits)")
+        # the wall-time runs above reused the hit and filter buffers: recompute both on the resident banks
+        h32, _ = ext.run(ia, ib)
+        g32, p32 = B.gapped_filter(ia, ib, h32, params.S2, out=(gbuf, pbuf), tuning=tuning)
+        stage32 = run_stage32(B, torch, np, w, ia, ib, h32, g32, p32, 3, not args.no_cpu_baseline)
+        log("stage 3.2: %d alignments in %.1f ms" % (stage32["alignments"], stage32["call_ms"]))
+
     achieved = n_ext * OPS_PER_EXT / (batched_kernel_ms * 1e-3) / 1e12
     out = {
         "metric": METRIC,
@@ -552,6 +630,7 @@ def main():
             "kernel": "k_ungapped_persistent", "ops_per_ext": OPS_PER_EXT,
         },
         "cpu_baseline": None,
+        "stage32": stage32,
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a key sample)")

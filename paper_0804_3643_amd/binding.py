@@ -598,24 +598,41 @@ def align_params(ia, ib, gap_open=11, gap_extend=1, max_len1=None, max_len2=None
     return p, m
 
 
+class Aligner:
+    """Stage 3.2 with buffers allocated once for up to ``capacity`` input hits
+    (records, cover array, workspace)."""
+
+    def __init__(self, ia, ib, capacity, gap_open=11, gap_extend=1, max_len1=None, max_len2=None, n_waves=0,
+                 max_pieces=4096, matrix=None):
+        self.ia, self.ib = ia, ib
+        self.capacity = int(capacity)
+        dev = ia.codes.device
+        self.params, self._m = align_params(ia, ib, gap_open, gap_extend, max_len1, max_len2, n_waves, max_pieces,
+                                            matrix)
+        self.out = torch.empty((max(self.capacity, 1), len(ALIGN_FIELDS)), dtype=torch.int32, device=dev)
+        self.cover = torch.empty(max(self.capacity, 1), dtype=torch.int32, device=dev)
+        self.ws = _alloc(align_workspace_bytes(self.capacity, self.params), dev)
+
+    def run(self, hits, gscore, passed, stream=None):
+        n = hits.shape[0]
+        if n > self.capacity:
+            raise ValueError("%d hits exceed the aligner capacity %d" % (n, self.capacity))
+        n_out = ctypes.c_int64(0)
+        hp = hits if hits.is_contiguous() else hits.contiguous()
+        _check(load().plast_align(ctypes.byref(self.ia.view), ctypes.byref(self.ib.view), _ptr(hp), _ptr(gscore),
+                                  _ptr(passed), n, ctypes.byref(self.params), _ptr(self.ws), self.ws.numel(),
+                                  _ptr(self.out), _ptr(self.cover), ctypes.byref(n_out), _stream(stream)),
+               "plast_align")
+        return self.out[:n_out.value], self.cover[:n]
+
+
 def align(ia, ib, hits, gscore, passed, gap_open=11, gap_extend=1, max_len1=None, max_len2=None, n_waves=0,
           max_pieces=4096, matrix=None, stream=None):
     """Stage 3.2 (``plast_align``): full gapped alignments of the hits that
     passed the gapped filter.  Returns (records int32[n_out, 14] with columns
     ALIGN_FIELDS, in no particular order; cover int32[n_hits]) device tensors."""
-    n = hits.shape[0]
-    dev = ia.codes.device
-    p, m = align_params(ia, ib, gap_open, gap_extend, max_len1, max_len2, n_waves, max_pieces, matrix)
-    out = torch.empty((max(n, 1), len(ALIGN_FIELDS)), dtype=torch.int32, device=dev)
-    cover = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
-    ws = _alloc(align_workspace_bytes(n, p), dev)
-    n_out = ctypes.c_int64(0)
-    hp = hits if hits.is_contiguous() else hits.contiguous()
-    _check(load().plast_align(ctypes.byref(ia.view), ctypes.byref(ib.view), _ptr(hp), _ptr(gscore), _ptr(passed), n,
-                              ctypes.byref(p), _ptr(ws), ws.numel(), _ptr(out), _ptr(cover), ctypes.byref(n_out),
-                              _stream(stream)), "plast_align")
-    del m
-    return out[:n_out.value], cover[:n]
+    a = Aligner(ia, ib, hits.shape[0], gap_open, gap_extend, max_len1, max_len2, n_waves, max_pieces, matrix)
+    return a.run(hits, gscore, passed, stream)
 
 
 def canonical_alignments(rec):

@@ -15,9 +15,9 @@
 // a gap of k letters costing open + k * extend, best = max over cells of H, the
 // end cell the first in row-major order holding best.  A wavefront sweeps
 // strips of 64 rows (one row per lane) across the columns as a skewed front:
-// at step t lane r holds column t - r; H and F move one lane down per step
-// through a wavefront DPP shift, and the strip's last row waits in LDS for the
-// next strip.  Each cell leaves a 4-bit trace (source of H; whether E and F
+// at step t lane r holds column t - r; H (less the gap-opening cost) and F move
+// one lane down per step through a wavefront DPP shift, and the strip's last
+// row waits in LDS for the next strip.  Each cell leaves a 4-bit trace (source of H; whether E and F
 // opened) in a per-wavefront buffer; the trace-back then reads it through an
 // LDS window of 64 rows x 64 steps.
 //
@@ -35,7 +35,8 @@ namespace {
 
 constexpr int kANeg = -(1 << 28);
 constexpr int kSortTile = 4096;     // radix-sort elements per tile (one wavefront, 64 per lane)
-constexpr int kMatStride = 32;      // LDS matrix row stride (bytes)
+constexpr int kTStride = 32;        // entries per row of the LDS score table
+constexpr int kWall = -16384;       // table entry of any pair with the sentinel letter
 constexpr int kWalkDwords = 512;    // trace-back window: 8 dwords (64 steps) x 64 rows
 constexpr size_t kMaxLds = 160 * 1024;
 
@@ -78,7 +79,7 @@ int bits_for(int64_t v) {  // bits needed for values 0..v
 
 int64_t tb_words(int max_len1, int max_len2) {
   const int64_t strips = (max_len1 + 63) / 64;
-  const int64_t nu8 = (max_len2 + 71) / 8;
+  const int64_t nu8 = (max_len2 + 71) / 8;  // steps of a strip, rounded up to 8, over 8
   return strips * nu8 * 64;
 }
 
@@ -114,12 +115,20 @@ AlignLayout align_layout(int64_t n, const plast_align_params_t& p, int64_t waves
   return L;
 }
 
+// LDS of one alignment workgroup: score table, the strip's per-lane profile,
+// x letters, y letters by column, and the row above the current strip (with
+// padding), whose space the trace-back window reuses once the DP is done.
+size_t strip_bytes(int max_len2) {
+  const size_t b = sizeof(int2) * ((size_t)max_len2 + 72);
+  return b > sizeof(uint32_t) * kWalkDwords ? b : sizeof(uint32_t) * kWalkDwords;
+}
+
 size_t align_lds_bytes(int max_len1, int max_len2) {
-  size_t b = 20 * kMatStride;
-  b += align_up((size_t)max_len1 + 64, 16);          // x letters
-  b += align_up((size_t)max_len2 + 64, 16);          // y letters (index = column)
-  b += sizeof(int2) * ((size_t)max_len2 + 1);        // H, F of the row above the strip
-  b += sizeof(uint32_t) * kWalkDwords;               // trace-back window
+  size_t b = sizeof(int16_t) * 21 * kTStride;
+  b += sizeof(int16_t) * 21 * 64;
+  b += align_up((size_t)max_len1 + 64, 16);
+  b += sizeof(int) * ((size_t)max_len2 + 72);
+  b += strip_bytes(max_len2);
   return b;
 }
 
@@ -137,29 +146,45 @@ __global__ __launch_bounds__(256) void k_align_keys(AlignArgs A, const plast_hit
                                                     AlignHeader* hdr, int32_t* hidx, uint64_t* klo, uint64_t* khi,
                                                     int32_t* cover) {
   const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (h >= n) return;
-  cover[h] = -1;
-  if (!pass[h]) return;
-  const plast_hit_t r = hits[h];
-  if (r.seq1 < 0 || r.seq1 >= A.a_nseq || r.seq2 < 0 || r.seq2 >= A.b_nseq) {
-    atomicOr(&hdr->status, 4);
-    return;
+  bool ok = false;
+  uint64_t lo = 0, hi = 0;
+  if (h < n) {
+    cover[h] = -1;
+    if (pass[h]) {
+      const plast_hit_t r = hits[h];
+      if (r.seq1 < 0 || r.seq1 >= A.a_nseq || r.seq2 < 0 || r.seq2 >= A.b_nseq) {
+        atomicOr(&hdr->status, 4);
+      } else {
+        const int la = seq_len(A.a_start, r.seq1), lb = seq_len(A.b_start, r.seq2);
+        if (la > A.max_len1 || lb > A.max_len2) {
+          atomicOr(&hdr->status, 1);
+        } else if (r.pos1 < 0 || r.pos1 >= la || r.pos2 < 0 || r.pos2 >= lb) {
+          atomicOr(&hdr->status, 4);
+        } else {
+          int g = gscore[h];
+          g = g < 0 ? 0 : (g > 16383 ? 16383 : g);
+          lo = ((uint64_t)(16383 - g) << (bp1 + bp2)) | ((uint64_t)r.pos1 << bp2) | (uint64_t)r.pos2;
+          hi = ((uint64_t)r.seq1 << b2) | (uint64_t)r.seq2;
+          ok = true;
+        }
+      }
+    }
   }
-  const int la = seq_len(A.a_start, r.seq1), lb = seq_len(A.b_start, r.seq2);
-  if (la > A.max_len1 || lb > A.max_len2) {
-    atomicOr(&hdr->status, 1);
-    return;
+  // one counter update per wavefront
+  const uint64_t mask = __ballot(ok);
+  if (!mask) return;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((long long)mask) - 1;
+  unsigned long long base = 0;
+  if (lane == leader) base = atomicAdd(&hdr->n_pass, (unsigned long long)__popcll(mask));
+  base = __shfl(base, leader);
+  if (ok) {
+    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    const unsigned long long c = base + __popcll(mask & below);
+    hidx[c] = (int32_t)h;
+    klo[c] = lo;
+    khi[c] = hi;
   }
-  if (r.pos1 < 0 || r.pos1 >= la || r.pos2 < 0 || r.pos2 >= lb) {
-    atomicOr(&hdr->status, 4);
-    return;
-  }
-  int g = gscore[h];
-  g = g < 0 ? 0 : (g > 16383 ? 16383 : g);
-  const unsigned long long c = atomicAdd(&hdr->n_pass, 1ull);
-  hidx[c] = (int32_t)h;
-  klo[c] = ((uint64_t)(16383 - g) << (bp1 + bp2)) | ((uint64_t)r.pos1 << bp2) | (uint64_t)r.pos2;
-  khi[c] = ((uint64_t)r.seq1 << b2) | (uint64_t)r.seq2;
 }
 
 __global__ __launch_bounds__(64) void k_align_clear(AlignHeader* hdr) {
@@ -225,10 +250,17 @@ __global__ __launch_bounds__(64) void k_rs_scatter(const int32_t* perm_in, const
 __global__ __launch_bounds__(256) void k_align_heads(const int32_t* perm, const uint64_t* khi, AlignHeader* hdr,
                                                      int32_t* heads) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (int64_t)hdr->n_pass) return;
-  if (i == 0 || khi[perm[i]] != khi[perm[i - 1]]) {
-    const unsigned long long g = atomicAdd(&hdr->n_groups, 1ull);
-    heads[g] = (int32_t)i;
+  const bool head = i < (int64_t)hdr->n_pass && (i == 0 || khi[perm[i]] != khi[perm[i - 1]]);
+  const uint64_t mask = __ballot(head);
+  if (!mask) return;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((long long)mask) - 1;
+  unsigned long long base = 0;
+  if (lane == leader) base = atomicAdd(&hdr->n_groups, (unsigned long long)__popcll(mask));
+  base = __shfl(base, leader);
+  if (head) {
+    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    heads[base + __popcll(mask & below)] = (int32_t)i;
   }
 }
 
@@ -246,76 +278,142 @@ __device__ __forceinline__ int shr1(int old, int v) {
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// One side.  x (lx letters, step dx) runs down the rows, y (ly letters) across
-// the columns; dir = +1 (pairs a[p1 + i - 1], b[p2 + j - 1]) or -1 (pairs
-// a[p1 - i], b[p2 - j]).  Appends the side's pieces to P (count *np).
-__device__ __forceinline__ SideStats align_side(const AlignArgs& A, const uint8_t* x, int lx, int dx, const uint8_t* y, int ly,
-                                int dy, int dir, int p1, int p2, int owner, const int8_t* mat, uint8_t* xb,
-                                uint8_t* yb, int2* strip, uint32_t* walk, uint32_t* tb, Piece* P, int* np,
-                                int32_t* status) {
+// The strips of one DP over lx rows and the columns 0 .. steps - 64 (x letters
+// in xb, y letters by column in yb, sentinels past both ends, the row above
+// strip 0 in strip[]).
+//
+// Each lane carries H - open - extend (hm) and F one lane down per step, so
+// that F(i, j) = max(F(i-1, j) - extend, hm(i-1, j)), E likewise from the left,
+// and the diagonal is hm(i-1, j-1) + T[x][y] with T = score + open + extend.
+// Every register starts a strip at NEG and column 0 of row 0 feeds lane 0, so
+// column 0 comes out of the same recurrence; letters past either end are the
+// sentinel, whose negative T entry makes every cell beyond the matrix strictly
+// smaller than some cell inside it, so the best needs no range test.
+// TRACE = false: scores only, the lane's best and its position ((strip << 16) |
+// step); TRACE = true: the 4-bit trace of every cell into tb, no best.
+template <bool TRACE>
+__device__ __forceinline__ void side_dp(int lx, int ly, int steps, int ge, int oe, const int16_t* T, int16_t* prof,
+                                        const uint8_t* xb, const int* yb, int2* strip, uint32_t* tb, int& best,
+                                        int& bpos) {
   const int lane = threadIdx.x;
-  const int ge = A.gap_extend, oe = A.gap_open + A.gap_extend;
-  SideStats st = {0, 0, 0, 0, 0, 0, 0};
-  if (lx == 0 || ly == 0) return st;
-  for (int k = lane; k < lx; k += 64) xb[k] = x[(int64_t)k * dx];
-  for (int k = lane; k <= ly; k += 64) yb[k] = k ? y[(int64_t)(k - 1) * dy] : 0;
-  for (int k = lane; k <= ly; k += 64) strip[k] = make_int2(k ? -(oe + (k - 1) * ge) : 0, kANeg);
-  __syncthreads();
-
-  const int nu8 = (ly + 71) >> 3;
+  const int nu8 = steps >> 3;
   const int strips = (lx + 63) >> 6;
-  int best = 0, bpos = 0;
   for (int s = 0; s < strips; ++s) {
-    const int i = s * 64 + lane + 1;
-    const bool rowv = i <= lx;
-    const int8_t* mrow = mat + (rowv ? xb[i - 1] : 0) * kMatStride;
-    const int bnd = -(oe + (i - 1) * ge);  // H(i, 0) = F(i, 0)
-    int hout = 0, fout = kANeg, yl = 0;    // passed one lane down each step
-    int hup = 0, hleft = bnd, eleft = kANeg;
-    uint32_t acc = 0;
+    // this strip's profile: prof[y * 64 + lane] = T[x of the lane's row][y], so
+    // that every lane's lookup falls in its own LDS bank
+    {
+      const int16_t* trow = T + (int)xb[s * 64 + lane] * kTStride;
+      int16_t v[21];
+#pragma unroll
+      for (int yc = 0; yc < 21; ++yc) v[yc] = trow[yc];
+#pragma unroll
+      for (int yc = 0; yc < 21; ++yc) prof[yc * 64 + lane] = v[yc];
+    }
+    const int16_t* pcol = prof + lane;
+    int hm = kANeg, f = kANeg, yl = kPadCode, hup = kANeg, eleft = kANeg, hmleft = kANeg;
     uint32_t* tbs = tb + (size_t)s * nu8 * 64 + lane;
-    const int steps = ly + 64;
-    for (int t = 0; t < steps; ++t) {
-      const int tc = t < ly ? t : ly;
-      const int2 fd = strip[tc];
-      const int hdiag = hup;
-      hup = shr1(fd.x, hout);
-      const int fup = shr1(fd.y, fout);
-      yl = shr1((int)yb[tc], yl);
-      const int j = t - lane;
-      const int e1 = eleft - ge, e2 = hleft - oe;
-      const int e = max(e1, e2);
-      const int f1 = fup - ge, f2 = hup - oe;
-      const int f = max(f1, f2);
-      const int d = hdiag + (int)mrow[yl];
-      int h = max(max(d, e), f);
-      const uint32_t nib = (h == d ? 0u : (h == e ? 1u : 2u)) | (e2 >= e1 ? 4u : 0u) | (f2 >= f1 ? 8u : 0u);
-      acc |= nib << ((t & 7) * 4);
-      const bool valid = rowv && j >= 1 && j <= ly;
-      if (valid && h > best) {
-        best = h;
-        bpos = (i << 16) | j;
+    const int sbase = s << 16;
+    // Only lane 0 takes its inputs from LDS (the others from the lane above),
+    // so only lane 0 reads them: a 64-lane broadcast would cost the LDS the
+    // bandwidth of 64 reads.
+    int4 s0 = make_int4(0, 0, 0, 0), s1 = s0, s2 = s0, s3 = s0, y0 = s0, y1 = s0;
+    for (int t8 = 0; t8 < steps; t8 += 8) {
+      if (lane == 0) {
+        const int4* sf = (const int4*)(strip + t8);
+        const int4* yf = (const int4*)(yb + t8);
+        s0 = sf[0];
+        s1 = sf[1];
+        s2 = sf[2];
+        s3 = sf[3];
+        y0 = yf[0];
+        y1 = yf[1];
       }
-      int fo = f, eo = e;
-      if (j == 0) {
-        h = bnd;
-        fo = bnd;
-        eo = kANeg;
+      const int fh[8] = {s0.x, s0.z, s1.x, s1.z, s2.x, s2.z, s3.x, s3.z};
+      const int ff[8] = {s0.y, s0.w, s1.y, s1.w, s2.y, s2.w, s3.y, s3.w};
+      const int fy[8] = {y0.x, y0.y, y0.z, y0.w, y1.x, y1.y, y1.z, y1.w};
+      int oh[8], of[8];
+      uint32_t acc = 0;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int hdiag = hup;
+        hup = shr1(fh[k], hm);
+        const int fup = shr1(ff[k], f);
+        yl = shr1(fy[k], yl);
+        const int e1 = eleft - ge;
+        const int e = max(e1, hmleft);
+        const int f1 = fup - ge;
+        f = max(f1, hup);
+        const int d = hdiag + (int)pcol[yl * 64];
+        const int h = max(max(d, e), f);
+        if (TRACE) {
+          const uint32_t nib =
+              (h == d ? 0u : (h == e ? 1u : 2u)) | (hmleft >= e1 ? 4u : 0u) | (hup >= f1 ? 8u : 0u);
+          acc |= nib << (4 * k);
+        } else if (h > best) {
+          best = h;
+          bpos = sbase + t8 + k;
+        }
+        hm = h - oe;
+        hmleft = hm;
+        eleft = e;
+        oh[k] = hm;
+        of[k] = f;
       }
-      hout = h;
-      fout = fo;
-      hleft = h;
-      eleft = eo;
-      if (lane == 63 && j >= 0 && j <= ly) strip[j] = make_int2(h, fo);
-      if ((t & 7) == 7 || t == steps - 1) {
-        tbs[(t >> 3) * 64] = acc;
-        acc = 0;
+      if (TRACE) tbs[(t8 >> 3) * 64] = acc;
+      if (lane == 63) {  // lane 63 finished columns t8 - 63 .. t8 - 56 of the strip's last row
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int j = t8 + k - 63;
+          if (j >= 0 && j <= ly) strip[j] = make_int2(oh[k], of[k]);
+        }
       }
     }
     __syncthreads();
   }
+}
+
+// Letters of a DP over lx x ly: x past lx and y past ly (and column 0) are the
+// sentinel; the row above strip 0 is row 0: hm(0, 0) = -oe, hm(0, k) =
+// -(oe + (k - 1) ge) - oe, F = NEG, and NEG past ly.
+__device__ __forceinline__ void side_pad(int lx, int ly, int steps, int ge, int oe, uint8_t* xb, int* yb,
+                                         int2* strip) {
+  const int lane = threadIdx.x;
+  for (int k = lx + lane; k < lx + 64; k += 64) xb[k] = (uint8_t)kPadCode;
+  for (int k = ly + 1 + lane; k < steps; k += 64) yb[k] = kPadCode;
+  if (lane == 0) yb[0] = kPadCode;
+  for (int k = lane; k < steps; k += 64)
+    strip[k] = make_int2(k == 0 ? -oe : (k <= ly ? -(2 * oe + (k - 1) * ge) : kANeg), kANeg);
+  __syncthreads();
+}
+
+// One side.  x (lx letters, step dx) runs down the rows, y (ly letters) across
+// the columns; dir = +1 (pairs a[p1 + i - 1], b[p2 + j - 1]) or -1 (pairs
+// a[p1 - i], b[p2 - j]).  A score pass over the whole matrix finds the best and
+// its end cell; a trace pass over rows 1..i_end and columns 1..j_end (which
+// depend on no other cell) recomputes the same values with their traces, and
+// the trace-back reads those.  Appends the side's pieces to P (count np).
+__device__ __forceinline__ SideStats align_side(const AlignArgs& A, const uint8_t* x, int lx, int dx,
+                                                const uint8_t* y, int ly, int dy, int dir, int p1, int p2, int owner,
+                                                const int16_t* T, int16_t* prof, uint8_t* xb, int* yb, int2* strip,
+                                                uint32_t* walk, uint32_t* tb, Piece* P, int& np, int32_t* status) {
+  const int lane = threadIdx.x;
+  const int ge = A.gap_extend, oe = A.gap_open + A.gap_extend;
+  SideStats st = {0, 0, 0, 0, 0, 0, 0};
+  if (lx == 0 || ly == 0) return st;
+  const int steps = (ly + 64 + 7) & ~7;
+  for (int k = lane; k < lx; k += 64) xb[k] = x[(int64_t)k * dx];
+  for (int k = lane; k < ly; k += 64) yb[k + 1] = (int)y[(int64_t)k * dy];
+  side_pad(lx, ly, steps, ge, oe, xb, yb, strip);
+  int best = 0, bpos = 0;  // bpos = (strip << 16) | step of the lane's best cell; 0: cell (0, 0)
+  side_dp<false>(lx, ly, steps, ge, oe, T, prof, xb, yb, strip, tb, best, bpos);
 
   // best over the wavefront: largest value, then first cell in row-major order
+  int key = 0;
+  if (bpos != 0) {
+    const int s = bpos >> 16, t = bpos & 0xffff;
+    key = ((s * 64 + lane + 1) << 16) | (t - lane);
+  }
+  bpos = key;
   for (int o = 32; o >= 1; o >>= 1) {
     const int ob = __shfl_xor(best, o), op = __shfl_xor(bpos, o);
     if (ob > best || (ob == best && op < bpos)) {
@@ -329,8 +427,21 @@ __device__ __forceinline__ SideStats align_side(const AlignArgs& A, const uint8_
   st.i_end = bpos >> 16;
   st.j_end = bpos & 0xffff;
 
-  // trace-back, uniform across the wavefront
-  __threadfence();
+  // the trace of the rectangle up to the end cell
+  int nu8 = 0;
+  if (st.i_end > 0 && st.j_end > 0) {
+    const int steps2 = (st.j_end + 64 + 7) & ~7;
+    side_pad(st.i_end, st.j_end, steps2, ge, oe, xb, yb, strip);
+    int unused0 = 0, unused1 = 0;
+    side_dp<true>(st.i_end, st.j_end, steps2, ge, oe, T, prof, xb, yb, strip, tb, unused0, unused1);
+    nu8 = steps2 >> 3;
+  }
+
+  // trace-back, uniform across the wavefront.  The trace and the pieces are
+  // private to this wavefront and re-read by it on the same compute unit, so
+  // ordering at workgroup scope suffices (an agent-scope fence would write back
+  // the whole L2 of the XCD).
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
   int i = st.i_end, j = st.j_end;
   int state = 0;           // 0: H, 1: E, 2: F
   int prev = 0;            // last move: 0 none, 1 D, 2 E, 3 F
@@ -338,10 +449,10 @@ __device__ __forceinline__ SideStats align_side(const AlignArgs& A, const uint8_
   int blk_s = -1, blk_g0 = 0;
   auto close_run = [&]() {
     if (run_a >= 0) {
-      const int k = *np;
+      const int k = np;
       if (k < A.max_pieces) {
         if (lane == 0) P[k] = Piece{run_diag, min(run_a, run_b), max(run_a, run_b) + 1, owner};
-        *np = k + 1;
+        np = k + 1;
       } else if (lane == 0) {
         atomicOr(status, 2);
       }
@@ -404,7 +515,7 @@ __device__ __forceinline__ SideStats align_side(const AlignArgs& A, const uint8_
     }
   }
   close_run();
-  __threadfence();
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
   return st;
 }
 
@@ -413,13 +524,18 @@ __global__ __launch_bounds__(64) void k_align(AlignArgs A, const plast_hit_t* hi
                                               AlignHeader* hdr, uint32_t* tb_all, size_t tb_words, Piece* pieces_all,
                                               plast_alignment_t* out, int32_t* cover) {
   extern __shared__ __align__(16) uint8_t lds[];
-  int8_t* mat = (int8_t*)lds;
-  uint8_t* xb = lds + 20 * kMatStride;
-  uint8_t* yb = xb + ((A.max_len1 + 64 + 15) & ~15);
-  int2* strip = (int2*)(yb + ((A.max_len2 + 64 + 15) & ~15));
-  uint32_t* walk = (uint32_t*)(strip + A.max_len2 + 1);
+  int16_t* T = (int16_t*)lds;
+  int16_t* prof = T + 21 * kTStride;
+  uint8_t* xb = (uint8_t*)(prof + 21 * 64);
+  int* yb = (int*)(xb + ((A.max_len1 + 64 + 15) & ~15));
+  int2* strip = (int2*)(yb + A.max_len2 + 72);
+  uint32_t* walk = (uint32_t*)strip;  // the trace-back runs after the DP of its side
   const int lane = threadIdx.x;
-  for (int k = lane; k < 400; k += 64) mat[(k / 20) * kMatStride + k % 20] = A.mat[k];
+  const int oe = A.gap_open + A.gap_extend;
+  for (int k = lane; k < 21 * kTStride; k += 64) {
+    const int xa = k / kTStride, yc = k % kTStride;
+    T[k] = (int16_t)((xa < 20 && yc < 20) ? (int)A.mat[xa * 20 + yc] + oe : kWall);
+  }
   __syncthreads();
 
   uint32_t* tb = tb_all + (size_t)blockIdx.x * tb_words;
@@ -467,10 +583,10 @@ __global__ __launch_bounds__(64) void k_align(AlignArgs A, const plast_hit_t* hi
       const uint8_t* a = A.a_codes + A.a_start[s1];
       const uint8_t* b = A.b_codes + A.b_start[s2];
       const int la = seq_len(A.a_start, s1), lb = seq_len(A.b_start, s2);
-      const SideStats R = align_side(A, a + p1, la - p1, 1, b + p2, lb - p2, 1, +1, p1, p2, h, mat, xb, yb, strip,
-                                     walk, tb, P, &np, &hdr->status);
-      const SideStats L = align_side(A, a + p1 - 1, p1, -1, b + p2 - 1, p2, -1, -1, p1, p2, h, mat, xb, yb, strip,
-                                     walk, tb, P, &np, &hdr->status);
+      const SideStats R = align_side(A, a + p1, la - p1, 1, b + p2, lb - p2, 1, +1, p1, p2, h, T, prof, xb, yb, strip,
+                                     walk, tb, P, np, &hdr->status);
+      const SideStats L = align_side(A, a + p1 - 1, p1, -1, b + p2 - 1, p2, -1, -1, p1, p2, h, T, prof, xb, yb, strip,
+                                     walk, tb, P, np, &hdr->status);
       if (lane == 0) {
         const unsigned long long o = atomicAdd(&hdr->n_out, 1ull);
         plast_alignment_t rec;
@@ -490,7 +606,6 @@ __global__ __launch_bounds__(64) void k_align(AlignArgs A, const plast_hit_t* hi
         rec.hit = h;
         out[o] = rec;
       }
-      __threadfence();
     }
   }
 }
