@@ -127,7 +127,7 @@ size_t align_lds_bytes(int max_len1, int max_len2) {
   size_t b = sizeof(int16_t) * 21 * kTStride;
   b += sizeof(int16_t) * 21 * 64;
   b += align_up((size_t)max_len1 + 64, 16);
-  b += sizeof(int) * ((size_t)max_len2 + 72);
+  b += align_up((size_t)max_len2 + 136, 16);   // y letters, 64 sentinels before column 0
   b += strip_bytes(max_len2);
   return b;
 }
@@ -293,7 +293,7 @@ __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlan
 // step); TRACE = true: the 4-bit trace of every cell into tb, no best.
 template <bool TRACE>
 __device__ __forceinline__ void side_dp(int lx, int ly, int steps, int ge, int oe, const int16_t* T, int16_t* prof,
-                                        const uint8_t* xb, const int* yb, int2* strip, uint32_t* tb, int& best,
+                                        const uint8_t* xb, const uint8_t* yb, int2* strip, uint32_t* tb, int& best,
                                         int& bpos) {
   const int lane = threadIdx.x;
   const int nu8 = steps >> 3;
@@ -310,27 +310,27 @@ __device__ __forceinline__ void side_dp(int lx, int ly, int steps, int ge, int o
       for (int yc = 0; yc < 21; ++yc) prof[yc * 64 + lane] = v[yc];
     }
     const int16_t* pcol = prof + lane;
-    int hm = kANeg, f = kANeg, yl = kPadCode, hup = kANeg, eleft = kANeg, hmleft = kANeg;
+    const uint8_t* ycol = yb + 64 - lane;  // the letter of this lane's column t - lane at step t
+    int hm = kANeg, f = kANeg, hup = kANeg, eleft = kANeg, hmleft = kANeg;
     uint32_t* tbs = tb + (size_t)s * nu8 * 64 + lane;
     const int sbase = s << 16;
     // Only lane 0 takes its inputs from LDS (the others from the lane above),
     // so only lane 0 reads them: a 64-lane broadcast would cost the LDS the
     // bandwidth of 64 reads.
-    int4 s0 = make_int4(0, 0, 0, 0), s1 = s0, s2 = s0, s3 = s0, y0 = s0, y1 = s0;
+    int4 s0 = make_int4(0, 0, 0, 0), s1 = s0, s2 = s0, s3 = s0;
     for (int t8 = 0; t8 < steps; t8 += 8) {
       if (lane == 0) {
         const int4* sf = (const int4*)(strip + t8);
-        const int4* yf = (const int4*)(yb + t8);
         s0 = sf[0];
         s1 = sf[1];
         s2 = sf[2];
         s3 = sf[3];
-        y0 = yf[0];
-        y1 = yf[1];
       }
       const int fh[8] = {s0.x, s0.z, s1.x, s1.z, s2.x, s2.z, s3.x, s3.z};
       const int ff[8] = {s0.y, s0.w, s1.y, s1.w, s2.y, s2.w, s3.y, s3.w};
-      const int fy[8] = {y0.x, y0.y, y0.z, y0.w, y1.x, y1.y, y1.z, y1.w};
+      int sc[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) sc[k] = pcol[(int)ycol[t8 + k] * 64];
       int oh[8], of[8];
       uint32_t acc = 0;
 #pragma unroll
@@ -338,12 +338,11 @@ __device__ __forceinline__ void side_dp(int lx, int ly, int steps, int ge, int o
         const int hdiag = hup;
         hup = shr1(fh[k], hm);
         const int fup = shr1(ff[k], f);
-        yl = shr1(fy[k], yl);
         const int e1 = eleft - ge;
         const int e = max(e1, hmleft);
         const int f1 = fup - ge;
         f = max(f1, hup);
-        const int d = hdiag + (int)pcol[yl * 64];
+        const int d = hdiag + sc[k];
         const int h = max(max(d, e), f);
         if (TRACE) {
           const uint32_t nib =
@@ -375,12 +374,13 @@ __device__ __forceinline__ void side_dp(int lx, int ly, int steps, int ge, int o
 // Letters of a DP over lx x ly: x past lx and y past ly (and column 0) are the
 // sentinel; the row above strip 0 is row 0: hm(0, 0) = -oe, hm(0, k) =
 // -(oe + (k - 1) ge) - oe, F = NEG, and NEG past ly.
-__device__ __forceinline__ void side_pad(int lx, int ly, int steps, int ge, int oe, uint8_t* xb, int* yb,
+__device__ __forceinline__ void side_pad(int lx, int ly, int steps, int ge, int oe, uint8_t* xb, uint8_t* yb,
                                          int2* strip) {
   const int lane = threadIdx.x;
   for (int k = lx + lane; k < lx + 64; k += 64) xb[k] = (uint8_t)kPadCode;
-  for (int k = ly + 1 + lane; k < steps; k += 64) yb[k] = kPadCode;
-  if (lane == 0) yb[0] = kPadCode;
+  for (int k = ly + 1 + lane; k < steps; k += 64) yb[64 + k] = (uint8_t)kPadCode;
+  yb[lane] = (uint8_t)kPadCode;  // columns -64 .. -1
+  if (lane == 0) yb[64] = (uint8_t)kPadCode;
   for (int k = lane; k < steps; k += 64)
     strip[k] = make_int2(k == 0 ? -oe : (k <= ly ? -(2 * oe + (k - 1) * ge) : kANeg), kANeg);
   __syncthreads();
@@ -394,7 +394,7 @@ __device__ __forceinline__ void side_pad(int lx, int ly, int steps, int ge, int 
 // the trace-back reads those.  Appends the side's pieces to P (count np).
 __device__ __forceinline__ SideStats align_side(const AlignArgs& A, const uint8_t* x, int lx, int dx,
                                                 const uint8_t* y, int ly, int dy, int dir, int p1, int p2, int owner,
-                                                const int16_t* T, int16_t* prof, uint8_t* xb, int* yb, int2* strip,
+                                                const int16_t* T, int16_t* prof, uint8_t* xb, uint8_t* yb, int2* strip,
                                                 uint32_t* walk, uint32_t* tb, Piece* P, int& np, int32_t* status) {
   const int lane = threadIdx.x;
   const int ge = A.gap_extend, oe = A.gap_open + A.gap_extend;
@@ -402,7 +402,7 @@ __device__ __forceinline__ SideStats align_side(const AlignArgs& A, const uint8_
   if (lx == 0 || ly == 0) return st;
   const int steps = (ly + 64 + 7) & ~7;
   for (int k = lane; k < lx; k += 64) xb[k] = x[(int64_t)k * dx];
-  for (int k = lane; k < ly; k += 64) yb[k + 1] = (int)y[(int64_t)k * dy];
+  for (int k = lane; k < ly; k += 64) yb[65 + k] = y[(int64_t)k * dy];
   side_pad(lx, ly, steps, ge, oe, xb, yb, strip);
   int best = 0, bpos = 0;  // bpos = (strip << 16) | step of the lane's best cell; 0: cell (0, 0)
   side_dp<false>(lx, ly, steps, ge, oe, T, prof, xb, yb, strip, tb, best, bpos);
@@ -481,7 +481,7 @@ __device__ __forceinline__ SideStats align_side(const AlignArgs& A, const uint8_
     if (state == 0) {
       const uint32_t src = nib & 3u;
       if (src == 0) {
-        const int xa = xb[i - 1], yc = yb[j];
+        const int xa = xb[i - 1], yc = yb[64 + j];
         const int pa = dir > 0 ? p1 + i - 1 : p1 - i;
         const int pb = dir > 0 ? p2 + j - 1 : p2 - j;
         if (run_a < 0) {
@@ -527,8 +527,8 @@ __global__ __launch_bounds__(64) void k_align(AlignArgs A, const plast_hit_t* hi
   int16_t* T = (int16_t*)lds;
   int16_t* prof = T + 21 * kTStride;
   uint8_t* xb = (uint8_t*)(prof + 21 * 64);
-  int* yb = (int*)(xb + ((A.max_len1 + 64 + 15) & ~15));
-  int2* strip = (int2*)(yb + A.max_len2 + 72);
+  uint8_t* yb = xb + ((A.max_len1 + 64 + 15) & ~15);
+  int2* strip = (int2*)(yb + ((A.max_len2 + 136 + 15) & ~15));
   uint32_t* walk = (uint32_t*)strip;  // the trace-back runs after the DP of its side
   const int lane = threadIdx.x;
   const int oe = A.gap_open + A.gap_extend;
