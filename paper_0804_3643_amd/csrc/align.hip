@@ -43,6 +43,8 @@ constexpr size_t kMaxLds = 160 * 1024;
 struct AlignHeader {
   int32_t status;                 // bit 1: sequence longer than its max_len; 2: piece list full; 4: bad hit
   int32_t sort_total;
+  int32_t pass_total;             // passing hits (scan total of the per-wavefront counts)
+  int32_t group_total;            // sequence pairs (likewise)
   unsigned long long n_pass;
   unsigned long long n_groups;
   unsigned long long next_group;
@@ -66,7 +68,7 @@ struct AlignArgs {
 };
 
 struct AlignLayout {
-  size_t hdr, hidx, klo, khi, perm0, perm1, counts, scan_tmp, heads, tb, pieces, total;
+  size_t hdr, hidx, klo, khi, perm0, perm1, counts, pcount, scan_tmp, heads, tb, pieces, total;
   int64_t tiles;
   size_t tb_words_per_wave;
 };
@@ -102,8 +104,12 @@ AlignLayout align_layout(int64_t n, const plast_align_params_t& p, int64_t waves
   off = align_up(off + sizeof(int32_t) * (size_t)n, 256);
   L.counts = off;
   off = align_up(off + sizeof(int32_t) * 256 * (size_t)L.tiles, 256);
+  const int64_t wave_slots = (n + 63) / 64 + 1;
+  L.pcount = off;
+  off = align_up(off + sizeof(int32_t) * (size_t)wave_slots, 256);
   L.scan_tmp = off;
-  off = align_up(off + scan_tmp_bytes(256 * L.tiles), 256);
+  const int64_t scan_n = 256 * L.tiles > wave_slots ? 256 * L.tiles : wave_slots;
+  off = align_up(off + scan_tmp_bytes(scan_n), 256);
   L.heads = off;
   off = align_up(off + sizeof(int32_t) * (size_t)n, 256);
   L.tb_words_per_wave = (size_t)tb_words(p.max_len1, p.max_len2);
@@ -138,57 +144,66 @@ __device__ __forceinline__ int seq_len(const int64_t* start, int s) {
 
 // ------------------------------------------------------------------ keys and sort
 
-// Passing hits get a compact index c; their sort keys are (seq1, seq2) in khi
-// and (16383 - gscore, pos1, pos2) in klo, so ascending order is the group
-// order.  cover[] starts at -1 for every hit.
+// A passing hit with ids and positions inside its banks (and sequences within
+// max_len): it gets a compact index.  Error bits otherwise (count pass only).
+__device__ __forceinline__ bool align_hit_ok(const AlignArgs& A, const plast_hit_t* hits, const uint8_t* pass,
+                                             int64_t h, int64_t n, AlignHeader* hdr, bool report) {
+  if (h >= n || !pass[h]) return false;
+  const plast_hit_t r = hits[h];
+  if (r.seq1 < 0 || r.seq1 >= A.a_nseq || r.seq2 < 0 || r.seq2 >= A.b_nseq) {
+    if (report) atomicOr(&hdr->status, 4);
+    return false;
+  }
+  const int la = seq_len(A.a_start, r.seq1), lb = seq_len(A.b_start, r.seq2);
+  if (la > A.max_len1 || lb > A.max_len2) {
+    if (report) atomicOr(&hdr->status, 1);
+    return false;
+  }
+  if (r.pos1 < 0 || r.pos1 >= la || r.pos2 < 0 || r.pos2 >= lb) {
+    if (report) atomicOr(&hdr->status, 4);
+    return false;
+  }
+  return true;
+}
+
+// Compaction of the passing hits in two passes (no shared counter: one
+// atomic per wavefront on a single address serialises in L2): per-wavefront
+// counts, an exclusive scan, then each wavefront writes at its offset.
+__global__ __launch_bounds__(256) void k_align_count(AlignArgs A, const plast_hit_t* hits, const uint8_t* pass,
+                                                     int64_t n, AlignHeader* hdr, int32_t* pcount, int32_t* cover) {
+  const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (h < n) cover[h] = -1;
+  const uint64_t mask = __ballot(align_hit_ok(A, hits, pass, h, n, hdr, true));
+  if ((threadIdx.x & 63) == 0 && (h >> 6) < (n + 63) / 64) pcount[h >> 6] = (int32_t)__popcll(mask);
+}
+
+// Sort keys of the compacted hits: (seq1, seq2) in khi, (16383 - gscore, pos1,
+// pos2) in klo, so ascending order is the group order.
 __global__ __launch_bounds__(256) void k_align_keys(AlignArgs A, const plast_hit_t* hits, const int32_t* gscore,
                                                     const uint8_t* pass, int64_t n, int bp1, int bp2, int b2,
-                                                    AlignHeader* hdr, int32_t* hidx, uint64_t* klo, uint64_t* khi,
-                                                    int32_t* cover) {
+                                                    AlignHeader* hdr, const int32_t* poffset, int32_t* hidx,
+                                                    uint64_t* klo, uint64_t* khi) {
   const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  bool ok = false;
-  uint64_t lo = 0, hi = 0;
-  if (h < n) {
-    cover[h] = -1;
-    if (pass[h]) {
-      const plast_hit_t r = hits[h];
-      if (r.seq1 < 0 || r.seq1 >= A.a_nseq || r.seq2 < 0 || r.seq2 >= A.b_nseq) {
-        atomicOr(&hdr->status, 4);
-      } else {
-        const int la = seq_len(A.a_start, r.seq1), lb = seq_len(A.b_start, r.seq2);
-        if (la > A.max_len1 || lb > A.max_len2) {
-          atomicOr(&hdr->status, 1);
-        } else if (r.pos1 < 0 || r.pos1 >= la || r.pos2 < 0 || r.pos2 >= lb) {
-          atomicOr(&hdr->status, 4);
-        } else {
-          int g = gscore[h];
-          g = g < 0 ? 0 : (g > 16383 ? 16383 : g);
-          lo = ((uint64_t)(16383 - g) << (bp1 + bp2)) | ((uint64_t)r.pos1 << bp2) | (uint64_t)r.pos2;
-          hi = ((uint64_t)r.seq1 << b2) | (uint64_t)r.seq2;
-          ok = true;
-        }
-      }
-    }
-  }
-  // one counter update per wavefront
+  const bool ok = align_hit_ok(A, hits, pass, h, n, hdr, false);
   const uint64_t mask = __ballot(ok);
-  if (!mask) return;
+  if (!ok) return;
   const int lane = threadIdx.x & 63;
-  const int leader = __ffsll((long long)mask) - 1;
-  unsigned long long base = 0;
-  if (lane == leader) base = atomicAdd(&hdr->n_pass, (unsigned long long)__popcll(mask));
-  base = __shfl(base, leader);
-  if (ok) {
-    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
-    const unsigned long long c = base + __popcll(mask & below);
-    hidx[c] = (int32_t)h;
-    klo[c] = lo;
-    khi[c] = hi;
-  }
+  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  const int64_t c = (int64_t)poffset[h >> 6] + __popcll(mask & below);
+  const plast_hit_t r = hits[h];
+  int g = gscore[h];
+  g = g < 0 ? 0 : (g > 16383 ? 16383 : g);
+  hidx[c] = (int32_t)h;
+  klo[c] = ((uint64_t)(16383 - g) << (bp1 + bp2)) | ((uint64_t)r.pos1 << bp2) | (uint64_t)r.pos2;
+  khi[c] = ((uint64_t)r.seq1 << b2) | (uint64_t)r.seq2;
 }
 
 __global__ __launch_bounds__(64) void k_align_clear(AlignHeader* hdr) {
-  if (threadIdx.x == 0) *hdr = AlignHeader{0, 0, 0, 0, 0, 0};
+  if (threadIdx.x == 0) *hdr = AlignHeader{0, 0, 0, 0, 0, 0, 0, 0};
+}
+
+__global__ __launch_bounds__(64) void k_align_npass(AlignHeader* hdr) {
+  if (threadIdx.x == 0) hdr->n_pass = (unsigned long long)hdr->pass_total;
 }
 
 __global__ __launch_bounds__(256) void k_iota(int32_t* perm, const AlignHeader* hdr) {
@@ -247,21 +262,32 @@ __global__ __launch_bounds__(64) void k_rs_scatter(const int32_t* perm_in, const
   }
 }
 
-__global__ __launch_bounds__(256) void k_align_heads(const int32_t* perm, const uint64_t* khi, AlignHeader* hdr,
-                                                     int32_t* heads) {
+// First element of each sequence pair in sorted order, compacted in two passes
+// like the passing hits.
+__device__ __forceinline__ bool is_head(const int32_t* perm, const uint64_t* khi, const AlignHeader* hdr, int64_t i) {
+  return i < (int64_t)hdr->n_pass && (i == 0 || khi[perm[i]] != khi[perm[i - 1]]);
+}
+
+__global__ __launch_bounds__(256) void k_align_head_count(const int32_t* perm, const uint64_t* khi,
+                                                          const AlignHeader* hdr, int32_t* hcount) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool head = i < (int64_t)hdr->n_pass && (i == 0 || khi[perm[i]] != khi[perm[i - 1]]);
+  const uint64_t mask = __ballot(is_head(perm, khi, hdr, i));
+  if ((threadIdx.x & 63) == 0 && i < (int64_t)hdr->n_pass) hcount[i >> 6] = (int32_t)__popcll(mask);
+}
+
+__global__ __launch_bounds__(256) void k_align_heads(const int32_t* perm, const uint64_t* khi, AlignHeader* hdr,
+                                                     const int32_t* hoffset, int32_t* heads) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool head = is_head(perm, khi, hdr, i);
   const uint64_t mask = __ballot(head);
-  if (!mask) return;
+  if (!head) return;
   const int lane = threadIdx.x & 63;
-  const int leader = __ffsll((long long)mask) - 1;
-  unsigned long long base = 0;
-  if (lane == leader) base = atomicAdd(&hdr->n_groups, (unsigned long long)__popcll(mask));
-  base = __shfl(base, leader);
-  if (head) {
-    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
-    heads[base + __popcll(mask & below)] = (int32_t)i;
-  }
+  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  heads[hoffset[i >> 6] + __popcll(mask & below)] = (int32_t)i;
+}
+
+__global__ __launch_bounds__(64) void k_align_ngroups(AlignHeader* hdr) {
+  if (threadIdx.x == 0) hdr->n_groups = (unsigned long long)hdr->group_total;
 }
 
 // ------------------------------------------------------------------ alignment
@@ -676,8 +702,14 @@ int align_impl(const plast_index_t* a, const plast_index_t* b, const plast_hit_t
   const int b1 = bits_for(a->n_seqs), b2 = bits_for(b->n_seqs);
   hipLaunchKernelGGL(k_align_clear, dim3(1), dim3(64), 0, s, hdr);
   const unsigned nb = (unsigned)((n_hits + 255) / 256);
+  int32_t* pcount = (int32_t*)(ws + L.pcount);
+  const int64_t wave_slots = (n_hits + 63) / 64;
+  hipLaunchKernelGGL(k_align_count, dim3(nb ? nb : 1), dim3(256), 0, s, A, d_hits, d_pass, n_hits, hdr, pcount,
+                     d_cover);
+  exclusive_scan_i32(pcount, wave_slots, &hdr->pass_total, ws + L.scan_tmp, s);
+  hipLaunchKernelGGL(k_align_npass, dim3(1), dim3(64), 0, s, hdr);
   hipLaunchKernelGGL(k_align_keys, dim3(nb ? nb : 1), dim3(256), 0, s, A, d_hits, d_gscore, d_pass, n_hits, bp1, bp2,
-                     b2, hdr, hidx, klo, khi, d_cover);
+                     b2, hdr, (const int32_t*)pcount, hidx, klo, khi);
   AlignHeader h0;
   PLAST_HIP(hipMemcpyAsync(&h0, hdr, sizeof(h0), hipMemcpyDeviceToHost, s));
   PLAST_HIP(hipStreamSynchronize(s));
@@ -699,7 +731,11 @@ int align_impl(const plast_index_t* a, const plast_index_t* b, const plast_hit_t
         cur ^= 1;
       }
     }
-    hipLaunchKernelGGL(k_align_heads, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, perm[cur], khi, hdr, heads);
+    const unsigned mb = (unsigned)((m + 255) / 256);
+    hipLaunchKernelGGL(k_align_head_count, dim3(mb), dim3(256), 0, s, perm[cur], khi, hdr, pcount);
+    exclusive_scan_i32(pcount, (m + 63) / 64, &hdr->group_total, ws + L.scan_tmp, s);
+    hipLaunchKernelGGL(k_align_ngroups, dim3(1), dim3(64), 0, s, hdr);
+    hipLaunchKernelGGL(k_align_heads, dim3(mb), dim3(256), 0, s, perm[cur], khi, hdr, (const int32_t*)pcount, heads);
     const size_t lds = align_lds_bytes(p->max_len1, p->max_len2);
     PLAST_HIP(hipFuncSetAttribute((const void*)k_align, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL(k_align, dim3((unsigned)waves), dim3(64), lds, s, A, d_hits, hidx, perm[cur], khi, heads, hdr,
