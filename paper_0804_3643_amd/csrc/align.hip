@@ -41,7 +41,8 @@ constexpr int kWalkDwords = 512;    // trace-back window: 8 dwords (64 steps) x 
 constexpr size_t kMaxLds = 160 * 1024;
 
 struct AlignHeader {
-  int32_t status;                 // bit 1: sequence longer than its max_len; 2: piece list full; 4: bad hit
+  int32_t status;                 // bit 1: sequence longer than its max_len; 2: piece list full; 4: bad hit;
+                                  // 8: internal (end cell not found)
   int32_t sort_total;
   int32_t pass_total;             // passing hits (scan total of the per-wavefront counts)
   int32_t group_total;            // sequence pairs (likewise)
@@ -315,12 +316,14 @@ __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlan
 // column 0 comes out of the same recurrence; letters past either end are the
 // sentinel, whose negative T entry makes every cell beyond the matrix strictly
 // smaller than some cell inside it, so the best needs no range test.
-// TRACE = false: scores only, the lane's best and its position ((strip << 16) |
-// step); TRACE = true: the 4-bit trace of every cell into tb, no best.
+// TRACE = false: scores only; the lane's best value and the first block of 8
+// steps where it reached it, as (strip << 16) | (block start + 1).
+// TRACE = true: the 4-bit trace of every cell into tb, and in jf the first
+// column of row `row` (per lane: -1 elsewhere) whose H equals `target`.
 template <bool TRACE>
 __device__ __forceinline__ void side_dp(int lx, int ly, int steps, int ge, int oe, const int16_t* T, int16_t* prof,
                                         const uint8_t* xb, const uint8_t* yb, int2* strip, uint32_t* tb, int& best,
-                                        int& bpos) {
+                                        int& bpos, int row = 0, int target = 0, int* jf = nullptr) {
   const int lane = threadIdx.x;
   const int nu8 = steps >> 3;
   const int strips = (lx + 63) >> 6;
@@ -340,6 +343,7 @@ __device__ __forceinline__ void side_dp(int lx, int ly, int steps, int ge, int o
     int hm = kANeg, f = kANeg, hup = kANeg, eleft = kANeg, hmleft = kANeg;
     uint32_t* tbs = tb + (size_t)s * nu8 * 64 + lane;
     const int sbase = s << 16;
+    const bool my_row = TRACE && s * 64 + lane + 1 == row;
     // Only lane 0 takes its inputs from LDS (the others from the lane above),
     // so only lane 0 reads them: a 64-lane broadcast would cost the LDS the
     // bandwidth of 64 reads.
@@ -359,6 +363,7 @@ __device__ __forceinline__ void side_dp(int lx, int ly, int steps, int ge, int o
       for (int k = 0; k < 8; ++k) sc[k] = pcol[(int)ycol[t8 + k] * 64];
       int oh[8], of[8];
       uint32_t acc = 0;
+      int bmax = kANeg;
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
         const int hdiag = hup;
@@ -374,9 +379,9 @@ __device__ __forceinline__ void side_dp(int lx, int ly, int steps, int ge, int o
           const uint32_t nib =
               (h == d ? 0u : (h == e ? 1u : 2u)) | (hmleft >= e1 ? 4u : 0u) | (hup >= f1 ? 8u : 0u);
           acc |= nib << (4 * k);
-        } else if (h > best) {
-          best = h;
-          bpos = sbase + t8 + k;
+          if (my_row && h == target && *jf < 0) *jf = t8 + k - lane;
+        } else {
+          bmax = max(bmax, h);
         }
         hm = h - oe;
         hmleft = hm;
@@ -384,7 +389,12 @@ __device__ __forceinline__ void side_dp(int lx, int ly, int steps, int ge, int o
         oh[k] = hm;
         of[k] = f;
       }
-      if (TRACE) tbs[(t8 >> 3) * 64] = acc;
+      if (TRACE) {
+        tbs[(t8 >> 3) * 64] = acc;
+      } else if (bmax > best) {
+        best = bmax;
+        bpos = sbase + t8 + 1;
+      }
       if (lane == 63) {  // lane 63 finished columns t8 - 63 .. t8 - 56 of the strip's last row
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
@@ -430,14 +440,15 @@ __device__ __forceinline__ SideStats align_side(const AlignArgs& A, const uint8_
   for (int k = lane; k < lx; k += 64) xb[k] = x[(int64_t)k * dx];
   for (int k = lane; k < ly; k += 64) yb[65 + k] = y[(int64_t)k * dy];
   side_pad(lx, ly, steps, ge, oe, xb, yb, strip);
-  int best = 0, bpos = 0;  // bpos = (strip << 16) | step of the lane's best cell; 0: cell (0, 0)
+  int best = 0, bpos = 0;  // bpos = (strip << 16) | (block start + 1); 0: cell (0, 0)
   side_dp<false>(lx, ly, steps, ge, oe, T, prof, xb, yb, strip, tb, best, bpos);
 
-  // best over the wavefront: largest value, then first cell in row-major order
+  // best over the wavefront: largest value, then first row, then first block
+  // (a row belongs to one lane, so the block decides only within a row)
   int key = 0;
   if (bpos != 0) {
-    const int s = bpos >> 16, t = bpos & 0xffff;
-    key = ((s * 64 + lane + 1) << 16) | (t - lane);
+    const int s = bpos >> 16, t8 = (bpos & 0xffff) - 1;
+    key = ((s * 64 + lane + 1) << 16) | (t8 + 64);
   }
   bpos = key;
   for (int o = 32; o >= 1; o >>= 1) {
@@ -451,16 +462,27 @@ __device__ __forceinline__ SideStats align_side(const AlignArgs& A, const uint8_
   bpos = uni(bpos);
   st.best = best;
   st.i_end = bpos >> 16;
-  st.j_end = bpos & 0xffff;
+  st.j_end = 0;
 
-  // the trace of the rectangle up to the end cell
+  // The trace of rows 1..i_end up to the end of the best's block (those cells
+  // depend on no other); the end cell is the first cell of row i_end there
+  // whose H is the best.
   int nu8 = 0;
-  if (st.i_end > 0 && st.j_end > 0) {
-    const int steps2 = (st.j_end + 64 + 7) & ~7;
-    side_pad(st.i_end, st.j_end, steps2, ge, oe, xb, yb, strip);
-    int unused0 = 0, unused1 = 0;
-    side_dp<true>(st.i_end, st.j_end, steps2, ge, oe, T, prof, xb, yb, strip, tb, unused0, unused1);
+  if (st.i_end > 0) {
+    const int r_end = (st.i_end - 1) & 63, t8 = (bpos & 0xffff) - 64;
+    const int j_hi = min(ly, t8 + 7 - r_end);
+    const int steps2 = (j_hi + 64 + 7) & ~7;
+    side_pad(st.i_end, j_hi, steps2, ge, oe, xb, yb, strip);
+    int unused0 = 0, unused1 = 0, jf = -1;
+    side_dp<true>(st.i_end, j_hi, steps2, ge, oe, T, prof, xb, yb, strip, tb, unused0, unused1, st.i_end, best,
+                  &jf);
     nu8 = steps2 >> 3;
+    st.j_end = __shfl(jf, r_end);
+    st.j_end = uni(st.j_end);
+    if (st.j_end < 1) {  // cannot happen: the block holds a cell with the best value
+      if (lane == 0) atomicOr(status, 8);
+      st.j_end = j_hi;
+    }
   }
 
   // trace-back, uniform across the wavefront.  The trace and the pieces are
@@ -749,6 +771,7 @@ int align_impl(const plast_index_t* a, const plast_index_t* b, const plast_hit_t
   if (h0.status & 4) return set_error(PLAST_E_ARG, "a passing hit lies outside its banks");
   if (h0.status & 2) return set_error(PLAST_E_WORKSPACE, "a sequence pair needs more than max_pieces=%d pieces",
                                       p->max_pieces);
+  if (h0.status & 8) return set_error(PLAST_E_HIP, "internal: an alignment's end cell was not found");
   return PLAST_OK;
 }
 
