@@ -155,3 +155,33 @@ def test_align_config1_sampled_groups(B):
     got = rec[np.isin(rkey, pick)]
     assert np.array_equal(got, ref)
     assert np.array_equal(cov_p[sel], hit_of[rcov])
+
+
+def test_align_many_gaps_piece_overflow_and_bad_hits(B, cfg0):
+    """A copy with a deletion every 20 letters (alignments of 39 gap openings,
+    161 pieces in the pair): equal to the oracle with the default piece list,
+    PLAST_E_WORKSPACE with a 16-piece list.  A passing hit naming a sequence
+    outside its bank gives PLAST_E_ARG (the kernels check ids before reading)."""
+    rng = np.random.default_rng(31)
+    s = rng.integers(0, 20, 800)
+    keep = np.ones(800, bool)
+    keep[np.arange(20, 800, 20)] = False
+    bank1, bank2 = _bank([s]), _bank([s[keep]])
+    _say("align a pair with 40 deletions")
+    ia, ib, hits, gs, ps = _stage31(B, bank1, bank2)
+    rec, _ = _assert_parity(B, bank1, bank2, ia, ib, hits, gs, ps)
+    F = {k: i for i, k in enumerate(O.ALIGN_FIELDS)}
+    assert (rec[:, F["gap_opens"]] >= 30).all()
+    _say("align with a 16-piece list")
+    with pytest.raises(B.PlastError) as e:
+        B.align(ia, ib, hits, gs, ps, max_pieces=16)
+    assert e.value.code == B.E_WORKSPACE
+    _say("align with a hit outside its bank")
+    ia0, ib0, h0, g0, p0 = _stage31(B, cfg0.bank1, cfg0.bank2)
+    bad = h0.clone()
+    bad[0, 0] = ia0.n_seqs
+    p1 = p0.clone()
+    p1[0] = 1
+    with pytest.raises(B.PlastError) as e:
+        B.align(ia0, ib0, bad, g0, p1)
+    assert e.value.code == B.E_ARG
