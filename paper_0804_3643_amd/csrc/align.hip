@@ -309,19 +309,24 @@ __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlan
 // in xb, y letters by column in yb, sentinels past both ends, the row above
 // strip 0 in strip[]).
 //
-// Each lane carries H - open - extend (hm) and F one lane down per step, so
-// that F(i, j) = max(F(i-1, j) - extend, hm(i-1, j)), E likewise from the left,
-// and the diagonal is hm(i-1, j-1) + T[x][y] with T = score + open + extend.
-// Every register starts a strip at NEG and column 0 of row 0 feeds lane 0, so
-// column 0 comes out of the same recurrence; letters past either end are the
-// sentinel, whose negative T entry makes every cell beyond the matrix strictly
-// smaller than some cell inside it, so the best needs no range test.
-// TRACE = false: scores only; the lane's best value and the first block of 8
-// steps where it reached it, as (strip << 16) | (block start + 1).
+// Values are carried shifted by (i + j) * extend (H' = H + (i + j) ext, and
+// likewise E', F'), which removes the extension term from both gap recurrences:
+// E'(i, j) = max(E'(i, j-1), H'(i, j-1) - open), F' likewise from above, and
+// the diagonal is H'(i-1, j-1) + score + 2 ext.  Each lane carries hm = H' -
+// open and F' one lane down per step, so the diagonal is hm(i-1, j-1) + T[x][y]
+// with T = score + open + 2 extend.  On the skewed front every lane of a step
+// lies on the same anti-diagonal i + j = 64 s + 1 + t, so unshifting for the
+// best is one subtraction of a uniform value.  Every register starts a strip at
+// NEG and column 0 of row 0 feeds lane 0, so column 0 comes out of the same
+// recurrence; letters past either end are the sentinel, whose negative T entry
+// makes every cell beyond the matrix strictly smaller (unshifted) than some
+// cell inside it, so the best needs no range test.
+// TRACE = false: scores only; the lane's best (unshifted) value and the first
+// block of 8 steps where it reached it, as (strip << 16) | (block start + 1).
 // TRACE = true: the 4-bit trace of every cell into tb, and in jf the first
 // column of row `row` (per lane: -1 elsewhere) whose H equals `target`.
 template <bool TRACE>
-__device__ __forceinline__ void side_dp(int lx, int ly, int steps, int ge, int oe, const int16_t* T, int16_t* prof,
+__device__ __forceinline__ void side_dp(int lx, int ly, int steps, int ge, int go, const int16_t* T, int16_t* prof,
                                         const uint8_t* xb, const uint8_t* yb, int2* strip, uint32_t* tb, int& best,
                                         int& bpos, int row = 0, int target = 0, int* jf = nullptr) {
   const int lane = threadIdx.x;
@@ -364,31 +369,31 @@ __device__ __forceinline__ void side_dp(int lx, int ly, int steps, int ge, int o
       int oh[8], of[8];
       uint32_t acc = 0;
       int bmax = kANeg;
+      const int diag0 = (s * 64 + 1 + t8) * ge;  // (i + j) * extend of the block's first step
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
         const int hdiag = hup;
         hup = shr1(fh[k], hm);
         const int fup = shr1(ff[k], f);
-        const int e1 = eleft - ge;
-        const int e = max(e1, hmleft);
-        const int f1 = fup - ge;
-        f = max(f1, hup);
+        const int e = max(eleft, hmleft);
+        f = max(fup, hup);
         const int d = hdiag + sc[k];
         const int h = max(max(d, e), f);
         if (TRACE) {
           const uint32_t nib =
-              (h == d ? 0u : (h == e ? 1u : 2u)) | (hmleft >= e1 ? 4u : 0u) | (hup >= f1 ? 8u : 0u);
+              (h == d ? 0u : (h == e ? 1u : 2u)) | (hmleft >= eleft ? 4u : 0u) | (hup >= fup ? 8u : 0u);
           acc |= nib << (4 * k);
-          if (my_row && h == target && *jf < 0) *jf = t8 + k - lane;
+          if (my_row && h - (diag0 + k * ge) == target && *jf < 0) *jf = t8 + k - lane;
         } else {
-          bmax = max(bmax, h);
+          bmax = max(bmax, h - k * ge);
         }
-        hm = h - oe;
+        hm = h - go;
         hmleft = hm;
         eleft = e;
         oh[k] = hm;
         of[k] = f;
       }
+      if (!TRACE) bmax -= diag0;
       if (TRACE) {
         tbs[(t8 >> 3) * 64] = acc;
       } else if (bmax > best) {
@@ -396,10 +401,15 @@ __device__ __forceinline__ void side_dp(int lx, int ly, int steps, int ge, int o
         bpos = sbase + t8 + 1;
       }
       if (lane == 63) {  // lane 63 finished columns t8 - 63 .. t8 - 56 of the strip's last row
+        if (t8 >= 63 && t8 - 56 <= ly) {
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          const int j = t8 + k - 63;
-          if (j >= 0 && j <= ly) strip[j] = make_int2(oh[k], of[k]);
+          for (int k = 0; k < 8; ++k) strip[t8 + k - 63] = make_int2(oh[k], of[k]);
+        } else {
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const int j = t8 + k - 63;
+            if (j >= 0 && j <= ly) strip[j] = make_int2(oh[k], of[k]);
+          }
         }
       }
     }
@@ -408,9 +418,10 @@ __device__ __forceinline__ void side_dp(int lx, int ly, int steps, int ge, int o
 }
 
 // Letters of a DP over lx x ly: x past lx and y past ly (and column 0) are the
-// sentinel; the row above strip 0 is row 0: hm(0, 0) = -oe, hm(0, k) =
-// -(oe + (k - 1) ge) - oe, F = NEG, and NEG past ly.
-__device__ __forceinline__ void side_pad(int lx, int ly, int steps, int ge, int oe, uint8_t* xb, uint8_t* yb,
+// sentinel; the row above strip 0 is row 0, shifted: H'(0, 0) = 0 and H'(0, k)
+// = -(open + k ext) + k ext = -open, so hm(0, 0) = -open, hm(0, k) = -2 open,
+// F' = NEG, and NEG past ly.
+__device__ __forceinline__ void side_pad(int lx, int ly, int steps, int go, uint8_t* xb, uint8_t* yb,
                                          int2* strip) {
   const int lane = threadIdx.x;
   for (int k = lx + lane; k < lx + 64; k += 64) xb[k] = (uint8_t)kPadCode;
@@ -418,7 +429,7 @@ __device__ __forceinline__ void side_pad(int lx, int ly, int steps, int ge, int 
   yb[lane] = (uint8_t)kPadCode;  // columns -64 .. -1
   if (lane == 0) yb[64] = (uint8_t)kPadCode;
   for (int k = lane; k < steps; k += 64)
-    strip[k] = make_int2(k == 0 ? -oe : (k <= ly ? -(2 * oe + (k - 1) * ge) : kANeg), kANeg);
+    strip[k] = make_int2(k == 0 ? -go : (k <= ly ? -2 * go : kANeg), kANeg);
   __syncthreads();
 }
 
@@ -433,15 +444,15 @@ __device__ __forceinline__ SideStats align_side(const AlignArgs& A, const uint8_
                                                 const int16_t* T, int16_t* prof, uint8_t* xb, uint8_t* yb, int2* strip,
                                                 uint32_t* walk, uint32_t* tb, Piece* P, int& np, int32_t* status) {
   const int lane = threadIdx.x;
-  const int ge = A.gap_extend, oe = A.gap_open + A.gap_extend;
+  const int ge = A.gap_extend, go = A.gap_open;
   SideStats st = {0, 0, 0, 0, 0, 0, 0};
   if (lx == 0 || ly == 0) return st;
   const int steps = (ly + 64 + 7) & ~7;
   for (int k = lane; k < lx; k += 64) xb[k] = x[(int64_t)k * dx];
   for (int k = lane; k < ly; k += 64) yb[65 + k] = y[(int64_t)k * dy];
-  side_pad(lx, ly, steps, ge, oe, xb, yb, strip);
+  side_pad(lx, ly, steps, go, xb, yb, strip);
   int best = 0, bpos = 0;  // bpos = (strip << 16) | (block start + 1); 0: cell (0, 0)
-  side_dp<false>(lx, ly, steps, ge, oe, T, prof, xb, yb, strip, tb, best, bpos);
+  side_dp<false>(lx, ly, steps, ge, go, T, prof, xb, yb, strip, tb, best, bpos);
 
   // best over the wavefront: largest value, then first row, then first block
   // (a row belongs to one lane, so the block decides only within a row)
@@ -472,9 +483,9 @@ __device__ __forceinline__ SideStats align_side(const AlignArgs& A, const uint8_
     const int r_end = (st.i_end - 1) & 63, t8 = (bpos & 0xffff) - 64;
     const int j_hi = min(ly, t8 + 7 - r_end);
     const int steps2 = (j_hi + 64 + 7) & ~7;
-    side_pad(st.i_end, j_hi, steps2, ge, oe, xb, yb, strip);
+    side_pad(st.i_end, j_hi, steps2, go, xb, yb, strip);
     int unused0 = 0, unused1 = 0, jf = -1;
-    side_dp<true>(st.i_end, j_hi, steps2, ge, oe, T, prof, xb, yb, strip, tb, unused0, unused1, st.i_end, best,
+    side_dp<true>(st.i_end, j_hi, steps2, ge, go, T, prof, xb, yb, strip, tb, unused0, unused1, st.i_end, best,
                   &jf);
     nu8 = steps2 >> 3;
     st.j_end = __shfl(jf, r_end);
@@ -579,10 +590,10 @@ __global__ __launch_bounds__(64) void k_align(AlignArgs A, const plast_hit_t* hi
   int2* strip = (int2*)(yb + ((A.max_len2 + 136 + 15) & ~15));
   uint32_t* walk = (uint32_t*)strip;  // the trace-back runs after the DP of its side
   const int lane = threadIdx.x;
-  const int oe = A.gap_open + A.gap_extend;
+  const int t_add = A.gap_open + 2 * A.gap_extend;  // the diagonal term in shifted values
   for (int k = lane; k < 21 * kTStride; k += 64) {
     const int xa = k / kTStride, yc = k % kTStride;
-    T[k] = (int16_t)((xa < 20 && yc < 20) ? (int)A.mat[xa * 20 + yc] + oe : kWall);
+    T[k] = (int16_t)((xa < 20 && yc < 20) ? (int)A.mat[xa * 20 + yc] + t_add : kWall);
   }
   __syncthreads();
 
