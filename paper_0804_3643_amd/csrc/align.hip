@@ -17,13 +17,16 @@
 // strips of 64 rows (one row per lane) across the columns as a skewed front:
 // at step t lane r holds column t - r; H (less the gap-opening cost) and F move
 // one lane down per step through a wavefront DPP shift, and the strip's last
-// row waits in LDS for the next strip.  Each cell leaves a 4-bit trace (source of H; whether E and F
-// opened) in a per-wavefront buffer; the trace-back then reads it through an
-// LDS window of 64 rows x 64 steps.
+// row waits in LDS for the next strip.  A score pass over the whole matrix
+// finds the best and its end cell; a trace pass over the rectangle up to the
+// end cell stores a 4-bit trace per cell (source of H; whether E and F opened)
+// in a per-wavefront buffer; the trace-back reads it through an LDS window of
+// 64 rows x 64 steps.
 //
-// Layout of the trace of a side: strip s, lane r and step u = j + r hold the
-// nibble (u & 7) of dword ((s * nu8 + (u >> 3)) * 64 + r), nu8 = (ly + 71) / 8,
-// so every eighth step the wavefront stores one coalesced 256-byte row.
+// Layout of the trace: strip s, lane r and step u = j + r hold the nibble
+// (u & 7) of dword ((s * nu8 + (u >> 3)) * 64 + r), nu8 = (ly + 71) / 8 for the
+// trace pass's ly, so every eighth step the wavefront stores one coalesced
+// 256-byte row.
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
