@@ -45,6 +45,10 @@ METRIC = "ungapped extensions/sec and bank-vs-bank wall time (plain vs batched, 
 OPS_PER_EXT = 88           # 44 scan steps x (1 add + 1 max), int16
 # MI355X: 256 CUs x 64 VALU lanes x 2 int16 ops per packed instruction x 2.4 GHz
 PEAK_INT16_TOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+# Stage 3.2: 7 int32 operations per DP cell (E: subtract, max; F: subtract, max;
+# diagonal add; two maxima for H) against 256 CUs x 64 VALU lanes x 2.4 GHz
+ALIGN_OPS_PER_CELL = 7
+PEAK_INT32_TOPS = 256 * 64 * 2.4e9 / 1e12
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ungapped_persistent_cfg1_traffic.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_0804_3643_amd", "csrc", "ungapped.hip")
 
@@ -150,12 +154,15 @@ def run_stage32(B, torch, np, w, ia, ib, hits, gs, ps, reps, cpu):
     al = B.Aligner(ia, ib, n)
     al.run(hits, gs, ps)
     torch.cuda.synchronize()
-    walls = []
+    walls, kernel_ms = [], []
+    B.timing_enable(True)
     for _ in range(reps):
         t1 = time.perf_counter()
         rec, cov = al.run(hits, gs, ps)
         torch.cuda.synchronize()
         walls.append(time.perf_counter() - t1)
+        kernel_ms.append(B.timing_read()["align_ms"])
+    B.timing_enable(False)
     F = {k: i for i, k in enumerate(B.ALIGN_FIELDS)}
     r = rec.cpu().numpy().astype(np.int64)
     la = np.diff(w.bank1.seq_start) - B.PAD_LEN
@@ -164,8 +171,13 @@ def run_stage32(B, torch, np, w, ia, ib, hits, gs, ps, reps, cpu):
     cells = int(((la[s1] - p1) * (lb[s2] - p2) + p1 * p2).sum())
     n_pass = int(ps.sum().item())
     ms = 1e3 * float(np.min(walls))
+    kms = float(np.mean(kernel_ms))
+    achieved = cells * ALIGN_OPS_PER_CELL / (kms * 1e-3) / 1e12
     out = {"passing_hits": n_pass, "alignments": len(r), "covered_hits": n_pass - len(r), "call_ms": ms,
-           "dp_cells": cells, "dp_cells_per_s": cells / (ms * 1e-3),
+           "kernel_ms": kms, "dp_cells": cells, "dp_cells_per_s": cells / (ms * 1e-3),
+           "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_INT32_TOPS, "unit": "TOP/s",
+                        "frac": achieved / PEAK_INT32_TOPS, "traffic": None, "kernel": "k_align",
+                        "ops_per_cell": ALIGN_OPS_PER_CELL},
            "mean_score": float(r[:, F["score"]].mean()) if len(r) else 0.0,
            "call": "plast_align: key pass, radix sort by (seq1, seq2, -gscore, pos1, pos2), alignment kernel; "
                    "wall time of the synchronous call, best of %d" % reps}

@@ -207,6 +207,7 @@ typedef struct {
                                   (all per-key grids in PLAST_PLAIN mode) */
   float gapped_ms;             /* last plast_gapped_filter: its kernel */
   int64_t ungapped_launches;   /* extension-kernel launches of the last extension call */
+  float align_ms;              /* last plast_align: its alignment kernel (not the grouping before it) */
 } plast_timing_t;
 
 int plast_timing_enable(int on);

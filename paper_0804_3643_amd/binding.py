@@ -51,7 +51,7 @@ class IndexView(ctypes.Structure):
 
 class Timing(ctypes.Structure):
     _fields_ = [("index_ms", ctypes.c_float), ("plan_ms", ctypes.c_float), ("ungapped_ms", ctypes.c_float),
-                ("gapped_ms", ctypes.c_float), ("ungapped_launches", ctypes.c_int64)]
+                ("gapped_ms", ctypes.c_float), ("ungapped_launches", ctypes.c_int64), ("align_ms", ctypes.c_float)]
 
 
 class Tuning(ctypes.Structure):
@@ -473,7 +473,7 @@ def timing_read():
     t = Timing()
     _check(load().plast_timing_read(ctypes.byref(t)), "plast_timing_read")
     return {"index_ms": t.index_ms, "plan_ms": t.plan_ms, "ungapped_ms": t.ungapped_ms, "gapped_ms": t.gapped_ms,
-            "ungapped_launches": int(t.ungapped_launches)}
+            "ungapped_launches": int(t.ungapped_launches), "align_ms": t.align_ms}
 
 
 class Searcher:

@@ -774,8 +774,10 @@ int align_impl(const plast_index_t* a, const plast_index_t* b, const plast_hit_t
     hipLaunchKernelGGL(k_align_heads, dim3(mb), dim3(256), 0, s, perm[cur], khi, hdr, (const int32_t*)pcount, heads);
     const size_t lds = align_lds_bytes(p->max_len1, p->max_len2);
     PLAST_HIP(hipFuncSetAttribute((const void*)k_align, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    timing_mark(kStageAlign, false, s);
     hipLaunchKernelGGL(k_align, dim3((unsigned)waves), dim3(64), lds, s, A, d_hits, hidx, perm[cur], khi, heads, hdr,
                        tb, L.tb_words_per_wave, pieces, d_out, d_cover);
+    timing_mark(kStageAlign, true, s);
     PLAST_HIP(hipGetLastError());
     PLAST_HIP(hipMemcpyAsync(&h0, hdr, sizeof(h0), hipMemcpyDeviceToHost, s));
     PLAST_HIP(hipStreamSynchronize(s));

@@ -133,7 +133,7 @@ int plast_timing_enable(int on) {
 int plast_timing_read(plast_timing_t* out) {
   g_last_error[0] = 0;
   if (!out) return set_error(PLAST_E_ARG, "null output pointer");
-  float ms[kNumStages] = {0.f, 0.f, 0.f, 0.f};
+  float ms[kNumStages] = {};
   for (int i = 0; i < kNumStages; ++i) {
     if (!g_ev_made || !g_ev_used[i]) continue;
     PLAST_HIP(hipEventSynchronize(g_ev[i][1]));
@@ -144,6 +144,7 @@ int plast_timing_read(plast_timing_t* out) {
   out->ungapped_ms = ms[kStageUngapped];
   out->gapped_ms = ms[kStageGapped];
   out->ungapped_launches = g_launches;
+  out->align_ms = ms[kStageAlign];
   return PLAST_OK;
 }
 

@@ -56,7 +56,14 @@ int hip_check(hipError_t e, const char* what);
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // ---------------------------------------------------------------- timing
-enum TimedStage { kStageIndex = 0, kStagePlan = 1, kStageUngapped = 2, kStageGapped = 3, kNumStages = 4 };
+enum TimedStage {
+  kStageIndex = 0,
+  kStagePlan = 1,
+  kStageUngapped = 2,
+  kStageGapped = 3,
+  kStageAlign = 4,
+  kNumStages = 5
+};
 bool timing_on();
 // Record the start / stop event of a stage on `s` (no-ops while timing is off).
 void timing_mark(TimedStage st, bool stop, hipStream_t s);

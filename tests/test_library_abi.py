@@ -224,8 +224,9 @@ def test_align_layout_and_validation_without_gpu(tmp_path):
 #include <stddef.h>
 #include "plast.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu\\n", sizeof(plast_alignment_t), offsetof(plast_alignment_t, score),
-         offsetof(plast_alignment_t, hit), sizeof(plast_align_params_t), offsetof(plast_align_params_t, matrix));
+  printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(plast_alignment_t), offsetof(plast_alignment_t, score),
+         offsetof(plast_alignment_t, hit), sizeof(plast_align_params_t), offsetof(plast_align_params_t, matrix),
+         sizeof(plast_timing_t), offsetof(plast_timing_t, align_ms));
   return 0;
 }
 """)
@@ -235,7 +236,7 @@ int main(void) {
     AP = binding.AlignParams
     nf = len(binding.ALIGN_FIELDS)
     assert got == [4 * nf, 4 * binding.ALIGN_FIELDS.index("score"), 4 * binding.ALIGN_FIELDS.index("hit"),
-                   ctypes.sizeof(AP), AP.matrix.offset]
+                   ctypes.sizeof(AP), AP.matrix.offset, ctypes.sizeof(binding.Timing), binding.Timing.align_ms.offset]
 
     lib = binding.load()
     sz = ctypes.c_size_t(0)
