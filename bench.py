@@ -28,7 +28,7 @@ reported:
     seeded sample of keys of the same workload, scaled to the whole job, and
     its hits compared with the GPU's for those keys.
 
-Usage: python bench.py [--steps K] [--warmup W] [--config 1]
+Usage: python bench.py [--steps K] [--warmup W] [--config 1|2|3] [--serving] [--plastx]
 """
 import argparse
 import hashlib
@@ -294,10 +294,12 @@ def run_serving(args):
     print(json.dumps(out), flush=True)
 
 
-def run_tplastn(args):
-    """Configuration 3 (TPLAST-N): 5000 proteins against 2000 DNA sequences of
-    50-200 kb translated on the device in six frames; one step = translation +
-    index of both banks + batched extension + gapped filter."""
+def run_translated(args, plastx=False):
+    """TPLAST-N (configuration 3: 5000 proteins against 2000 DNA sequences of
+    50-200 kb) or PLAST-X (200 against 1000 DNA sequences of 20-50 kb, both
+    translated): the DNA banks are translated on the device in six frames every
+    step; one step = translation + index of both banks + batched extension +
+    gapped filter."""
     import numpy as np
     import torch
 
@@ -307,15 +309,24 @@ def run_tplastn(args):
     from paper_0804_3643_amd import params, synth
 
     B.load()
-    log("generating configuration 3")
-    w = synth.make_tplastn()
     dev = torch.device("cuda:0")
-    pa, sa = B.bank_to_device(w.bank1, dev)
-    dna, dstart = B.dna_to_device(w.dna, dev)
-    tr = B.Translator(dna, dstart)
-    codes, starts, frag = tr.run()
-    ia = B.build_index(pa, sa)
-    ib = B.build_index(codes, starts)
+    if plastx:
+        log("generating the PLAST-X workload")
+        w = synth.make_plastx()
+        dnas = [w.dna1, w.dna2]
+    else:
+        log("generating configuration 3")
+        w = synth.make_tplastn()
+        dnas = [w.dna]
+    trs = [B.Translator(*B.dna_to_device(d, dev)) for d in dnas]
+    outs = [t.run() for t in trs]
+    if plastx:
+        (ca, sa, fa), (cb, sb, fb) = outs
+    else:
+        ca, sa = B.bank_to_device(w.bank1, dev)
+        cb, sb, fb = outs[0]
+    ia = B.build_index(ca, sa)
+    ib = B.build_index(cb, sb)
     tuning = None
     if not args.no_autotune:
         log("autotuning launch shapes")
@@ -325,23 +336,28 @@ def run_tplastn(args):
     cap = ext.hits.shape[0]
     gbuf = torch.empty(cap, dtype=torch.int32, device=dev)
     pbuf = torch.empty(cap, dtype=torch.uint8, device=dev)
-    iba, wba = B.index_bytes(pa.numel(), sa.numel() - 1)
-    ibb, wbb = B.index_bytes(codes.numel(), starts.numel() - 1)
+    iba, wba = B.index_bytes(ca.numel(), sa.numel() - 1)
+    ibb, wbb = B.index_bytes(cb.numel(), sb.numel() - 1)
     buf_a, buf_b, ws_idx = B._alloc(iba, dev), B._alloc(ibb, dev), B._alloc(max(wba, wbb), dev)
 
     def step():
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
         ev[0].record()
-        c, st, _ = tr.run()
+        res = [t.run() for t in trs]
+        if plastx:
+            (xca, xsa, _), (xcb, xsb, _) = res
+        else:
+            xca, xsa = ca, sa
+            xcb, xsb, _ = res[0]
         ev[1].record()
-        xa = B.build_index(pa, sa, workspace=ws_idx, out_buf=buf_a)
-        xb = B.build_index(c, st, workspace=ws_idx, out_buf=buf_b)
+        xa = B.build_index(xca, xsa, workspace=ws_idx, out_buf=buf_a)
+        xb = B.build_index(xcb, xsb, workspace=ws_idx, out_buf=buf_b)
         ev[2].record()
         h, ne = ext.run(xa, xb)
         ev[3].record()
         B.gapped_filter(xa, xb, h, params.S2, out=(gbuf, pbuf), tuning=tuning)
         ev[4].record()
-        return h, ne, ev
+        return h, ne, ev, res
 
     for _ in range(args.warmup):
         step()
@@ -350,7 +366,7 @@ def run_tplastn(args):
     t0 = time.perf_counter()
     stage = []
     for _ in range(args.steps):
-        h, ne, ev = step()
+        h, ne, ev, res = step()
         torch.cuda.synchronize()
         stage.append([ev[k].elapsed_time(ev[k + 1]) for k in range(4)])
     ms = (time.perf_counter() - t0) * 1e3 / args.steps
@@ -359,39 +375,46 @@ def run_tplastn(args):
     n_pass = int(pbuf[:n_hits].sum().item())
     # bit-exact checks: translation of sampled DNA sequences, and hits of sampled keys, against the oracle
     log("checks against the oracle")
-    fr = frag.cpu().numpy()
     rng = np.random.default_rng(3)
     tr_equal = True
-    st_h = starts.cpu().numpy()
-    codes_h = codes.cpu().numpy()
-    for d in rng.choice(w.dna.n_seqs, size=4, replace=False):
-        frags, table = O.translate6(w.dna.seq(int(d)), np.array([0, int(w.dna.start[d + 1] - w.dna.start[d])]))
-        sel = np.nonzero(fr[:, 0] == d)[0]
-        got = [codes_h[st_h[j]:st_h[j + 1] - B.PAD_LEN] for j in sel]
-        tr_equal &= len(got) == len(frags) and all(np.array_equal(a, b) for a, b in zip(got, frags))
-        tr_equal &= bool(np.array_equal(fr[sel, 1:], table[:, 1:]))
-    frag_bank = synth.Bank(codes_h, st_h)
-    i1, i2 = C.build_index(w.bank1), C.build_index(frag_bank)
+    frag_banks, frag_tables = [], []
+    for d_bank, (c_t, s_t, f_t) in zip(dnas, res):
+        fr = f_t.cpu().numpy()
+        st_h = s_t.cpu().numpy()
+        codes_h = c_t.cpu().numpy()
+        for d in rng.choice(d_bank.n_seqs, size=min(4, d_bank.n_seqs), replace=False):
+            frags, table = O.translate6(d_bank.seq(int(d)), np.array([0, int(d_bank.start[d + 1] - d_bank.start[d])]))
+            sel = np.nonzero(fr[:, 0] == d)[0]
+            got = [codes_h[st_h[j]:st_h[j + 1] - B.PAD_LEN] for j in sel]
+            tr_equal &= len(got) == len(frags) and all(np.array_equal(a, b) for a, b in zip(got, frags))
+            tr_equal &= bool(np.array_equal(fr[sel, 1:], table[:, 1:]))
+        frag_banks.append(synth.Bank(codes_h, st_h))
+        frag_tables.append(fr)
+    bank_a = frag_banks[0] if plastx else w.bank1
+    bank_b = frag_banks[-1]
+    i1, i2 = C.build_index(bank_a), C.build_index(bank_b)
     work = np.diff(i1[0]) * np.diff(i2[0])
     keys = np.sort(rng.choice(np.nonzero(work)[0], size=24, replace=False)).astype(np.int32)
-    ref, _ = C.ungapped_hits(w.bank1, frag_bank, params.S1, keys=keys, idx1=i1, idx2=i2)
+    ref, _ = C.ungapped_hits(bank_a, bank_b, params.S1, keys=keys, idx1=i1, idx2=i2)
     hh = h.cpu().numpy().astype(np.int64)
-    c1 = w.bank1.codes
-    q = w.bank1.seq_start[hh[:, 0]] + hh[:, 1]
+    c1 = bank_a.codes
+    q = bank_a.seq_start[hh[:, 0]] + hh[:, 1]
     hk = O.seed_key(c1[q].astype(np.int64), c1[q + 1].astype(np.int64), c1[q + 2].astype(np.int64),
                     c1[q + 3].astype(np.int64))
     hits_equal = bool(np.array_equal(O.canonical(hh[np.isin(hk, keys)]), ref))
+    name = "PLAST-X" if plastx else "TPLAST-N"
     out = {
-        "metric": "TPLAST-N: ungapped extensions/s, whole step including the six-frame translation",
+        "metric": "%s: ungapped extensions/s, whole step including the six-frame translation%s"
+                  % (name, " of both banks" if plastx else ""),
         "value": n_ext / (ms * 1e-3), "unit": "ext/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms, "higher_is_better": True, "dtype": "f16", "data": "synthetic",
         "stages_device_ms": {"translate": stage[0], "index": stage[1], "ungapped": stage[2], "gapped": stage[3]},
         "n_ext": n_ext, "n_hits": n_hits, "n_gapped_pass": n_pass,
-        "n_fragments": int(fr.shape[0]), "fragment_residues": int(codes.numel() - B.PAD_LEN * (fr.shape[0] + 1)),
+        "n_fragments": [int(f.shape[0]) for f in frag_tables],
         "tuning": tuning.as_dict() if tuning is not None else None,
-        "bit_exact": {"translation_equals_oracle_on_4_sampled_dna": bool(tr_equal),
+        "bit_exact": {"translation_equals_oracle_on_sampled_dna": bool(tr_equal),
                       "hits_equal_oracle_on_24_sampled_keys": hits_equal},
-        "config": {"workload": w.description, "dna_nt": int(w.dna.codes.shape[0])},
+        "config": {"workload": w.description, "dna_nt": [int(d.codes.shape[0]) for d in dnas]},
     }
     print(json.dumps(out, default=float), flush=True)
 
@@ -418,6 +441,8 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=1000)
     ap.add_argument("--serving-scale", type=float, default=1.0, help="resident bank size factor (1 = 1M proteins)")
     ap.add_argument("--serving-slots", type=int, default=3)
+    ap.add_argument("--plastx", action="store_true",
+                    help="PLAST-X: both banks nucleotide, translated on the device in six frames")
     ap.add_argument("--no-stage32", dest="stage32", action="store_false",
                     help="skip stage 3.2 (full gapped alignment of the passing hits, reported apart from the step)")
     args = ap.parse_args()
@@ -438,8 +463,8 @@ def main():
     if args.serving:
         run_serving(args)
         return
-    if args.config == 3:
-        run_tplastn(args)
+    if args.config == 3 or args.plastx:
+        run_translated(args, plastx=args.plastx)
         return
     B.load()
     log("generating configuration %d" % args.config)
