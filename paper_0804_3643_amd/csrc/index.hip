@@ -1,36 +1,26 @@
 // Stage 0, bank indexing (Sec. 3.3.1): subset-seed key of every word, then a
-// stable counting sort by key into CSR form (key_off, occ, occ_seq).
+// stable sort by key into CSR form (key_off, occ, occ_seq).
 //
-// Layout: the bank is cut into contiguous position chunks (about 16K
-// positions, at most 16384 chunks), one wavefront each.
-// Pass 1 counts keys per chunk in LDS (8800 counters) and writes them key-major,
-// an exclusive scan over (key, chunk) gives every chunk its first slot in each
-// key's run, and pass 2 re-reads the chunk and scatters positions in order.
-// Inside a wavefront, equal keys are ranked with 14 ballots (one per key bit),
-// so the order inside a key is the position order: ascending (sequence,
-// position), independent of scheduling.  HBM traffic is ~2 reads of the codes
-// plus 8 bytes written per word.
+// The sort is a two-pass LSD radix sort on the 14-bit key: the low 7 bits
+// (128 buckets), then the high 7 bits (69 buckets).  Each pass cuts its input
+// into tiles of kIxTile elements, one wavefront each: a counting kernel writes
+// the tile's bucket histogram bucket-major, an exclusive scan over (bucket,
+// tile) gives every tile its first slot in each bucket, and a scattering
+// kernel walks the tile in order, ranking equal buckets among the 64 lanes of
+// a round with one ballot per digit bit.  Both passes are stable, so the order
+// inside a key is the position order: ascending (sequence, position),
+// independent of scheduling.  A tile's writes to one bucket are consecutive
+// slots, so they fill whole cache lines while the tile runs (a one-pass
+// counting sort over 8800 keys wrote one 4-byte entry per line).  Pass 1 reads
+// the codes and writes (position, sequence, key) of every word; pass 2 writes
+// occ, occ_seq and the sorted keys, from which key_off is read off.
 #include "plast_internal.h"
 
 namespace plast {
 
 namespace {
 
-constexpr int kChunkWave = 64;
-
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
-
-__device__ __forceinline__ uint64_t peers_of(int key, bool valid) {
-  // Lanes of the wavefront holding a valid word with the same key.
-  uint64_t peers = __ballot(valid);
-#pragma unroll
-  for (int b = 0; b < 14; ++b) {
-    int bit = (key >> b) & 1;
-    uint64_t m = __ballot(bit);
-    peers &= bit ? m : ~m;
-  }
-  return peers;
-}
 
 __device__ __forceinline__ int word_key(const uint8_t* __restrict__ codes, int64_t q, int64_t end,
                                         const SeedClasses& sc) {
@@ -40,54 +30,114 @@ __device__ __forceinline__ int word_key(const uint8_t* __restrict__ codes, int64
   return seed_key_dev(sc, w0, w1, w2, w3);
 }
 
+constexpr int kIxTile = 2048;                       // elements per tile (32 rounds of 64)
+constexpr int kIxWaves = 4;                         // tiles (one per wavefront) per workgroup
+constexpr int kD0Bits = 7;                          // pass-1 digit: key & 127
+constexpr int kD0 = 1 << kD0Bits;
+constexpr int kD1 = (kNKeys + kD0 - 1) >> kD0Bits;  // pass-2 digit: key >> 7, 69 values
+static_assert(kD1 <= 128, "pass-2 digits must fit 7 bits");
+
+// Keeps the compiler from moving LDS accesses across a step of a wavefront's
+// read-then-update of its own LDS table.  The lanes of a wavefront issue LDS
+// instructions together and the LDS serves one wavefront's instructions in
+// order, so no hardware barrier is needed.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Layout check, and the tile table: tile_seq[t] is the sequence holding
+// position t * kIxTile (sequence 0 for the leading separators).  A sequence
+// writes its tiles only when its own starts are consistent; the table is read
+// only when no thread flagged the layout, and then every tile is written.
 __global__ void k_layout_check(const int64_t* __restrict__ seq_start, int32_t n_seqs, int64_t n_padded,
-                               int32_t* __restrict__ err) {
+                               int32_t* __restrict__ tile_seq, int64_t tiles, int32_t* __restrict__ err) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i > n_seqs) return;
   int64_t s = seq_start[i];
   bool bad = s < kPadLen || s > n_padded;
   if (i == 0 && s != kPadLen) bad = true;
   if (i == n_seqs && s != n_padded) bad = true;
-  if (i < n_seqs && seq_start[i + 1] - s < kPadLen) bad = true;
+  if (i < n_seqs) {
+    const int64_t nx = seq_start[i + 1];
+    if (nx - s < kPadLen) bad = true;
+    if (!bad) {
+      const int64_t lo = i == 0 ? 0 : s;
+      for (int64_t t = (lo + kIxTile - 1) / kIxTile; t < tiles && t * kIxTile < nx; ++t) tile_seq[t] = (int32_t)i;
+    }
+  }
   if (bad) atomicOr(err, 1);
+}
+
+// Loads starts s0 + 1 .. s0 + 64 * K of the sequences (INT64_MAX past the
+// last) into a wavefront's LDS table, one coalesced load per 64.
+template <int K>
+__device__ __forceinline__ void load_starts(const int64_t* __restrict__ seq_start, int32_t n_seqs, int s0,
+                                            int64_t* st, int lane) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int64_t idx = (int64_t)s0 + 1 + k * 64 + lane;
+    st[k * 64 + lane] = idx < n_seqs ? seq_start[idx] : INT64_MAX;
+  }
+}
+
+// The sequence holding position q, for a window of 64 consecutive positions
+// whose first one lies in sequence s_cur (or before the first one, -1).  Every
+// sequence takes at least kPadLen positions (its separator run), so a window
+// meets at most 4 sequence starts: lanes 0..7 read the next 8 from the table
+// (st[k] is start s0 + 1 + k) and every lane counts those at or before q.
+template <int K>
+__device__ __forceinline__ int seq_of(const int64_t* st, int s_cur, int s0, int64_t q, int lane) {
+  const int j = min(s_cur - s0 + lane, 64 * K - 1);
+  const int64_t nxt = lane < 8 ? st[j] : INT64_MAX;
+  int s = s_cur;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) s += q >= __shfl(nxt, k) ? 1 : 0;
+  return s;
 }
 
 // Validation and scan codes, position-parallel (so that banks of many short
 // sequences, such as translated fragments, keep every lane busy).  Each
-// wavefront takes kCheckChunk consecutive positions of [0, scan_len): it finds
-// the sequence holding its first position by binary search, then walks its
-// positions in order.  Position p is a residue iff some sequence s has
-// seq_start[s] <= p < seq_start[s + 1] - kPadLen; every other position below
-// n_padded must hold the separator code, and the tail slack is set to it.
-constexpr int64_t kCheckChunk = 4096;
+// wavefront takes kCheckChunk consecutive positions of [0, scan_len), two
+// tiles: it takes the sequence holding its first position from the tile table
+// and then walks its positions in order.  Position p is a residue iff some
+// sequence s has seq_start[s] <= p < seq_start[s + 1] - kPadLen; every other
+// position below n_padded must hold the separator code, and the tail slack is
+// set to it.
+constexpr int64_t kCheckChunk = 2 * kIxTile;
+constexpr int kCheckStarts = 4;  // 256 starts: a chunk holds at most 205
 
-__global__ __launch_bounds__(kChunkWave) void k_codes_check(const uint8_t* __restrict__ codes,
-                                                            const int64_t* __restrict__ seq_start, int32_t n_seqs,
-                                                            int64_t n_padded, uint8_t* __restrict__ scan,
-                                                            int64_t scan_len, int32_t* __restrict__ err) {
-  if (*err & 1) return;  // no walk over a bad layout
+__global__ __launch_bounds__(64 * kIxWaves) void k_codes_check(const uint8_t* __restrict__ codes,
+                                                              const int64_t* __restrict__ seq_start, int32_t n_seqs,
+                                                              int64_t n_padded, const int32_t* __restrict__ tile_seq,
+                                                              int64_t tiles, uint8_t* __restrict__ scan,
+                                                              int64_t scan_len, int32_t* __restrict__ err) {
+  __shared__ int64_t st_all[kIxWaves][64 * kCheckStarts];
   const int lane = lane_id();
-  const int64_t beg = (int64_t)blockIdx.x * kCheckChunk;
+  const int64_t chunk = (int64_t)blockIdx.x * kIxWaves + (threadIdx.x >> 6);
+  const int64_t beg = chunk * kCheckChunk;
+  if (beg >= scan_len || (*err & 1)) return;  // no walk over a bad layout
   const int64_t end = min(beg + kCheckChunk, scan_len);
-  // s_cur: the last sequence with seq_start <= beg (-1 before the first one)
-  int lo = -1, hi = n_seqs - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (seq_start[mid] <= beg) lo = mid; else hi = mid - 1;
+  int64_t* st = st_all[threadIdx.x >> 6];
+  // s0: the last sequence with seq_start <= beg (-1 before the first one)
+  int s0 = n_seqs - 1;
+  if (beg < n_padded && n_seqs > 0) {
+    s0 = min(max(tile_seq[beg / kIxTile], 0), n_seqs - 1);
+    if (seq_start[s0] > beg) s0 = -1;
   }
-  int s_cur = lo;
+  load_starts<kCheckStarts>(seq_start, n_seqs, s0, st, lane);
+  wave_sync();
+  int s_cur = s0;
   bool bad = false;
   for (int64_t base = beg; base < end; base += 64) {
     const int64_t p = base + lane;
-    // at most 4 sequence starts in a window (each sequence takes >= kPadLen
-    // positions): lanes 0..7 load the next 8 and every lane counts its own
-    const int64_t nxt = (lane < 8 && s_cur + 1 + lane < n_seqs) ? seq_start[s_cur + 1 + lane] : INT64_MAX;
-    int s = s_cur;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) s += p >= __shfl(nxt, j) ? 1 : 0;
+    const int s = seq_of<kCheckStarts>(st, s_cur, s0, p, lane);
     if (p < end) {
       if (p < n_padded) {
-        const bool residue = s >= 0 && p < seq_start[s + 1] - kPadLen;
+        // end of sequence s from the table (seq_start[n_seqs] == n_padded)
+        const int64_t nx = s + 1 < n_seqs ? st[min(s - s0, 64 * kCheckStarts - 1)] : n_padded;
+        const bool residue = s >= 0 && p < nx - kPadLen;
         const uint8_t c = codes[p];
         bad |= residue ? (c >= 20) : (c != kPadCode);
         scan[p] = (uint8_t)((residue && c < 20 ? c : kPadCode) * kScale);
@@ -100,69 +150,234 @@ __global__ __launch_bounds__(kChunkWave) void k_codes_check(const uint8_t* __res
   if (bad) atomicOr(err, 2);
 }
 
-__global__ __launch_bounds__(kChunkWave) void k_index_count(const uint8_t* __restrict__ codes, int64_t n_padded,
-                                                            int64_t chunk, int32_t nchunks, SeedClasses sc,
-                                                            int32_t* __restrict__ counts) {
-  __shared__ int32_t cnt[kNKeys];
-  const int lane = lane_id();
-  for (int k = lane; k < kNKeys; k += 64) cnt[k] = 0;
-  __syncthreads();
-  const int64_t beg = (int64_t)blockIdx.x * chunk;
-  const int64_t end = min(beg + chunk, n_padded - (kSeed - 1));
-  // the next window's letters are loaded one window ahead
-  int key_next = beg < end ? word_key(codes, beg + lane, end, sc) : -1;
-  for (int64_t base = beg; base < end; base += 64) {
-    const int key = key_next;
-    key_next = word_key(codes, base + 64 + lane, end, sc);
-    uint64_t peers = peers_of(key, key >= 0);
-    if (key >= 0 && lane == 63 - __clzll(peers)) cnt[key] += __popcll(peers);
+// Lanes of the wavefront holding a valid element with the same 7-bit digit.
+__device__ __forceinline__ uint64_t digit_peers(int d, bool valid) {
+  uint64_t peers = __ballot(valid);
+#pragma unroll
+  for (int b = 0; b < 7; ++b) {
+    const int bit = (d >> b) & 1;
+    const uint64_t m = __ballot(bit);
+    peers &= bit ? m : ~m;
   }
-  __syncthreads();
-  for (int k = lane; k < kNKeys; k += 64) counts[(int64_t)k * nchunks + blockIdx.x] = cnt[k];
+  return peers;
 }
 
-__global__ __launch_bounds__(kChunkWave) void k_index_scatter(const uint8_t* __restrict__ codes,
-                                                              const int64_t* __restrict__ seq_start,
-                                                              int32_t n_seqs, int64_t n_padded, int64_t chunk,
-                                                              int32_t nchunks, SeedClasses sc,
-                                                              const int32_t* __restrict__ offs,
-                                                              int32_t* __restrict__ occ,
-                                                              int32_t* __restrict__ occ_seq) {
-  __shared__ int32_t cur[kNKeys];
+// Pass 1, counting: histogram of the low digit of the words starting in the
+// tile's positions.
+__global__ __launch_bounds__(64 * kIxWaves) void k_ix_count1(const uint8_t* __restrict__ codes, int64_t n_padded,
+                                                            int64_t tiles, SeedClasses sc,
+                                                            int32_t* __restrict__ hist) {
+  __shared__ int32_t cnt_all[kIxWaves][kD0];
   const int lane = lane_id();
-  for (int k = lane; k < kNKeys; k += 64) cur[k] = offs[(int64_t)k * nchunks + blockIdx.x];
-  __syncthreads();
-  if (n_seqs == 0) return;
-  const int64_t beg = (int64_t)blockIdx.x * chunk;
-  const int64_t end = min(beg + chunk, n_padded - (kSeed - 1));
-  // sequence holding position beg: largest s with seq_start[s] <= beg (0 if none)
-  int lo = 0, hi = n_seqs - 1;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (seq_start[mid] <= beg) lo = mid; else hi = mid - 1;
+  const int64_t tile = (int64_t)blockIdx.x * kIxWaves + (threadIdx.x >> 6);
+  if (tile >= tiles) return;
+  int32_t* cnt = cnt_all[threadIdx.x >> 6];
+  cnt[lane] = 0;
+  cnt[lane + 64] = 0;
+  wave_sync();
+  const int64_t beg = tile * kIxTile;
+  const int64_t end = min(beg + kIxTile, n_padded - (kSeed - 1));
+  for (int64_t q = beg + lane; q < end; q += 64) {
+    const int key = word_key(codes, q, end, sc);
+    if (key >= 0) atomicAdd(&cnt[key & (kD0 - 1)], 1);
   }
-  int s_cur = lo;
-  int key_next = beg < end ? word_key(codes, beg + lane, end, sc) : -1;  // one window ahead
-  for (int64_t base = beg; base < end; base += 64) {
-    int64_t q = base + lane;
-    const int key = key_next;
-    key_next = word_key(codes, q + 64, end, sc);
-    // Every sequence takes at least kPadLen positions (its separator run), so
-    // a 64-position window meets at most 5 sequence starts: lanes 0..7 load the
-    // next 8 starts at once and every lane counts those at or before q.
-    const int64_t nxt = (lane < 8 && s_cur + 1 + lane < n_seqs) ? seq_start[s_cur + 1 + lane] : INT64_MAX;
-    int s = s_cur;
+  wave_sync();
+  hist[(int64_t)lane * tiles + tile] = cnt[lane];
+  hist[(int64_t)(lane + 64) * tiles + tile] = cnt[lane + 64];
+}
+
+// A tile's bucket tables from the scanned histogram (bucket-major over
+// tiles, n_total words in all): gst[d] is the tile's first slot in bucket d,
+// lst[d] the first slot of bucket d in the tile's own bucket order, cur[d] a
+// running copy of lst[d].  Returns the tile's word count.
+template <int ND>
+__device__ __forceinline__ int tile_tables(const int32_t* __restrict__ offs, int64_t tiles, int64_t tile,
+                                           int64_t n_total, int32_t* gst, int32_t* lst, int32_t* cur, int lane) {
+  int c[2], g[2], incl[2], tot[2];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) s += q >= __shfl(nxt, j) ? 1 : 0;
-    uint64_t peers = peers_of(key, key >= 0);
-    if (key >= 0) {
-      int rank = __popcll(peers & ((1ull << lane) - 1ull));
-      int slot = cur[key] + rank;
-      occ[slot] = (int32_t)q;
-      occ_seq[slot] = s;
+  for (int h = 0; h < 2; ++h) {
+    const int d = lane + 64 * h;
+    g[h] = 0;
+    c[h] = 0;
+    if (d < ND) {
+      const int64_t idx = (int64_t)d * tiles + tile;
+      g[h] = offs[idx];
+      c[h] = (int)((idx + 1 < (int64_t)ND * tiles ? (int64_t)offs[idx + 1] : n_total) - g[h]);
     }
-    if (key >= 0 && lane == 63 - __clzll(peers)) cur[key] += __popcll(peers);
+    incl[h] = c[h];
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int t = __shfl_up(incl[h], o);
+      if (lane >= o) incl[h] += t;
+    }
+    tot[h] = __shfl(incl[h], 63);
+  }
+  const int l0 = incl[0] - c[0], l1 = tot[0] + incl[1] - c[1];
+  gst[lane] = g[0];
+  gst[lane + 64] = g[1];
+  lst[lane] = cur[lane] = l0;
+  lst[lane + 64] = cur[lane + 64] = l1;
+  return tot[0] + tot[1];
+}
+
+// Stable rank of the round's valid lanes within their digit: writes every
+// valid lane's tile-local slot and advances the digit's running counter.
+__device__ __forceinline__ int rank_in_tile(int d, bool valid, int32_t* cur, uint64_t below) {
+  const uint64_t peers = digit_peers(d, valid);
+  const int start = valid ? cur[d] : 0;
+  wave_sync();
+  const int l = start + __popcll(peers & below);
+  if (valid && (peers & below) == 0) cur[d] = start + __popcll(peers);
+  wave_sync();
+  return l;
+}
+
+// The word arrays between the passes hold one 64-bit entry per word: the
+// position (bits 0-31), the sequence as an offset from the first sequence of
+// the position's pass-1 tile (bits 32-38) and the key (bits 39-52).
+__device__ __forceinline__ uint64_t word_entry(int64_t q, int seq_off, int key) {
+  return (uint64_t)(uint32_t)q | ((uint64_t)seq_off << 32) | ((uint64_t)key << 39);
+}
+
+// Pass 1, scattering.  The tile's codes are staged in LDS; every word, in
+// position order, is ranked within its low digit into the tile's own bucket
+// order in LDS (key | position offset << 14 | sequence offset << 25), and the
+// staged words are then written out bucket by bucket, consecutive lanes to
+// consecutive slots.  Runs only on a valid layout (the tile table is complete,
+// a tile meets at most 103 sequence starts and the words fit the word array).
+constexpr int kTileStarts = 2;  // 128 starts
+static_assert(kIxTile == 2048, "word staging packs a position offset in 11 bits");
+
+__device__ __forceinline__ int word_key_lds(const uint8_t* cl, int off, bool in_range, const SeedClasses& sc) {
+  if (!in_range) return -1;
+  const int w0 = cl[off], w1 = cl[off + 1], w2 = cl[off + 2], w3 = cl[off + 3];
+  if (w0 >= 20 || w1 >= 20 || w2 >= 20 || w3 >= 20) return -1;
+  return seed_key_dev(sc, w0, w1, w2, w3);
+}
+
+__global__ __launch_bounds__(64 * kIxWaves) void k_ix_scatter1(
+    const uint8_t* __restrict__ codes, const int64_t* __restrict__ seq_start, int32_t n_seqs, int64_t n_padded,
+    int64_t tiles, SeedClasses sc, const int32_t* __restrict__ tile_seq, const int32_t* __restrict__ err,
+    const int32_t* __restrict__ offs, int64_t cap, uint64_t* __restrict__ words) {
+  __shared__ int32_t gst_all[kIxWaves][kD0], lst_all[kIxWaves][kD0], cur_all[kIxWaves][kD0];
+  __shared__ int64_t st_all[kIxWaves][64 * kTileStarts];
+  __shared__ uint32_t stage_all[kIxWaves][kIxTile];
+  __shared__ uint8_t cl_all[kIxWaves][kIxTile + 64];
+  const int lane = lane_id(), wv = threadIdx.x >> 6;
+  const int64_t tile = (int64_t)blockIdx.x * kIxWaves + wv;
+  if (tile >= tiles || n_seqs == 0 || (*err & 1)) return;
+  int32_t *gst = gst_all[wv], *lst = lst_all[wv], *cur = cur_all[wv];
+  int64_t* st = st_all[wv];
+  uint32_t* stage = stage_all[wv];
+  uint8_t* cl = cl_all[wv];
+  const int64_t beg = tile * kIxTile;
+  const int64_t end = min(beg + kIxTile, n_padded - (kSeed - 1));  // word starts [beg, end)
+  const int64_t cend = min(beg + kIxTile + 64, n_padded);          // codes staged [beg, cend)
+#pragma unroll 4
+  for (int r = 0; r < kIxTile / 64 + 1; ++r) {
+    const int64_t p = beg + r * 64 + lane;
+    cl[r * 64 + lane] = p < cend ? codes[p] : (uint8_t)kPadCode;
+  }
+  const int s0 = min(max(tile_seq[tile], 0), n_seqs - 1);
+  load_starts<kTileStarts>(seq_start, n_seqs, s0, st, lane);
+  const int nt = tile_tables<kD0>(offs, tiles, tile, (int64_t)err[1], gst, lst, cur, lane);
+  wave_sync();
+  int s_cur = s0;
+  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  for (int off = 0; beg + off < end; off += 64) {
+    const int64_t q = beg + off + lane;
+    const int key = word_key_lds(cl, off + lane, q < end, sc);
+    const int s = seq_of<kTileStarts>(st, s_cur, s0, q, lane);
+    const int l = rank_in_tile(key & (kD0 - 1), key >= 0, cur, below);
+    if (key >= 0 && (unsigned)l < (unsigned)kIxTile) stage[l] = (uint32_t)key | ((uint32_t)(off + lane) << 14) | ((uint32_t)min(s - s0, 127) << 25);
     s_cur = __shfl(s, 63);
+  }
+  wave_sync();
+  for (int l = lane; l < min(nt, kIxTile); l += 64) {
+    const uint32_t e = stage[l];
+    const int key = (int)(e & 0x3fffu);
+    const int d = key & (kD0 - 1);
+    const int64_t slot = (int64_t)gst[d] + (l - lst[d]);
+    if (slot >= 0 && slot < cap) words[slot] = word_entry(beg + ((e >> 14) & 2047u), (int)(e >> 25), key);
+  }
+}
+
+// Pass 2, counting: histogram of the high digit over the tile's words.
+__global__ __launch_bounds__(64 * kIxWaves) void k_ix_count2(const uint64_t* __restrict__ words,
+                                                            const int32_t* __restrict__ err, int64_t cap,
+                                                            int64_t tiles, int32_t* __restrict__ hist) {
+  __shared__ int32_t cnt_all[kIxWaves][kD0];
+  const int lane = lane_id();
+  const int64_t tile = (int64_t)blockIdx.x * kIxWaves + (threadIdx.x >> 6);
+  if (tile >= tiles || (*err & 1)) return;
+  int32_t* cnt = cnt_all[threadIdx.x >> 6];
+  cnt[lane] = 0;
+  cnt[lane + 64] = 0;
+  wave_sync();
+  const int64_t n = min((int64_t)err[1], cap);
+  const int64_t beg = tile * kIxTile;
+  const int64_t end = min(beg + kIxTile, n);
+  for (int64_t i = beg + lane; i < end; i += 64) atomicAdd(&cnt[min((int)(words[i] >> (39 + kD0Bits)), kD1 - 1)], 1);
+  wave_sync();
+  if (lane < kD1) hist[(int64_t)lane * tiles + tile] = cnt[lane];
+  if (lane + 64 < kD1) hist[(int64_t)(lane + 64) * tiles + tile] = cnt[lane + 64];
+}
+
+// Pass 2, scattering: the tile's words ranked within their high digit into
+// the tile's bucket order in LDS, eight rounds of loads in flight ahead of
+// the ranking, then written out bucket by bucket as occ, occ_seq and the
+// sorted key.
+constexpr int kBatch = 8;
+
+__global__ __launch_bounds__(64 * kIxWaves) void k_ix_scatter2(
+    const uint64_t* __restrict__ words, const int32_t* __restrict__ tile_seq, int64_t tiles1,
+    const int32_t* __restrict__ err, int64_t cap, int64_t tiles, const int32_t* __restrict__ offs, int32_t* __restrict__ occ,
+    int32_t* __restrict__ occ_seq, uint16_t* __restrict__ fkey) {
+  __shared__ int32_t gst_all[kIxWaves][kD0], lst_all[kIxWaves][kD0], cur_all[kIxWaves][kD0];
+  __shared__ uint64_t stage_all[kIxWaves][kIxTile];
+  const int lane = lane_id(), wv = threadIdx.x >> 6;
+  const int64_t tile = (int64_t)blockIdx.x * kIxWaves + wv;
+  if (tile >= tiles || (*err & 1)) return;
+  int32_t *gst = gst_all[wv], *lst = lst_all[wv], *cur = cur_all[wv];
+  uint64_t* stage = stage_all[wv];
+  const int64_t n = min((int64_t)err[1], cap);
+  const int64_t beg = tile * kIxTile;
+  const int64_t end = min(beg + kIxTile, n);
+  const int nt = tile_tables<kD1>(offs, tiles, tile, n, gst, lst, cur, lane);
+  wave_sync();
+  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  uint64_t e_cur[kBatch], e_nxt[kBatch];
+#pragma unroll
+  for (int k = 0; k < kBatch; ++k) {
+    const int64_t i = beg + k * 64 + lane;
+    e_cur[k] = i < end ? words[i] : 0;
+  }
+  for (int64_t b0 = beg; b0 < end; b0 += 64 * kBatch) {
+#pragma unroll
+    for (int k = 0; k < kBatch; ++k) {
+      const int64_t i = b0 + (kBatch + k) * 64 + lane;
+      e_nxt[k] = i < end ? words[i] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < kBatch; ++k) {
+      const bool valid = b0 + k * 64 + lane < end;
+      const int l = rank_in_tile(min((int)(e_cur[k] >> (39 + kD0Bits)), kD1 - 1), valid, cur, below);
+      if (valid && (unsigned)l < (unsigned)kIxTile) stage[l] = e_cur[k];
+    }
+#pragma unroll
+    for (int k = 0; k < kBatch; ++k) e_cur[k] = e_nxt[k];
+  }
+  wave_sync();
+  for (int l = lane; l < min(nt, kIxTile); l += 64) {
+    const uint64_t e = stage[l];
+    const int key = (int)(e >> 39);
+    const int d = min(key >> kD0Bits, kD1 - 1);
+    const int64_t slot = (int64_t)gst[d] + (l - lst[d]);
+    if (slot < 0 || slot >= n) continue;
+    const uint32_t pos = (uint32_t)e;
+    occ[slot] = (int32_t)pos;
+    occ_seq[slot] = (int64_t)(pos >> 11) < tiles1 ? tile_seq[pos >> 11] + (int)((e >> 32) & 127u) : -1;
+    fkey[slot] = (uint16_t)key;
   }
 }
 
@@ -170,11 +385,24 @@ __global__ void k_clear2(int32_t* __restrict__ p) {
   if (threadIdx.x < 2) p[threadIdx.x] = 0;
 }
 
-__global__ void k_key_off(const int32_t* __restrict__ offs, int32_t nchunks, const int32_t* __restrict__ total,
-                          int64_t* __restrict__ key_off) {
-  int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < kNKeys) key_off[k] = offs[(int64_t)k * nchunks];
-  else if (k == kNKeys) key_off[k] = *total;
+// key_off from the sorted keys: the first slot of every key, and for keys with
+// no word the first slot of the next key that has one (n_words past the last).
+// After a layout error the index holds no word.
+__global__ __launch_bounds__(256) void k_ix_key_off(const uint16_t* __restrict__ fkey,
+                                                    const int32_t* __restrict__ err, int64_t cap,
+                                                    int64_t* __restrict__ key_off) {
+  const int64_t n = (err[0] & 1) ? 0 : min((int64_t)err[1], cap);
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n == 0) {
+    if (i <= kNKeys) key_off[i] = 0;
+    return;
+  }
+  if (i >= n) return;
+  const int key = min((int)fkey[i], kNKeys - 1);
+  const int prev = i > 0 ? min((int)fkey[i - 1], kNKeys - 1) : -1;
+  for (int k = prev + 1; k <= key; ++k) key_off[k] = i;
+  if (i == n - 1)
+    for (int k = key + 1; k <= kNKeys; ++k) key_off[k] = n;
 }
 
 // ---------------------------------------------------------------- scan
@@ -285,34 +513,47 @@ IndexLayout index_layout(int64_t n_padded) {
   return L;
 }
 
-// About 16K positions per wavefront, up to 16384 wavefronts (the per-chunk key
-// counts then take 8800 x 16384 x 4 bytes of scratch at most).
-constexpr int64_t kMaxChunks = 16384;
+// Workspace: [error words (256 B)] [tile table] [pass-1 histogram] [pass-2 histogram]
+// [scan scratch] [word entries between the passes (64-bit)] [sorted keys].
+// The word arrays hold n_padded - kPadLen entries, a bound on the residues of any valid
+// layout that grows with n_padded alone, so a workspace sized for the largest
+// bank serves every smaller one whatever its number of sequences.
+struct IxWs {
+  int64_t tiles1, tiles2, cap;
+  size_t tile_seq, hist1, hist2, tmp, words, fkey, total;
+};
 
-IndexChunks index_chunks(int64_t n_padded) {
-  int64_t nch = (n_padded + 16383) / 16384;
-  nch = nch < 1 ? 1 : (nch > kMaxChunks ? kMaxChunks : nch);
-  int64_t chunk = (n_padded + nch - 1) / nch;
-  chunk = (chunk + 63) / 64 * 64;
-  if (chunk < 64) chunk = 64;
-  IndexChunks c;
-  c.chunk = chunk;
-  c.nchunks = (int32_t)((n_padded + chunk - 1) / chunk);
-  if (c.nchunks < 1) c.nchunks = 1;
-  return c;
+IxWs ix_ws(int64_t n_padded) {
+  IxWs w;
+  w.cap = n_padded > kPadLen ? n_padded - kPadLen : 0;
+  w.tiles1 = (n_padded + kIxTile - 1) / kIxTile;
+  if (w.tiles1 < 1) w.tiles1 = 1;
+  w.tiles2 = (w.cap + kIxTile - 1) / kIxTile;
+  if (w.tiles2 < 1) w.tiles2 = 1;
+  size_t off = 256;
+  w.tile_seq = off;
+  off = align_up(off + sizeof(int32_t) * (size_t)w.tiles1, 256);
+  w.hist1 = off;
+  off = align_up(off + sizeof(int32_t) * (size_t)(kD0 * w.tiles1), 256);
+  w.hist2 = off;
+  off = align_up(off + sizeof(int32_t) * (size_t)(kD1 * w.tiles2), 256);
+  w.tmp = off;
+  const int64_t scan_n = kD0 * w.tiles1 > kD1 * w.tiles2 ? kD0 * w.tiles1 : kD1 * w.tiles2;
+  off = align_up(off + scan_tmp_bytes(scan_n), 256);
+  w.words = off;
+  off = align_up(off + sizeof(uint64_t) * (size_t)w.cap, 256);
+  w.fkey = off;
+  off = align_up(off + sizeof(uint16_t) * (size_t)w.cap, 256);
+  w.total = off;
+  return w;
 }
 
-// workspace: [counters (256 B)] [counts: kNKeys * nchunks int32] [scan tops]
-size_t index_ws_bytes(int64_t n_padded) {
-  IndexChunks c = index_chunks(n_padded);
-  int64_t n = (int64_t)kNKeys * c.nchunks;
-  return 256 + align_up(sizeof(int32_t) * (size_t)n, 256) + scan_tmp_bytes(n);
-}
+size_t index_ws_bytes(int64_t n_padded) { return ix_ws(n_padded).total; }
 
 int index_enqueue(const uint8_t* d_codes, const int64_t* d_seq_start, int32_t n_seqs, int64_t n_padded,
                   void* d_index, void* d_ws, int32_t* d_err, plast_index_t* out, hipStream_t stream) {
   IndexLayout L = index_layout(n_padded);
-  IndexChunks C = index_chunks(n_padded);
+  const IxWs W = ix_ws(n_padded);
   uint8_t* base = (uint8_t*)d_index;
   int64_t* key_off = (int64_t*)(base + L.key_off);
   int32_t* occ = (int32_t*)(base + L.occ);
@@ -322,27 +563,42 @@ int index_enqueue(const uint8_t* d_codes, const int64_t* d_seq_start, int32_t n_
 
   uint8_t* ws = (uint8_t*)d_ws;
   int32_t* total = d_err + 1;
-  int64_t ncount = (int64_t)kNKeys * C.nchunks;
-  int32_t* counts = (int32_t*)(ws + 256);
-  void* tmp = ws + 256 + align_up(sizeof(int32_t) * (size_t)ncount, 256);
+  int32_t* tile_seq = (int32_t*)(ws + W.tile_seq);
+  int32_t* hist1 = (int32_t*)(ws + W.hist1);
+  int32_t* hist2 = (int32_t*)(ws + W.hist2);
+  void* tmp = ws + W.tmp;
+  uint64_t* words = (uint64_t*)(ws + W.words);
+  uint16_t* fkey = (uint16_t*)(ws + W.fkey);
 
   SeedClasses sc = seed_classes();
   timing_mark(kStageIndex, false, stream);
   // a fill kernel rather than a memset node, so that the sequence can be captured in a graph
   hipLaunchKernelGGL(k_clear2, dim3(1), dim3(64), 0, stream, d_err);
   hipLaunchKernelGGL(k_layout_check, dim3((unsigned)((n_seqs + 1 + 255) / 256)), dim3(256), 0, stream, d_seq_start,
-                     n_seqs, n_padded, d_err);
-  hipLaunchKernelGGL(k_codes_check, dim3((unsigned)((scan_len + kCheckChunk - 1) / kCheckChunk)), dim3(kChunkWave), 0,
-                     stream, d_codes, d_seq_start, n_seqs, n_padded, scan, scan_len, d_err);
-  // Counting and scattering read seq_start only as bounds of a search over
-  // [0, n_seqs), so they stay in bounds after a layout error.
-  hipLaunchKernelGGL(k_index_count, dim3((unsigned)C.nchunks), dim3(kChunkWave), 0, stream, d_codes, n_padded,
-                     C.chunk, C.nchunks, sc, counts);
-  exclusive_scan_i32(counts, ncount, total, tmp, stream);
-  hipLaunchKernelGGL(k_index_scatter, dim3((unsigned)C.nchunks), dim3(kChunkWave), 0, stream, d_codes,
-                     d_seq_start, n_seqs, n_padded, C.chunk, C.nchunks, sc, (const int32_t*)counts, occ, occ_seq);
-  hipLaunchKernelGGL(k_key_off, dim3((kNKeys + 1 + 255) / 256), dim3(256), 0, stream, (const int32_t*)counts,
-                     C.nchunks, (const int32_t*)total, key_off);
+                     n_seqs, n_padded, tile_seq, W.tiles1, d_err);
+  const int64_t chunks = (scan_len + kCheckChunk - 1) / kCheckChunk;
+  hipLaunchKernelGGL(k_codes_check, dim3((unsigned)((chunks + kIxWaves - 1) / kIxWaves)), dim3(64 * kIxWaves), 0,
+                     stream, d_codes, d_seq_start, n_seqs, n_padded, (const int32_t*)tile_seq, W.tiles1, scan,
+                     scan_len, d_err);
+  // After a layout error the passes that read the tile table or the word
+  // arrays return at once and key_off says the index holds no word.
+  const unsigned g1 = (unsigned)((W.tiles1 + kIxWaves - 1) / kIxWaves);
+  const unsigned g2 = (unsigned)((W.tiles2 + kIxWaves - 1) / kIxWaves);
+  hipLaunchKernelGGL(k_ix_count1, dim3(g1), dim3(64 * kIxWaves), 0, stream, d_codes, n_padded, W.tiles1, sc, hist1);
+  exclusive_scan_i32(hist1, kD0 * W.tiles1, total, tmp, stream);
+  hipLaunchKernelGGL(k_ix_scatter1, dim3(g1), dim3(64 * kIxWaves), 0, stream, d_codes, d_seq_start, n_seqs,
+                     n_padded, W.tiles1, sc, (const int32_t*)tile_seq, (const int32_t*)d_err, (const int32_t*)hist1,
+                     W.cap, words);
+  hipLaunchKernelGGL(k_ix_count2, dim3(g2), dim3(64 * kIxWaves), 0, stream, (const uint64_t*)words,
+                     (const int32_t*)d_err, W.cap, W.tiles2, hist2);
+  exclusive_scan_i32(hist2, kD1 * W.tiles2, nullptr, tmp, stream);
+  hipLaunchKernelGGL(k_ix_scatter2, dim3(g2), dim3(64 * kIxWaves), 0, stream, (const uint64_t*)words,
+                     (const int32_t*)tile_seq, W.tiles1, (const int32_t*)d_err, W.cap, W.tiles2,
+                     (const int32_t*)hist2, occ,
+                     occ_seq, fkey);
+  const int64_t nb = (W.cap + 255) / 256 > (kNKeys + 1 + 255) / 256 ? (W.cap + 255) / 256 : (kNKeys + 1 + 255) / 256;
+  hipLaunchKernelGGL(k_ix_key_off, dim3((unsigned)nb), dim3(256), 0, stream, (const uint16_t*)fkey,
+                     (const int32_t*)d_err, W.cap, key_off);
   timing_mark(kStageIndex, true, stream);
   PLAST_HIP(hipGetLastError());
 

@@ -74,11 +74,7 @@ struct IndexLayout {
   size_t key_off, occ, occ_seq, scan, total;
 };
 IndexLayout index_layout(int64_t n_padded);
-struct IndexChunks {
-  int64_t chunk;
-  int32_t nchunks;
-};
-IndexChunks index_chunks(int64_t n_padded);
+// Workspace of one index build; it grows with n_padded only.
 size_t index_ws_bytes(int64_t n_padded);
 
 // Enqueues the whole build (no host synchronisation).  d_err[0] receives error
