@@ -100,8 +100,9 @@ __device__ __forceinline__ int seq_of(const int64_t* st, int s_cur, int s0, int6
 // Validation and scan codes, position-parallel (so that banks of many short
 // sequences, such as translated fragments, keep every lane busy).  Each
 // wavefront takes kCheckChunk consecutive positions of [0, scan_len), two
-// tiles: it takes the sequence holding its first position from the tile table
-// and then walks its positions in order.  Position p is a residue iff some
+// tiles: it takes the sequence holding its first position from the tile table,
+// loads the starts its positions can meet into LDS and walks its positions in
+// order.  Position p is a residue iff some
 // sequence s has seq_start[s] <= p < seq_start[s + 1] - kPadLen; every other
 // position below n_padded must hold the separator code, and the tail slack is
 // set to it.
@@ -130,22 +131,36 @@ __global__ __launch_bounds__(64 * kIxWaves) void k_codes_check(const uint8_t* __
   wave_sync();
   int s_cur = s0;
   bool bad = false;
-  for (int64_t base = beg; base < end; base += 64) {
-    const int64_t p = base + lane;
-    const int s = seq_of<kCheckStarts>(st, s_cur, s0, p, lane);
-    if (p < end) {
-      if (p < n_padded) {
-        // end of sequence s from the table (seq_start[n_seqs] == n_padded)
-        const int64_t nx = s + 1 < n_seqs ? st[min(s - s0, 64 * kCheckStarts - 1)] : n_padded;
-        const bool residue = s >= 0 && p < nx - kPadLen;
-        const uint8_t c = codes[p];
+  // 256 positions per round, four consecutive ones per lane (scan is 256-byte
+  // aligned and scan_len a multiple of 256, so each lane writes one dword)
+  for (int64_t base = beg; base < end; base += 256) {
+    const int64_t p = base + 4 * lane;
+    // sequence holding p: a 256-position window meets at most 13 starts, so
+    // lanes 0..15 read the next 16 from the table and every lane counts them
+    const int64_t nxt = lane < 16 ? st[min(s_cur - s0 + lane, 64 * kCheckStarts - 1)] : INT64_MAX;
+    int s = s_cur;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) s += p >= __shfl(nxt, k) ? 1 : 0;
+    // starts of sequences s + 1 and s + 2 (seq_start[n_seqs] == n_padded); at
+    // most one of the lane's four positions begins a sequence
+    const int64_t e0 = s + 1 < n_seqs ? st[min(s - s0, 64 * kCheckStarts - 1)] : n_padded;
+    const int64_t e1 = s + 2 < n_seqs ? st[min(s + 1 - s0, 64 * kCheckStarts - 1)] : n_padded;
+    uint32_t out = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int64_t q = p + k;
+      uint32_t c = kPadCode;
+      if (q < n_padded) {
+        const bool next = q >= e0;
+        const bool residue = s + (next ? 1 : 0) >= 0 && q < (next ? e1 : e0) - kPadLen;
+        c = codes[q];
         bad |= residue ? (c >= 20) : (c != kPadCode);
-        scan[p] = (uint8_t)((residue && c < 20 ? c : kPadCode) * kScale);
-      } else {
-        scan[p] = (uint8_t)(kPadCode * kScale);
+        if (!(residue && c < 20)) c = kPadCode;
       }
+      out |= (c * kScale) << (8 * k);
     }
-    s_cur = __shfl(s, 63);
+    *(uint32_t*)(scan + p) = out;
+    s_cur = __shfl(s + (p + 3 >= e0 ? 1 : 0), 63);
   }
   if (bad) atomicOr(err, 2);
 }
@@ -387,22 +402,27 @@ __global__ void k_clear2(int32_t* __restrict__ p) {
 
 // key_off from the sorted keys: the first slot of every key, and for keys with
 // no word the first slot of the next key that has one (n_words past the last).
-// After a layout error the index holds no word.
+// After a layout error the index holds no word.  A fixed grid strides over the
+// words (their count is known only on the device).
+constexpr int kKeyOffBlocks = 4096;
+
 __global__ __launch_bounds__(256) void k_ix_key_off(const uint16_t* __restrict__ fkey,
                                                     const int32_t* __restrict__ err, int64_t cap,
                                                     int64_t* __restrict__ key_off) {
   const int64_t n = (err[0] & 1) ? 0 : min((int64_t)err[1], cap);
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n == 0) {
-    if (i <= kNKeys) key_off[i] = 0;
-    return;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < max(n, (int64_t)kNKeys + 1); i += stride) {
+    if (n == 0) {
+      key_off[i] = 0;  // i <= kNKeys here
+      continue;
+    }
+    if (i >= n) continue;
+    const int key = min((int)fkey[i], kNKeys - 1);
+    const int prev = i > 0 ? min((int)fkey[i - 1], kNKeys - 1) : -1;
+    for (int k = prev + 1; k <= key; ++k) key_off[k] = i;
+    if (i == n - 1)
+      for (int k = key + 1; k <= kNKeys; ++k) key_off[k] = n;
   }
-  if (i >= n) return;
-  const int key = min((int)fkey[i], kNKeys - 1);
-  const int prev = i > 0 ? min((int)fkey[i - 1], kNKeys - 1) : -1;
-  for (int k = prev + 1; k <= key; ++k) key_off[k] = i;
-  if (i == n - 1)
-    for (int k = key + 1; k <= kNKeys; ++k) key_off[k] = n;
 }
 
 // ---------------------------------------------------------------- scan
@@ -596,9 +616,9 @@ int index_enqueue(const uint8_t* d_codes, const int64_t* d_seq_start, int32_t n_
                      (const int32_t*)tile_seq, W.tiles1, (const int32_t*)d_err, W.cap, W.tiles2,
                      (const int32_t*)hist2, occ,
                      occ_seq, fkey);
-  const int64_t nb = (W.cap + 255) / 256 > (kNKeys + 1 + 255) / 256 ? (W.cap + 255) / 256 : (kNKeys + 1 + 255) / 256;
-  hipLaunchKernelGGL(k_ix_key_off, dim3((unsigned)nb), dim3(256), 0, stream, (const uint16_t*)fkey,
-                     (const int32_t*)d_err, W.cap, key_off);
+  const int64_t nb = (W.cap > kNKeys ? W.cap : kNKeys + 1) / 256 + 1;
+  hipLaunchKernelGGL(k_ix_key_off, dim3((unsigned)(nb < kKeyOffBlocks ? nb : kKeyOffBlocks)), dim3(256), 0, stream,
+                     (const uint16_t*)fkey, (const int32_t*)d_err, W.cap, key_off);
   timing_mark(kStageIndex, true, stream);
   PLAST_HIP(hipGetLastError());
 
