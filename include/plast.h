@@ -121,8 +121,9 @@ int plast_index_bytes(int64_t n_padded, int32_t n_seqs, size_t* index_bytes, siz
 
 /*
  * Stage 0, bank indexing (Sec. 3.3.1): the subset-seed key of every 4-letter
- * word that lies inside one sequence, then a stable counting sort by key, so
- * that inside a key occurrences are ascending by (sequence, position).
+ * word that lies inside one sequence, then a stable sort by key (two radix
+ * passes on 7-bit digits), so that inside a key occurrences are ascending by
+ * (sequence, position).
  *
  * Padded layout of the bank (d_codes, n_padded bytes; d_seq_start, n_seqs + 1
  * int64): a run of PLAST_PAD_LEN codes PLAST_PAD_CODE, sequence 0, a run, ...,

@@ -67,9 +67,23 @@ def test_index_edge_cases(B):
         synth.Bank.from_strings(["A" * 5000]),                              # one huge key
         synth.random_bank(rng, 300, 0, 90, 3),                              # skewed, ragged
         synth.random_bank(rng, 4000, 0, 12, 20),                            # many short sequences
+        _boundary_bank(rng),                                                # starts on tile boundaries
     ]
     for bank in cases:
         _assert_index_equal(B, bank)
+
+
+def _boundary_bank(rng):
+    """Sequence starts exactly on, one before and one after the 2048-position
+    tiles and 4096-position check chunks of the index build, a run of empty
+    sequences across a tile boundary, and n_padded a multiple of 4096."""
+    starts = [20, 2048, 4095, 6145, 8192] + [8192 + 20 * k for k in range(1, 12)] + [10239, 12289]
+    end = 16384
+    lens = [b - a - 20 for a, b in zip(starts, starts[1:] + [end])]
+    assert min(lens) >= 0
+    bank = synth.Bank.from_seqs([rng.integers(0, 20, n).astype(np.uint8) for n in lens])
+    assert list(bank.seq_start[:-1]) == starts and int(bank.seq_start[-1]) == end
+    return bank
 
 
 def test_index_rejects_bad_input(B):
