@@ -31,6 +31,7 @@ reported:
 Usage: python bench.py [--steps K] [--warmup W] [--config 1|2|3] [--serving] [--plastx]
 """
 import argparse
+import glob
 import hashlib
 import json
 import os
@@ -118,6 +119,7 @@ def cpu_baseline(w, gpu_hits_host, n_ext_total, sample_ext, s1, s2):
         acc += int(work[k])
         if acc >= sample_ext:
             break
+    keys_1t = np.array(sorted(keys[: max(1, len(keys) // 16)]), dtype=np.int32)  # same random order
     keys = np.array(sorted(keys), dtype=np.int32)
     t0 = time.perf_counter()
     ref, n_ext_s = C.ungapped_hits(w.bank1, w.bank2, s1, keys=keys, idx1=i1, idx2=i2, nthreads=cores)
@@ -133,6 +135,22 @@ def cpu_baseline(w, gpu_hits_host, n_ext_total, sample_ext, s1, s2):
     mine = O.canonical(gpu_hits_host[np.isin(hk, keys)])
     equal = bool(np.array_equal(mine, ref))
     t_job = t_index + (t_ung + t_gap) * (n_ext_total / max(1, n_ext_s))
+    # one thread, ungapped loop only, on a sixteenth of the sampled keys
+    t0 = time.perf_counter()
+    _, n_ext_1 = C.ungapped_hits(w.bank1, w.bank2, s1, keys=keys_1t, idx1=i1, idx2=i2, nthreads=1,
+                                 canonicalize=False)
+    t_1 = time.perf_counter() - t0
+    # configuration 0 end to end: both indexes, every key, the gapped filter and the sorted list
+    from paper_0804_3643_amd import synth
+    w0 = synth.make_workload(0)
+    e2e = {}
+    for nt in (cores, 1):
+        t0 = time.perf_counter()
+        j1, j2 = C.build_index(w0.bank1), C.build_index(w0.bank2)
+        r0, n0 = C.ungapped_hits(w0.bank1, w0.bank2, s1, idx1=j1, idx2=j2, nthreads=nt)
+        C.gapped_scores(w0.bank1, w0.bank2, r0, nthreads=nt)
+        e2e["%d_threads_s" % nt] = time.perf_counter() - t0
+    e2e["extensions"] = int(n0)
     return {
         "value": n_ext_total / t_job, "unit": "ext/s", "cores": cores, "kind": "oracle",
         "sample": ("plain C oracle, %d threads: index of both full banks (%.2f s) + %d seeded random keys "
@@ -140,6 +158,97 @@ def cpu_baseline(w, gpu_hits_host, n_ext_total, sample_ext, s1, s2):
                    "scaled to all %d extensions" % (cores, t_index, len(keys), n_ext_s, 100.0 * n_ext_s /
                                                     n_ext_total, t_ung, len(ref), t_gap, n_ext_total)),
         "oracle_hits_equal_gpu_on_sample": equal, "n_gapped_pass_sample": int((g >= s2).sum()),
+        "single_thread": {"ext_per_s": n_ext_1 / t_1,
+                          "sample": "ungapped loop, 1 thread, %d of the sampled keys (%d extensions) in %.2f s"
+                                    % (len(keys_1t), n_ext_1, t_1)},
+        "config0_end_to_end": e2e,
+    }
+
+
+# Published MI355X figures the measured peaks stand for: 256 CUs at up to
+# 2.4 GHz, 64 int32 / 128 packed 16-bit lane operations per clock per CU, LDS
+# 128 bytes (32 lookups of 4 bytes) per clock per CU, HBM3E 8 TB/s.
+PUBLISHED_PEAKS = {"valu_i32": 256 * 64 * 2.4e9, "valu_pk_i16": 256 * 128 * 2.4e9, "valu_pk_f16": 256 * 128 * 2.4e9,
+                   "lds_lookup": 256 * 32 * 2.4e9, "hbm_copy": 8e12}
+
+
+def machine_info():
+    """Host CPU (model, sockets, threads) and the GPU's engine clock levels
+    as sysfs lists them (the current level is starred), when readable."""
+    info = {"host_logical_cpus": os.cpu_count()}
+    try:
+        info["host_cpus_allowed"] = len(os.sched_getaffinity(0))
+    except AttributeError:
+        pass
+    try:
+        txt = open("/proc/cpuinfo").read()
+        models = re.findall(r"^model name\s*:\s*(.+)$", txt, re.M)
+        info["host_cpu_model"] = models[0].strip() if models else None
+        info["host_sockets"] = len(set(re.findall(r"^physical id\s*:\s*(\d+)$", txt, re.M))) or None
+    except OSError:
+        pass
+    clocks = []
+    for path in sorted(glob.glob("/sys/class/drm/card*/device/pp_dpm_sclk"))[:8]:
+        try:
+            clocks.append(" ".join(open(path).read().split()))
+        except OSError:
+            pass
+    info["gpu_sclk_levels"] = clocks or None
+    return info
+
+
+def measured_peaks(B, torch, dev):
+    """plast_probe_peak rates (best of 3) beside the published figures."""
+    buf = B._alloc(4 << 30, dev)  # the copy moves 2 GiB each way
+    out = {}
+    for kind, (_code, unit) in B.PROBES.items():
+        r = B.probe_peak(kind, buf, reps=3)
+        out[kind] = {"rate": r, "unit": unit, "published": PUBLISHED_PEAKS[kind],
+                     "frac_of_published": r / PUBLISHED_PEAKS[kind]}
+    del buf
+    # int32 lane operations per CU per clock if the chip ran at the published 2.4 GHz (64 by the figures)
+    out["valu_i32_lane_ops_per_cu_clock_at_2_4_ghz"] = out["valu_i32"]["rate"] / (256 * 2.4e9)
+    return out
+
+
+def plant_recall(torch, np, w, hits, passed):
+    """Planted homologous pairs with at least one ungapped hit and with at
+    least one hit passing the gapped filter, by bins of realised identity."""
+    if not w.plants:
+        return None
+    n2 = w.bank2.n_seqs
+    h = hits.to(torch.int64)
+    key = h[:, 0] * n2 + h[:, 2]
+    pk = torch.tensor([p.src * n2 + p.dst for p in w.plants], dtype=torch.int64, device=hits.device)
+    found = torch.isin(pk, key).cpu().numpy()
+    found_g = torch.isin(pk, key[passed.to(torch.bool)]).cpu().numpy()
+    ident = np.array([p.identity for p in w.plants])
+    bins = []
+    for lo in np.arange(0.20, 0.70, 0.05):
+        m = (ident >= lo - 1e-9) & (ident < lo + 0.05 - 1e-9)
+        if m.any():
+            bins.append({"identity": [round(float(lo), 2), round(float(lo + 0.05), 2)], "pairs": int(m.sum()),
+                         "with_hit": int(found[m].sum()), "passing_gapped": int(found_g[m].sum())})
+    return {"pairs": len(w.plants), "with_hit": int(found.sum()), "passing_gapped": int(found_g.sum()),
+            "by_realised_identity": bins}
+
+
+def key_stats(torch, np, ia, ib):
+    """Bucket sizes per seed key (bank 2) and the share of the work in the 16
+    heaviest keys (n1 x n2)."""
+    n1 = torch.diff(ia.key_off()).to(torch.float64)
+    n2 = torch.diff(ib.key_off()).to(torch.float64)
+    work = n1 * n2
+    c2 = n2.cpu().numpy()
+    nz = c2[c2 > 0]
+    hist = np.bincount(np.floor(np.log2(nz)).astype(np.int64)) if nz.size else np.zeros(0, np.int64)
+    return {
+        "bank2_nonempty_keys": int(nz.size),
+        "bank2_max": int(nz.max()) if nz.size else 0,
+        "bank2_min_nonempty": int(nz.min()) if nz.size else 0,
+        "bank2_quantiles_50_90_99": [float(np.quantile(nz, q)) for q in (0.5, 0.9, 0.99)] if nz.size else None,
+        "bank2_log2_histogram": {"%d-%d" % (1 << k, (2 << k) - 1): int(c) for k, c in enumerate(hist) if c},
+        "top16_work_share": float(torch.topk(work, 16).values.sum().item() / max(1.0, work.sum().item())),
     }
 
 
@@ -610,14 +719,18 @@ def main():
     if args.copy_calibration:
         copy_calibration(torch, dev)
 
+    # the wall-time runs above reused the hit and filter buffers: recompute both on the resident banks
+    h_fin, _ = ext.run(ia, ib)
+    g_fin, p_fin = B.gapped_filter(ia, ib, h_fin, params.S2, out=(gbuf, pbuf), tuning=tuning)
+    recall = plant_recall(torch, np, w, h_fin, p_fin)
+    keys_report = key_stats(torch, np, ia, ib)
     stage32 = None
     if args.stage32:
         log("stage 3.2 (full gapped alignment of the passing hits)")
-        # the wall-time runs above reused the hit and filter buffers: recompute both on the resident banks
-        h32, _ = ext.run(ia, ib)
-        g32, p32 = B.gapped_filter(ia, ib, h32, params.S2, out=(gbuf, pbuf), tuning=tuning)
-        stage32 = run_stage32(B, torch, np, w, ia, ib, h32, g32, p32, 3, not args.no_cpu_baseline)
+        stage32 = run_stage32(B, torch, np, w, ia, ib, h_fin, g_fin, p_fin, 3, not args.no_cpu_baseline)
         log("stage 3.2: %d alignments in %.1f ms" % (stage32["alignments"], stage32["call_ms"]))
+    log("measured peaks")
+    peaks = measured_peaks(B, torch, dev)
 
     achieved = n_ext * OPS_PER_EXT / (batched_kernel_ms * 1e-3) / 1e12
     out = {
@@ -665,10 +778,20 @@ def main():
             "bound": "alu", "achieved": achieved, "peak": PEAK_INT16_TOPS, "unit": "TOP/s",
             "frac": achieved / PEAK_INT16_TOPS, "traffic": recorded_traffic(),
             "kernel": "k_ungapped_persistent", "ops_per_ext": OPS_PER_EXT,
+            "measured_peak": peaks["valu_pk_f16"]["rate"] / 1e12,
+            "frac_of_measured_peak": achieved / (peaks["valu_pk_f16"]["rate"] / 1e12),
         },
         "cpu_baseline": None,
         "stage32": stage32,
+        "plant_recall": recall,
+        "key_stats": keys_report,
+        "measured_peaks": peaks,
+        "machine": machine_info(),
     }
+    if stage32 is not None:
+        r = stage32["roofline"]
+        r["measured_peak"] = peaks["valu_i32"]["rate"] / 1e12
+        r["frac_of_measured_peak"] = r["achieved"] / r["measured_peak"]
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a key sample)")
         hh = host_b[0].numpy().astype(np.int64)

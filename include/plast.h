@@ -421,6 +421,31 @@ int plast_align(const plast_index_t* a, const plast_index_t* b, const plast_hit_
                 const uint8_t* d_pass, int64_t n_hits, const plast_align_params_t* p, void* d_ws, size_t ws_bytes,
                 plast_alignment_t* d_out, int32_t* d_cover, int64_t* h_n_out, void* stream);
 
+/*
+ * Measured denominators for the rooflines (not part of the search): each probe
+ * runs one kind of work at the highest rate the chip sustains (2048 workgroups
+ * of 256 threads, 8 waves per SIMD), once to warm up and then reps times
+ * (1..100), timed with HIP events on the stream; *rate is the best rep.
+ *   PLAST_PROBE_VALU_I32     int32 add-then-max chains: operations/s (2 per update)
+ *   PLAST_PROBE_VALU_PK_I16  the same on packed 16-bit integers: operations/s (4 per update)
+ *   PLAST_PROBE_VALU_PK_F16  the same on packed binary16: operations/s (4 per update)
+ *   PLAST_PROBE_LDS          conflict-free 32-bit LDS lookups/s
+ *   PLAST_PROBE_HBM_COPY     copy of the first half of d_buf to the second: bytes/s read + written
+ * d_buf: caller device memory, 256-byte aligned, at least 2 MiB for the compute
+ * probes (each thread writes one int32) and 1 MiB for the copy, whose size is
+ * buf_bytes (1 GiB or more gives a stable figure).  Synchronises the stream.
+ * Errors: PLAST_E_ARG (null pointer, unknown kind, reps out of range,
+ * misaligned buffer), PLAST_E_WORKSPACE (buffer too small), PLAST_E_HIP.
+ */
+enum {
+  PLAST_PROBE_VALU_I32 = 0,
+  PLAST_PROBE_VALU_PK_I16 = 1,
+  PLAST_PROBE_VALU_PK_F16 = 2,
+  PLAST_PROBE_LDS = 3,
+  PLAST_PROBE_HBM_COPY = 4
+};
+int plast_probe_peak(int32_t kind, void* d_buf, size_t buf_bytes, int32_t reps, double* rate, void* stream);
+
 const char* plast_strerror(int code);
 const char* plast_last_error(void);
 

@@ -30,7 +30,11 @@ EXPORTS = ("plast_index_bytes", "plast_build_index", "plast_ungapped_workspace_b
            "plast_pipeline_result", "plast_pipeline_index", "plast_pipeline_destroy",
            "plast_search_workspace_bytes", "plast_search_enqueue", "plast_search_result",
            "plast_translate_ws_bytes", "plast_translate_count", "plast_translate_write",
-           "plast_align_workspace_bytes", "plast_align", "plast_strerror", "plast_last_error")
+           "plast_align_workspace_bytes", "plast_align", "plast_probe_peak", "plast_strerror", "plast_last_error")
+
+# plast_probe_peak kinds and the unit of each rate
+PROBES = {"valu_i32": (0, "op/s"), "valu_pk_i16": (1, "op/s"), "valu_pk_f16": (2, "op/s"),
+          "lds_lookup": (3, "lookup/s"), "hbm_copy": (4, "B/s")}
 
 TUNE_CLASSES = 4
 TUNE_WIDTHS = (1024, 2048, 4096, 8192, 16384)
@@ -168,6 +172,7 @@ def load():
         AP = ctypes.POINTER(AlignParams)
         lib.plast_align_workspace_bytes.argtypes = [i64, AP, ctypes.POINTER(sz)]
         lib.plast_align.argtypes = [IV, IV, P, P, P, i64, AP, P, sz, P, P, ctypes.POINTER(i64), P]
+        lib.plast_probe_peak.argtypes = [i32, P, sz, i32, ctypes.POINTER(ctypes.c_double), P]
         for f in EXPORTS[:-2]:
             getattr(lib, f).restype = ctypes.c_int
         lib.plast_strerror.argtypes = [ctypes.c_int]
@@ -467,6 +472,17 @@ def canonical_hits(hits):
 
 def timing_enable(on=True):
     _check(load().plast_timing_enable(1 if on else 0), "plast_timing_enable")
+
+
+def probe_peak(kind, buf, reps=3, stream=None):
+    """Measured peak rate of one kind of work (a key of ``PROBES``) with the
+    caller's device buffer ``buf`` (a uint8 tensor, 256-byte aligned): the
+    best of ``reps`` HIP-event timed launches after one warm-up."""
+    code, _unit = PROBES[kind]
+    rate = ctypes.c_double(0.0)
+    _check(load().plast_probe_peak(code, _ptr(buf), buf.numel() * buf.element_size(), reps, ctypes.byref(rate),
+                                   _stream(stream)), "plast_probe_peak")
+    return rate.value
 
 
 def timing_read():

@@ -1,0 +1,185 @@
+// Measured denominators for the rooflines: short kernels that run one kind of
+// work at the highest rate the chip sustains, timed with HIP events.
+//
+// * VALU, int32: independent add-then-max chains (two VALU operations per
+//   update), the operation mix of the DP recurrences.
+// * VALU, packed 16-bit integer and packed binary16: the same chains on
+//   two-element vectors, two operations per lane per instruction.
+// * LDS: 32-bit table lookups, each 64-lane read on 64 consecutive words (no
+//   bank conflict), the access pattern of the per-lane score profiles.
+// * HBM: a copy between the two halves of a buffer, four 16-byte loads in
+//   flight per lane.
+//
+// Every compute probe writes one value per thread, so no chain is dead code.
+#include "plast_internal.h"
+
+namespace plast {
+
+namespace {
+
+constexpr int kProbeThreads = 256;
+constexpr int kProbeBlocks = 2048;  // 8 waves per SIMD on 256 CUs
+constexpr int kChains = 8;
+
+typedef short short2v __attribute__((ext_vector_type(2)));
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+
+__global__ __launch_bounds__(kProbeThreads) void k_probe_i32(int32_t* __restrict__ out, int iters, int seed) {
+  int a[kChains];
+  const int x = (seed ^ (int)threadIdx.x) & 7, y = -seed;
+#pragma unroll
+  for (int k = 0; k < kChains; ++k) a[k] = (int)threadIdx.x + k * seed;
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int k = 0; k < kChains; ++k) a[k] = max((int)((unsigned)a[k] + (unsigned)x), y + k);
+  }
+  int s = 0;
+#pragma unroll
+  for (int k = 0; k < kChains; ++k) s ^= a[k];
+  out[(int64_t)blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kProbeThreads) void k_probe_pk_i16(int32_t* __restrict__ out, int iters, int seed) {
+  short2v a[kChains];
+  const short2v x = {(short)((seed ^ threadIdx.x) & 7), (short)(seed & 3)};
+  const short2v y = {(short)-seed, (short)(1 - seed)};
+#pragma unroll
+  for (int k = 0; k < kChains; ++k) a[k] = short2v{(short)(threadIdx.x + k), (short)(k * seed)};
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int k = 0; k < kChains; ++k) a[k] = __builtin_elementwise_max(a[k] + x, y);
+  }
+  int s = 0;
+#pragma unroll
+  for (int k = 0; k < kChains; ++k) s ^= (int)a[k].x ^ ((int)a[k].y << 16);
+  out[(int64_t)blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kProbeThreads) void k_probe_pk_f16(int32_t* __restrict__ out, int iters, int seed) {
+  half2v a[kChains];
+  const half2v x = {(_Float16)(-(int)((seed ^ threadIdx.x) & 3)), (_Float16)(-1)};
+  const half2v y = {(_Float16)(-seed), (_Float16)(-2 * seed)};
+#pragma unroll
+  for (int k = 0; k < kChains; ++k) a[k] = half2v{(_Float16)(int)(threadIdx.x & 63), (_Float16)k};
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int k = 0; k < kChains; ++k) a[k] = __builtin_elementwise_max(a[k] + x, y);
+  }
+  float s = 0.f;
+#pragma unroll
+  for (int k = 0; k < kChains; ++k) s += (float)a[k].x + (float)a[k].y;
+  out[(int64_t)blockIdx.x * blockDim.x + threadIdx.x] = (int32_t)s;
+}
+
+constexpr int kLdsWords = 64 * 64;  // 16 KB table
+
+__global__ __launch_bounds__(kProbeThreads) void k_probe_lds(int32_t* __restrict__ out, int iters, int seed) {
+  __shared__ int32_t tbl[kLdsWords];
+  for (int i = threadIdx.x; i < kLdsWords; i += blockDim.x) tbl[i] = i * 3 + seed;
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  int acc[kChains];
+#pragma unroll
+  for (int k = 0; k < kChains; ++k) acc[k] = 0;
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int k = 0; k < kChains; ++k) acc[k] += tbl[lane + 64 * ((it + 8 * k) & 63)];
+  }
+  int s = 0;
+#pragma unroll
+  for (int k = 0; k < kChains; ++k) s ^= acc[k];
+  out[(int64_t)blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
+// Four independent 16-byte loads in flight per lane before their stores.
+__global__ __launch_bounds__(kProbeThreads) void k_probe_copy(const int4* __restrict__ src, int4* __restrict__ dst,
+                                                              int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    const int4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+    dst[i] = a;
+    dst[i + stride] = b;
+    dst[i + 2 * stride] = c;
+    dst[i + 3 * stride] = d;
+  }
+  for (; i < n; i += stride) dst[i] = src[i];
+}
+
+}  // namespace
+
+}  // namespace plast
+
+extern "C" int plast_probe_peak(int32_t kind, void* d_buf, size_t buf_bytes, int32_t reps, double* rate,
+                                void* stream_) {
+  using namespace plast;
+  hipStream_t stream = (hipStream_t)stream_;
+  if (!d_buf || !rate) return set_error(PLAST_E_ARG, "plast_probe_peak: null pointer");
+  if (kind < PLAST_PROBE_VALU_I32 || kind > PLAST_PROBE_HBM_COPY)
+    return set_error(PLAST_E_ARG, "plast_probe_peak: unknown kind %d", (int)kind);
+  if (reps < 1 || reps > 100) return set_error(PLAST_E_ARG, "plast_probe_peak: reps must be in 1..100");
+  if ((uintptr_t)d_buf & 255) return set_error(PLAST_E_ARG, "plast_probe_peak: buffer must be 256-byte aligned");
+  const size_t out_bytes = sizeof(int32_t) * (size_t)kProbeBlocks * kProbeThreads;
+  const size_t need = kind == PLAST_PROBE_HBM_COPY ? ((size_t)1 << 20) : out_bytes;
+  if (buf_bytes < need)
+    return set_error(PLAST_E_WORKSPACE, "plast_probe_peak: buffer of %zu bytes, needs at least %zu", buf_bytes, need);
+  // about 3.5 ms per launch at the published peaks (1.7 ms for the LDS probe)
+  const int iters = kind == PLAST_PROBE_LDS ? 8192 : 16384;
+  const double threads = (double)kProbeBlocks * kProbeThreads;
+  double work = 0.0;  // operations, lookups or bytes per launch
+  int64_t n16 = 0;
+  switch (kind) {
+    case PLAST_PROBE_VALU_I32: work = threads * iters * kChains * 2.0; break;
+    case PLAST_PROBE_VALU_PK_I16:
+    case PLAST_PROBE_VALU_PK_F16: work = threads * iters * kChains * 4.0; break;
+    case PLAST_PROBE_LDS: work = threads * iters * kChains; break;
+    default:
+      n16 = (int64_t)(buf_bytes / 2 / 16);
+      work = 2.0 * 16.0 * (double)n16;
+      break;
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = PLAST_OK;
+  double best = 0.0;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    rc = set_error(PLAST_E_HIP, "plast_probe_peak: hipEventCreate failed");
+  }
+  for (int r = 0; rc == PLAST_OK && r <= reps; ++r) {  // launch 0 warms up
+    (void)hipEventRecord(e0, stream);
+    int32_t* out = (int32_t*)d_buf;
+    switch (kind) {
+      case PLAST_PROBE_VALU_I32:
+        hipLaunchKernelGGL(k_probe_i32, dim3(kProbeBlocks), dim3(kProbeThreads), 0, stream, out, iters, r + 1);
+        break;
+      case PLAST_PROBE_VALU_PK_I16:
+        hipLaunchKernelGGL(k_probe_pk_i16, dim3(kProbeBlocks), dim3(kProbeThreads), 0, stream, out, iters, r + 1);
+        break;
+      case PLAST_PROBE_VALU_PK_F16:
+        hipLaunchKernelGGL(k_probe_pk_f16, dim3(kProbeBlocks), dim3(kProbeThreads), 0, stream, out, iters, r + 1);
+        break;
+      case PLAST_PROBE_LDS:
+        hipLaunchKernelGGL(k_probe_lds, dim3(kProbeBlocks), dim3(kProbeThreads), 0, stream, out, iters, r + 1);
+        break;
+      default: {
+        const int4* src = (const int4*)d_buf;
+        int4* dst = (int4*)((uint8_t*)d_buf + (size_t)n16 * 16);
+        hipLaunchKernelGGL(k_probe_copy, dim3(kProbeBlocks), dim3(kProbeThreads), 0, stream, src, dst, n16);
+      }
+    }
+    if (hipGetLastError() != hipSuccess || hipEventRecord(e1, stream) != hipSuccess ||
+        hipEventSynchronize(e1) != hipSuccess) {
+      rc = set_error(PLAST_E_HIP, "plast_probe_peak: launch or event failed");
+      break;
+    }
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess || ms <= 0.f) {
+      rc = set_error(PLAST_E_HIP, "plast_probe_peak: hipEventElapsedTime failed");
+      break;
+    }
+    if (r > 0 && work / (ms * 1e-3) > best) best = work / (ms * 1e-3);
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (rc == PLAST_OK) *rate = best;
+  return rc;
+}

@@ -256,3 +256,20 @@ int main(void) {
     iv = binding.IndexView()
     assert lib.plast_align(ctypes.byref(iv), ctypes.byref(iv), None, None, None, 10, ctypes.byref(ok), None, 0,
                            None, None, ctypes.byref(n_out), None) == binding.E_ARG
+
+
+def test_probe_validation_without_gpu():
+    """plast_probe_peak rejects bad arguments before any HIP call."""
+    lib = binding.load()
+    rate = ctypes.c_double(0.0)
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.plast_probe_peak(0, None, 1 << 30, 3, ctypes.byref(rate), None) == binding.E_ARG
+    assert lib.plast_probe_peak(0, fake, 1 << 30, 3, None, None) == binding.E_ARG
+    assert lib.plast_probe_peak(7, fake, 1 << 30, 3, ctypes.byref(rate), None) == binding.E_ARG
+    assert lib.plast_probe_peak(-1, fake, 1 << 30, 3, ctypes.byref(rate), None) == binding.E_ARG
+    assert lib.plast_probe_peak(0, fake, 1 << 30, 0, ctypes.byref(rate), None) == binding.E_ARG
+    assert lib.plast_probe_peak(0, ctypes.c_void_p(0x1001), 1 << 30, 3, ctypes.byref(rate), None) == binding.E_ARG
+    assert lib.plast_probe_peak(0, fake, 1 << 20, 3, ctypes.byref(rate), None) == binding.E_WORKSPACE
+    assert lib.plast_probe_peak(4, fake, 1 << 19, 3, ctypes.byref(rate), None) == binding.E_WORKSPACE
+    assert b"probe" in lib.plast_last_error()
+    assert set(binding.PROBES) == {"valu_i32", "valu_pk_i16", "valu_pk_f16", "lds_lookup", "hbm_copy"}
