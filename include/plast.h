@@ -406,7 +406,7 @@ typedef struct {
 } plast_align_params_t;
 
 /* Workspace for n_hits input hits; fails with PLAST_E_ARG when
- * max_len1 + 9 max_len2 (about) exceeds the 160 KiB of LDS a workgroup may use. */
+ * max_len1 + 10 max_len2 (about) exceeds the 160 KiB of LDS a workgroup may use. */
 int plast_align_workspace_bytes(int64_t n_hits, const plast_align_params_t* p, size_t* bytes);
 /* d_hits / d_gscore / d_pass: n_hits records as written by plast_ungapped_extend
  * and plast_gapped_filter (only hits with d_pass != 0 are aligned).  Outputs:

@@ -40,6 +40,7 @@ constexpr int kANeg = -(1 << 28);
 constexpr int kSortTile = 4096;     // radix-sort elements per tile (one wavefront, 64 per lane)
 constexpr int kTStride = 32;        // entries per row of the LDS score table
 constexpr int kWall = -16384;       // table entry of any pair with the sentinel letter
+constexpr int kYScale = 64 * 2;     // bytes per letter row of the per-lane profile (64 int16)
 constexpr int kWalkDwords = 512;    // trace-back window: 8 dwords (64 steps) x 64 rows
 constexpr size_t kMaxLds = 160 * 1024;
 
@@ -72,7 +73,7 @@ struct AlignArgs {
 };
 
 struct AlignLayout {
-  size_t hdr, hidx, klo, khi, perm0, perm1, counts, pcount, scan_tmp, heads, tb, pieces, total;
+  size_t hdr, tbl, hidx, klo, khi, perm0, perm1, counts, pcount, scan_tmp, heads, tb, pieces, total;
   int64_t tiles;
   size_t tb_words_per_wave;
 };
@@ -96,6 +97,8 @@ AlignLayout align_layout(int64_t n, const plast_align_params_t& p, int64_t waves
   size_t off = 0;
   L.hdr = off;
   off = align_up(off + sizeof(AlignHeader), 256);
+  L.tbl = off;
+  off = align_up(off + sizeof(int16_t) * 21 * kTStride, 256);
   L.hidx = off;
   off = align_up(off + sizeof(int32_t) * (size_t)n, 256);
   L.klo = off;
@@ -125,19 +128,20 @@ AlignLayout align_layout(int64_t n, const plast_align_params_t& p, int64_t waves
   return L;
 }
 
-// LDS of one alignment workgroup: score table, the strip's per-lane profile,
-// x letters, y letters by column, and the row above the current strip (with
-// padding), whose space the trace-back window reuses once the DP is done.
+// LDS of one alignment workgroup: the strip's per-lane profile, x letters, y
+// letters by column (as profile offsets), and the row above the current strip
+// (with padding), whose space the trace-back window reuses once the DP is done.
+// The score table the profiles are built from stays in global memory (1.3 KB,
+// read once per strip), which keeps 11 workgroups per CU at 1000 letters.
 size_t strip_bytes(int max_len2) {
   const size_t b = sizeof(int2) * ((size_t)max_len2 + 72);
   return b > sizeof(uint32_t) * kWalkDwords ? b : sizeof(uint32_t) * kWalkDwords;
 }
 
 size_t align_lds_bytes(int max_len1, int max_len2) {
-  size_t b = sizeof(int16_t) * 21 * kTStride;
-  b += sizeof(int16_t) * 21 * 64;
+  size_t b = sizeof(int16_t) * 21 * 64;
   b += align_up((size_t)max_len1 + 64, 16);
-  b += align_up((size_t)max_len2 + 136, 16);   // y letters, 64 sentinels before column 0
+  b += align_up(2 * ((size_t)max_len2 + 136), 16);   // y offsets, 64 sentinels before column 0
   b += strip_bytes(max_len2);
   return b;
 }
@@ -309,8 +313,9 @@ __device__ __forceinline__ int shr1(int old, int v) {
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // The strips of one DP over lx rows and the columns 0 .. steps - 64 (x letters
-// in xb, y letters by column in yb, sentinels past both ends, the row above
-// strip 0 in strip[]).
+// in xb; y letters by column in yo, each stored as its byte offset in the
+// profile, letter * kYScale; sentinels past both ends; the row above strip 0 in
+// strip[]).  The stored offset makes a lookup address one addition.
 //
 // Values are carried shifted by (i + j) * extend (H' = H + (i + j) ext, and
 // likewise E', F'), which removes the extension term from both gap recurrences:
@@ -330,7 +335,7 @@ __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlan
 // column of row `row` (per lane: -1 elsewhere) whose H equals `target`.
 template <bool TRACE>
 __device__ __forceinline__ void side_dp(int lx, int ly, int steps, int ge, int go, const int16_t* T, int16_t* prof,
-                                        const uint8_t* xb, const uint8_t* yb, int2* strip, uint32_t* tb, int& best,
+                                        const uint8_t* xb, const uint16_t* yo, int2* strip, uint32_t* tb, int& best,
                                         int& bpos, int row = 0, int target = 0, int* jf = nullptr) {
   const int lane = threadIdx.x;
   const int nu8 = steps >> 3;
@@ -346,8 +351,8 @@ __device__ __forceinline__ void side_dp(int lx, int ly, int steps, int ge, int g
 #pragma unroll
       for (int yc = 0; yc < 21; ++yc) prof[yc * 64 + lane] = v[yc];
     }
-    const int16_t* pcol = prof + lane;
-    const uint8_t* ycol = yb + 64 - lane;  // the letter of this lane's column t - lane at step t
+    const uint8_t* pcol = (const uint8_t*)(prof + lane);
+    const uint16_t* ycol = yo + 64 - lane;  // the letter of this lane's column t - lane at step t
     int hm = kANeg, f = kANeg, hup = kANeg, eleft = kANeg, hmleft = kANeg;
     uint32_t* tbs = tb + (size_t)s * nu8 * 64 + lane;
     const int sbase = s << 16;
@@ -368,7 +373,7 @@ __device__ __forceinline__ void side_dp(int lx, int ly, int steps, int ge, int g
       const int ff[8] = {s0.y, s0.w, s1.y, s1.w, s2.y, s2.w, s3.y, s3.w};
       int sc[8];
 #pragma unroll
-      for (int k = 0; k < 8; ++k) sc[k] = pcol[(int)ycol[t8 + k] * 64];
+      for (int k = 0; k < 8; ++k) sc[k] = *(const int16_t*)(pcol + ycol[t8 + k]);
       int oh[8], of[8];
       uint32_t acc = 0;
       int bmax = kANeg;
@@ -424,13 +429,13 @@ __device__ __forceinline__ void side_dp(int lx, int ly, int steps, int ge, int g
 // sentinel; the row above strip 0 is row 0, shifted: H'(0, 0) = 0 and H'(0, k)
 // = -(open + k ext) + k ext = -open, so hm(0, 0) = -open, hm(0, k) = -2 open,
 // F' = NEG, and NEG past ly.
-__device__ __forceinline__ void side_pad(int lx, int ly, int steps, int go, uint8_t* xb, uint8_t* yb,
+__device__ __forceinline__ void side_pad(int lx, int ly, int steps, int go, uint8_t* xb, uint16_t* yo,
                                          int2* strip) {
   const int lane = threadIdx.x;
   for (int k = lx + lane; k < lx + 64; k += 64) xb[k] = (uint8_t)kPadCode;
-  for (int k = ly + 1 + lane; k < steps; k += 64) yb[64 + k] = (uint8_t)kPadCode;
-  yb[lane] = (uint8_t)kPadCode;  // columns -64 .. -1
-  if (lane == 0) yb[64] = (uint8_t)kPadCode;
+  for (int k = ly + 1 + lane; k < steps; k += 64) yo[64 + k] = (uint16_t)(kPadCode * kYScale);
+  yo[lane] = (uint16_t)(kPadCode * kYScale);  // columns -64 .. -1
+  if (lane == 0) yo[64] = (uint16_t)(kPadCode * kYScale);
   for (int k = lane; k < steps; k += 64)
     strip[k] = make_int2(k == 0 ? -go : (k <= ly ? -2 * go : kANeg), kANeg);
   __syncthreads();
@@ -444,7 +449,7 @@ __device__ __forceinline__ void side_pad(int lx, int ly, int steps, int go, uint
 // the trace-back reads those.  Appends the side's pieces to P (count np).
 __device__ __forceinline__ SideStats align_side(const AlignArgs& A, const uint8_t* x, int lx, int dx,
                                                 const uint8_t* y, int ly, int dy, int dir, int p1, int p2, int owner,
-                                                const int16_t* T, int16_t* prof, uint8_t* xb, uint8_t* yb, int2* strip,
+                                                const int16_t* T, int16_t* prof, uint8_t* xb, uint16_t* yo, int2* strip,
                                                 uint32_t* walk, uint32_t* tb, Piece* P, int& np, int32_t* status) {
   const int lane = threadIdx.x;
   const int ge = A.gap_extend, go = A.gap_open;
@@ -452,10 +457,10 @@ __device__ __forceinline__ SideStats align_side(const AlignArgs& A, const uint8_
   if (lx == 0 || ly == 0) return st;
   const int steps = (ly + 64 + 7) & ~7;
   for (int k = lane; k < lx; k += 64) xb[k] = x[(int64_t)k * dx];
-  for (int k = lane; k < ly; k += 64) yb[65 + k] = y[(int64_t)k * dy];
-  side_pad(lx, ly, steps, go, xb, yb, strip);
+  for (int k = lane; k < ly; k += 64) yo[65 + k] = (uint16_t)(y[(int64_t)k * dy] * kYScale);
+  side_pad(lx, ly, steps, go, xb, yo, strip);
   int best = 0, bpos = 0;  // bpos = (strip << 16) | (block start + 1); 0: cell (0, 0)
-  side_dp<false>(lx, ly, steps, ge, go, T, prof, xb, yb, strip, tb, best, bpos);
+  side_dp<false>(lx, ly, steps, ge, go, T, prof, xb, yo, strip, tb, best, bpos);
 
   // best over the wavefront: largest value, then first row, then first block
   // (a row belongs to one lane, so the block decides only within a row)
@@ -486,9 +491,9 @@ __device__ __forceinline__ SideStats align_side(const AlignArgs& A, const uint8_
     const int r_end = (st.i_end - 1) & 63, t8 = (bpos & 0xffff) - 64;
     const int j_hi = min(ly, t8 + 7 - r_end);
     const int steps2 = (j_hi + 64 + 7) & ~7;
-    side_pad(st.i_end, j_hi, steps2, go, xb, yb, strip);
+    side_pad(st.i_end, j_hi, steps2, go, xb, yo, strip);
     int unused0 = 0, unused1 = 0, jf = -1;
-    side_dp<true>(st.i_end, j_hi, steps2, ge, go, T, prof, xb, yb, strip, tb, unused0, unused1, st.i_end, best,
+    side_dp<true>(st.i_end, j_hi, steps2, ge, go, T, prof, xb, yo, strip, tb, unused0, unused1, st.i_end, best,
                   &jf);
     nu8 = steps2 >> 3;
     st.j_end = __shfl(jf, r_end);
@@ -543,7 +548,7 @@ __device__ __forceinline__ SideStats align_side(const AlignArgs& A, const uint8_
     if (state == 0) {
       const uint32_t src = nib & 3u;
       if (src == 0) {
-        const int xa = xb[i - 1], yc = yb[64 + j];
+        const int xa = xb[i - 1], yc = yo[64 + j] / kYScale;
         const int pa = dir > 0 ? p1 + i - 1 : p1 - i;
         const int pb = dir > 0 ? p2 + j - 1 : p2 - j;
         if (run_a < 0) {
@@ -581,23 +586,28 @@ __device__ __forceinline__ SideStats align_side(const AlignArgs& A, const uint8_
   return st;
 }
 
-__global__ __launch_bounds__(64) void k_align(AlignArgs A, const plast_hit_t* hits, const int32_t* hidx,
-                                              const int32_t* perm, const uint64_t* khi, const int32_t* heads,
-                                              AlignHeader* hdr, uint32_t* tb_all, size_t tb_words, Piece* pieces_all,
-                                              plast_alignment_t* out, int32_t* cover) {
-  extern __shared__ __align__(16) uint8_t lds[];
-  int16_t* T = (int16_t*)lds;
-  int16_t* prof = T + 21 * kTStride;
-  uint8_t* xb = (uint8_t*)(prof + 21 * 64);
-  uint8_t* yb = xb + ((A.max_len1 + 64 + 15) & ~15);
-  int2* strip = (int2*)(yb + ((A.max_len2 + 136 + 15) & ~15));
-  uint32_t* walk = (uint32_t*)strip;  // the trace-back runs after the DP of its side
-  const int lane = threadIdx.x;
+// The score table of the shifted recurrence: T[x][y] = score + open + 2 extend
+// for letters, kWall where either is the sentinel (row and column 20).
+__global__ __launch_bounds__(64) void k_align_table(AlignArgs A, int16_t* __restrict__ T) {
   const int t_add = A.gap_open + 2 * A.gap_extend;  // the diagonal term in shifted values
-  for (int k = lane; k < 21 * kTStride; k += 64) {
+  for (int k = threadIdx.x; k < 21 * kTStride; k += 64) {
     const int xa = k / kTStride, yc = k % kTStride;
     T[k] = (int16_t)((xa < 20 && yc < 20) ? (int)A.mat[xa * 20 + yc] + t_add : kWall);
   }
+}
+
+__global__ __launch_bounds__(64) void k_align(AlignArgs A, const int16_t* __restrict__ T, const plast_hit_t* hits,
+                                              const int32_t* hidx, const int32_t* perm, const uint64_t* khi,
+                                              const int32_t* heads, AlignHeader* hdr, uint32_t* tb_all,
+                                              size_t tb_words, Piece* pieces_all, plast_alignment_t* out,
+                                              int32_t* cover) {
+  extern __shared__ __align__(16) uint8_t lds[];
+  int16_t* prof = (int16_t*)lds;
+  uint8_t* xb = (uint8_t*)(prof + 21 * 64);
+  uint16_t* yo = (uint16_t*)(xb + ((A.max_len1 + 64 + 15) & ~15));
+  int2* strip = (int2*)((uint8_t*)yo + ((2 * (A.max_len2 + 136) + 15) & ~15));
+  uint32_t* walk = (uint32_t*)strip;  // the trace-back runs after the DP of its side
+  const int lane = threadIdx.x;
   __syncthreads();
 
   uint32_t* tb = tb_all + (size_t)blockIdx.x * tb_words;
@@ -645,9 +655,9 @@ __global__ __launch_bounds__(64) void k_align(AlignArgs A, const plast_hit_t* hi
       const uint8_t* a = A.a_codes + A.a_start[s1];
       const uint8_t* b = A.b_codes + A.b_start[s2];
       const int la = seq_len(A.a_start, s1), lb = seq_len(A.b_start, s2);
-      const SideStats R = align_side(A, a + p1, la - p1, 1, b + p2, lb - p2, 1, +1, p1, p2, h, T, prof, xb, yb, strip,
+      const SideStats R = align_side(A, a + p1, la - p1, 1, b + p2, lb - p2, 1, +1, p1, p2, h, T, prof, xb, yo, strip,
                                      walk, tb, P, np, &hdr->status);
-      const SideStats L = align_side(A, a + p1 - 1, p1, -1, b + p2 - 1, p2, -1, -1, p1, p2, h, T, prof, xb, yb, strip,
+      const SideStats L = align_side(A, a + p1 - 1, p1, -1, b + p2 - 1, p2, -1, -1, p1, p2, h, T, prof, xb, yo, strip,
                                      walk, tb, P, np, &hdr->status);
       if (lane == 0) {
         const unsigned long long o = atomicAdd(&hdr->n_out, 1ull);
@@ -774,9 +784,11 @@ int align_impl(const plast_index_t* a, const plast_index_t* b, const plast_hit_t
     hipLaunchKernelGGL(k_align_heads, dim3(mb), dim3(256), 0, s, perm[cur], khi, hdr, (const int32_t*)pcount, heads);
     const size_t lds = align_lds_bytes(p->max_len1, p->max_len2);
     PLAST_HIP(hipFuncSetAttribute((const void*)k_align, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    int16_t* tbl = (int16_t*)(ws + L.tbl);
+    hipLaunchKernelGGL(k_align_table, dim3(1), dim3(64), 0, s, A, tbl);
     timing_mark(kStageAlign, false, s);
-    hipLaunchKernelGGL(k_align, dim3((unsigned)waves), dim3(64), lds, s, A, d_hits, hidx, perm[cur], khi, heads, hdr,
-                       tb, L.tb_words_per_wave, pieces, d_out, d_cover);
+    hipLaunchKernelGGL(k_align, dim3((unsigned)waves), dim3(64), lds, s, A, (const int16_t*)tbl, d_hits, hidx,
+                       perm[cur], khi, heads, hdr, tb, L.tb_words_per_wave, pieces, d_out, d_cover);
     timing_mark(kStageAlign, true, s);
     PLAST_HIP(hipGetLastError());
     PLAST_HIP(hipMemcpyAsync(&h0, hdr, sizeof(h0), hipMemcpyDeviceToHost, s));
