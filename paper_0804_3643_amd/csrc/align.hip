@@ -141,7 +141,7 @@ size_t strip_bytes(int max_len2) {
 size_t align_lds_bytes(int max_len1, int max_len2) {
   size_t b = sizeof(int16_t) * 21 * 64;
   b += align_up((size_t)max_len1 + 64, 16);
-  b += align_up(2 * ((size_t)max_len2 + 136), 16);   // y offsets, 64 sentinels before column 0
+  b += align_up((size_t)max_len2 + 136, 16);   // y letters, 64 sentinels before column 0
   b += strip_bytes(max_len2);
   return b;
 }
@@ -335,7 +335,7 @@ __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlan
 // column of row `row` (per lane: -1 elsewhere) whose H equals `target`.
 template <bool TRACE>
 __device__ __forceinline__ void side_dp(int lx, int ly, int steps, int ge, int go, const int16_t* T, int16_t* prof,
-                                        const uint8_t* xb, const uint16_t* yo, int2* strip, uint32_t* tb, int& best,
+                                        const uint8_t* xb, const uint8_t* yo, int2* strip, uint32_t* tb, int& best,
                                         int& bpos, int row = 0, int target = 0, int* jf = nullptr) {
   const int lane = threadIdx.x;
   const int nu8 = steps >> 3;
@@ -352,28 +352,27 @@ __device__ __forceinline__ void side_dp(int lx, int ly, int steps, int ge, int g
       for (int yc = 0; yc < 21; ++yc) prof[yc * 64 + lane] = v[yc];
     }
     const uint8_t* pcol = (const uint8_t*)(prof + lane);
-    const uint16_t* ycol = yo + 64 - lane;  // the letter of this lane's column t - lane at step t
+    const uint8_t* ycol = yo + 64 - lane;  // the letter of this lane's column t - lane at step t
     int hm = kANeg, f = kANeg, hup = kANeg, eleft = kANeg, hmleft = kANeg;
     uint32_t* tbs = tb + (size_t)s * nu8 * 64 + lane;
     const int sbase = s << 16;
     const bool my_row = TRACE && s * 64 + lane + 1 == row;
-    // Only lane 0 takes its inputs from LDS (the others from the lane above),
-    // so only lane 0 reads them: a 64-lane broadcast would cost the LDS the
-    // bandwidth of 64 reads.
-    int4 s0 = make_int4(0, 0, 0, 0), s1 = s0, s2 = s0, s3 = s0;
+    // Only lane 0 uses the block's inputs from LDS (the others take theirs
+    // from the lane above), but every lane loads them: the registers are then
+    // fresh each block and the DPP shifts, whose lane 0 keeps the old value,
+    // write into them without a copy.  The broadcast costs LDS bandwidth the
+    // kernel has to spare (its bound is the latency of the per-step chain).
     for (int t8 = 0; t8 < steps; t8 += 8) {
-      if (lane == 0) {
-        const int4* sf = (const int4*)(strip + t8);
-        s0 = sf[0];
-        s1 = sf[1];
-        s2 = sf[2];
-        s3 = sf[3];
-      }
+      const int4* sf = (const int4*)(strip + t8);
+      const int4 s0 = sf[0], s1 = sf[1], s2 = sf[2], s3 = sf[3];
       const int fh[8] = {s0.x, s0.z, s1.x, s1.z, s2.x, s2.z, s3.x, s3.z};
       const int ff[8] = {s0.y, s0.w, s1.y, s1.w, s2.y, s2.w, s3.y, s3.w};
       int sc[8];
+      uint32_t yw[2];
+      __builtin_memcpy(yw, ycol + t8, 8);
 #pragma unroll
-      for (int k = 0; k < 8; ++k) sc[k] = *(const int16_t*)(pcol + ycol[t8 + k]);
+      for (int k = 0; k < 8; ++k)
+        sc[k] = *(const int16_t*)(pcol + (__builtin_amdgcn_ubfe(yw[k >> 2], 8 * (k & 3), 8) << 7));
       int oh[8], of[8];
       uint32_t acc = 0;
       int bmax = kANeg;
@@ -429,13 +428,13 @@ __device__ __forceinline__ void side_dp(int lx, int ly, int steps, int ge, int g
 // sentinel; the row above strip 0 is row 0, shifted: H'(0, 0) = 0 and H'(0, k)
 // = -(open + k ext) + k ext = -open, so hm(0, 0) = -open, hm(0, k) = -2 open,
 // F' = NEG, and NEG past ly.
-__device__ __forceinline__ void side_pad(int lx, int ly, int steps, int go, uint8_t* xb, uint16_t* yo,
+__device__ __forceinline__ void side_pad(int lx, int ly, int steps, int go, uint8_t* xb, uint8_t* yo,
                                          int2* strip) {
   const int lane = threadIdx.x;
   for (int k = lx + lane; k < lx + 64; k += 64) xb[k] = (uint8_t)kPadCode;
-  for (int k = ly + 1 + lane; k < steps; k += 64) yo[64 + k] = (uint16_t)(kPadCode * kYScale);
-  yo[lane] = (uint16_t)(kPadCode * kYScale);  // columns -64 .. -1
-  if (lane == 0) yo[64] = (uint16_t)(kPadCode * kYScale);
+  for (int k = ly + 1 + lane; k < steps; k += 64) yo[64 + k] = (uint8_t)kPadCode;
+  yo[lane] = (uint8_t)kPadCode;  // columns -64 .. -1
+  if (lane == 0) yo[64] = (uint8_t)kPadCode;
   for (int k = lane; k < steps; k += 64)
     strip[k] = make_int2(k == 0 ? -go : (k <= ly ? -2 * go : kANeg), kANeg);
   __syncthreads();
@@ -449,7 +448,7 @@ __device__ __forceinline__ void side_pad(int lx, int ly, int steps, int go, uint
 // the trace-back reads those.  Appends the side's pieces to P (count np).
 __device__ __forceinline__ SideStats align_side(const AlignArgs& A, const uint8_t* x, int lx, int dx,
                                                 const uint8_t* y, int ly, int dy, int dir, int p1, int p2, int owner,
-                                                const int16_t* T, int16_t* prof, uint8_t* xb, uint16_t* yo, int2* strip,
+                                                const int16_t* T, int16_t* prof, uint8_t* xb, uint8_t* yo, int2* strip,
                                                 uint32_t* walk, uint32_t* tb, Piece* P, int& np, int32_t* status) {
   const int lane = threadIdx.x;
   const int ge = A.gap_extend, go = A.gap_open;
@@ -457,7 +456,7 @@ __device__ __forceinline__ SideStats align_side(const AlignArgs& A, const uint8_
   if (lx == 0 || ly == 0) return st;
   const int steps = (ly + 64 + 7) & ~7;
   for (int k = lane; k < lx; k += 64) xb[k] = x[(int64_t)k * dx];
-  for (int k = lane; k < ly; k += 64) yo[65 + k] = (uint16_t)(y[(int64_t)k * dy] * kYScale);
+  for (int k = lane; k < ly; k += 64) yo[65 + k] = y[(int64_t)k * dy];
   side_pad(lx, ly, steps, go, xb, yo, strip);
   int best = 0, bpos = 0;  // bpos = (strip << 16) | (block start + 1); 0: cell (0, 0)
   side_dp<false>(lx, ly, steps, ge, go, T, prof, xb, yo, strip, tb, best, bpos);
@@ -548,7 +547,7 @@ __device__ __forceinline__ SideStats align_side(const AlignArgs& A, const uint8_
     if (state == 0) {
       const uint32_t src = nib & 3u;
       if (src == 0) {
-        const int xa = xb[i - 1], yc = yo[64 + j] / kYScale;
+        const int xa = xb[i - 1], yc = yo[64 + j];
         const int pa = dir > 0 ? p1 + i - 1 : p1 - i;
         const int pb = dir > 0 ? p2 + j - 1 : p2 - j;
         if (run_a < 0) {
@@ -604,8 +603,8 @@ __global__ __launch_bounds__(64) void k_align(AlignArgs A, const int16_t* __rest
   extern __shared__ __align__(16) uint8_t lds[];
   int16_t* prof = (int16_t*)lds;
   uint8_t* xb = (uint8_t*)(prof + 21 * 64);
-  uint16_t* yo = (uint16_t*)(xb + ((A.max_len1 + 64 + 15) & ~15));
-  int2* strip = (int2*)((uint8_t*)yo + ((2 * (A.max_len2 + 136) + 15) & ~15));
+  uint8_t* yo = xb + ((A.max_len1 + 64 + 15) & ~15);
+  int2* strip = (int2*)(yo + ((A.max_len2 + 136 + 15) & ~15));
   uint32_t* walk = (uint32_t*)strip;  // the trace-back runs after the DP of its side
   const int lane = threadIdx.x;
   __syncthreads();
