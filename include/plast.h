@@ -399,14 +399,15 @@ typedef struct {
   int32_t gap_open;          /* a gap of length k costs gap_open + k * gap_extend (11, 1) */
   int32_t gap_extend;
   int32_t max_len1;          /* longest sequence of bank a / bank b that a passing hit may lie in, */
-  int32_t max_len2;          /*   1..16384 each, with the LDS bound below */
+  int32_t max_len2;          /*   1..16384 each */
   int32_t n_waves;           /* alignment wavefronts (one workgroup each); 0 = as many as stay resident */
   int32_t max_pieces;        /* capacity of one sequence pair's piece list, >= 16 */
   const int8_t* matrix;      /* host, 20x20 row-major in code order; NULL = BLOSUM62 */
 } plast_align_params_t;
 
-/* Workspace for n_hits input hits; fails with PLAST_E_ARG when
- * max_len1 + 10 max_len2 (about) exceeds the 160 KiB of LDS a workgroup may use. */
+/* Workspace for n_hits input hits (the per-wavefront trace buffer grows with
+ * max_len1 x max_len2).  A workgroup takes about 9 max_len2 bytes of LDS
+ * (148 KiB at 16384, within the 160 KiB limit). */
 int plast_align_workspace_bytes(int64_t n_hits, const plast_align_params_t* p, size_t* bytes);
 /* d_hits / d_gscore / d_pass: n_hits records as written by plast_ungapped_extend
  * and plast_gapped_filter (only hits with d_pass != 0 are aligned).  Outputs:

@@ -128,19 +128,20 @@ AlignLayout align_layout(int64_t n, const plast_align_params_t& p, int64_t waves
   return L;
 }
 
-// LDS of one alignment workgroup: the strip's per-lane profile, x letters, y
-// letters by column (as profile offsets), and the row above the current strip
-// (with padding), whose space the trace-back window reuses once the DP is done.
-// The score table the profiles are built from stays in global memory (1.3 KB,
-// read once per strip), which keeps 11 workgroups per CU at 1000 letters.
+// LDS of one alignment workgroup: the strip's per-lane profile, y letters by
+// column, and the row above the current strip (with padding), whose space the
+// trace-back window reuses once the DP is done.  The score table the profiles
+// are built from and the x letters stay in global memory (read once per strip,
+// and once per step of the trace-back): the kernel is bound by the latency of
+// its per-step chain, so every workgroup more per CU counts (13 per CU at 1000
+// letters of bank b).
 size_t strip_bytes(int max_len2) {
   const size_t b = sizeof(int2) * ((size_t)max_len2 + 72);
   return b > sizeof(uint32_t) * kWalkDwords ? b : sizeof(uint32_t) * kWalkDwords;
 }
 
-size_t align_lds_bytes(int max_len1, int max_len2) {
+size_t align_lds_bytes(int max_len2) {
   size_t b = sizeof(int16_t) * 21 * 64;
-  b += align_up((size_t)max_len1 + 64, 16);
   b += align_up((size_t)max_len2 + 136, 16);   // y letters, 64 sentinels before column 0
   b += strip_bytes(max_len2);
   return b;
@@ -313,9 +314,8 @@ __device__ __forceinline__ int shr1(int old, int v) {
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // The strips of one DP over lx rows and the columns 0 .. steps - 64 (x letters
-// in xb; y letters by column in yo, each stored as its byte offset in the
-// profile, letter * kYScale; sentinels past both ends; the row above strip 0 in
-// strip[]).  The stored offset makes a lookup address one addition.
+// x[r * dx] in global memory, read once per strip for the profile; y letters by
+// column in yo, sentinels past both ends; the row above strip 0 in strip[]).
 //
 // Values are carried shifted by (i + j) * extend (H' = H + (i + j) ext, and
 // likewise E', F'), which removes the extension term from both gap recurrences:
@@ -335,7 +335,8 @@ __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlan
 // column of row `row` (per lane: -1 elsewhere) whose H equals `target`.
 template <bool TRACE>
 __device__ __forceinline__ void side_dp(int lx, int ly, int steps, int ge, int go, const int16_t* T, int16_t* prof,
-                                        const uint8_t* xb, const uint8_t* yo, int2* strip, uint32_t* tb, int& best,
+                                        const uint8_t* x, int dx, const uint8_t* yo, int2* strip, uint32_t* tb,
+                                        int& best,
                                         int& bpos, int row = 0, int target = 0, int* jf = nullptr) {
   const int lane = threadIdx.x;
   const int nu8 = steps >> 3;
@@ -344,7 +345,8 @@ __device__ __forceinline__ void side_dp(int lx, int ly, int steps, int ge, int g
     // this strip's profile: prof[y * 64 + lane] = T[x of the lane's row][y], so
     // that every lane's lookup falls in its own LDS bank
     {
-      const int16_t* trow = T + (int)xb[s * 64 + lane] * kTStride;
+      const int r = s * 64 + lane;
+      const int16_t* trow = T + (r < lx ? (int)x[(int64_t)r * dx] : kPadCode) * kTStride;
       int16_t v[21];
 #pragma unroll
       for (int yc = 0; yc < 21; ++yc) v[yc] = trow[yc];
@@ -372,7 +374,7 @@ __device__ __forceinline__ void side_dp(int lx, int ly, int steps, int ge, int g
       __builtin_memcpy(yw, ycol + t8, 8);
 #pragma unroll
       for (int k = 0; k < 8; ++k)
-        sc[k] = *(const int16_t*)(pcol + (__builtin_amdgcn_ubfe(yw[k >> 2], 8 * (k & 3), 8) << 7));
+        sc[k] = *(const int16_t*)(pcol + __builtin_amdgcn_ubfe(yw[k >> 2], 8 * (k & 3), 8) * kYScale);
       int oh[8], of[8];
       uint32_t acc = 0;
       int bmax = kANeg;
@@ -428,10 +430,8 @@ __device__ __forceinline__ void side_dp(int lx, int ly, int steps, int ge, int g
 // sentinel; the row above strip 0 is row 0, shifted: H'(0, 0) = 0 and H'(0, k)
 // = -(open + k ext) + k ext = -open, so hm(0, 0) = -open, hm(0, k) = -2 open,
 // F' = NEG, and NEG past ly.
-__device__ __forceinline__ void side_pad(int lx, int ly, int steps, int go, uint8_t* xb, uint8_t* yo,
-                                         int2* strip) {
+__device__ __forceinline__ void side_pad(int ly, int steps, int go, uint8_t* yo, int2* strip) {
   const int lane = threadIdx.x;
-  for (int k = lx + lane; k < lx + 64; k += 64) xb[k] = (uint8_t)kPadCode;
   for (int k = ly + 1 + lane; k < steps; k += 64) yo[64 + k] = (uint8_t)kPadCode;
   yo[lane] = (uint8_t)kPadCode;  // columns -64 .. -1
   if (lane == 0) yo[64] = (uint8_t)kPadCode;
@@ -448,18 +448,17 @@ __device__ __forceinline__ void side_pad(int lx, int ly, int steps, int go, uint
 // the trace-back reads those.  Appends the side's pieces to P (count np).
 __device__ __forceinline__ SideStats align_side(const AlignArgs& A, const uint8_t* x, int lx, int dx,
                                                 const uint8_t* y, int ly, int dy, int dir, int p1, int p2, int owner,
-                                                const int16_t* T, int16_t* prof, uint8_t* xb, uint8_t* yo, int2* strip,
+                                                const int16_t* T, int16_t* prof, uint8_t* yo, int2* strip,
                                                 uint32_t* walk, uint32_t* tb, Piece* P, int& np, int32_t* status) {
   const int lane = threadIdx.x;
   const int ge = A.gap_extend, go = A.gap_open;
   SideStats st = {0, 0, 0, 0, 0, 0, 0};
   if (lx == 0 || ly == 0) return st;
   const int steps = (ly + 64 + 7) & ~7;
-  for (int k = lane; k < lx; k += 64) xb[k] = x[(int64_t)k * dx];
   for (int k = lane; k < ly; k += 64) yo[65 + k] = y[(int64_t)k * dy];
-  side_pad(lx, ly, steps, go, xb, yo, strip);
+  side_pad(ly, steps, go, yo, strip);
   int best = 0, bpos = 0;  // bpos = (strip << 16) | (block start + 1); 0: cell (0, 0)
-  side_dp<false>(lx, ly, steps, ge, go, T, prof, xb, yo, strip, tb, best, bpos);
+  side_dp<false>(lx, ly, steps, ge, go, T, prof, x, dx, yo, strip, tb, best, bpos);
 
   // best over the wavefront: largest value, then first row, then first block
   // (a row belongs to one lane, so the block decides only within a row)
@@ -490,9 +489,9 @@ __device__ __forceinline__ SideStats align_side(const AlignArgs& A, const uint8_
     const int r_end = (st.i_end - 1) & 63, t8 = (bpos & 0xffff) - 64;
     const int j_hi = min(ly, t8 + 7 - r_end);
     const int steps2 = (j_hi + 64 + 7) & ~7;
-    side_pad(st.i_end, j_hi, steps2, go, xb, yo, strip);
+    side_pad(j_hi, steps2, go, yo, strip);
     int unused0 = 0, unused1 = 0, jf = -1;
-    side_dp<true>(st.i_end, j_hi, steps2, ge, go, T, prof, xb, yo, strip, tb, unused0, unused1, st.i_end, best,
+    side_dp<true>(st.i_end, j_hi, steps2, ge, go, T, prof, x, dx, yo, strip, tb, unused0, unused1, st.i_end, best,
                   &jf);
     nu8 = steps2 >> 3;
     st.j_end = __shfl(jf, r_end);
@@ -547,7 +546,7 @@ __device__ __forceinline__ SideStats align_side(const AlignArgs& A, const uint8_
     if (state == 0) {
       const uint32_t src = nib & 3u;
       if (src == 0) {
-        const int xa = xb[i - 1], yc = yo[64 + j];
+        const int xa = x[(int64_t)(i - 1) * dx], yc = yo[64 + j];
         const int pa = dir > 0 ? p1 + i - 1 : p1 - i;
         const int pb = dir > 0 ? p2 + j - 1 : p2 - j;
         if (run_a < 0) {
@@ -595,15 +594,15 @@ __global__ __launch_bounds__(64) void k_align_table(AlignArgs A, int16_t* __rest
   }
 }
 
-__global__ __launch_bounds__(64) void k_align(AlignArgs A, const int16_t* __restrict__ T, const plast_hit_t* hits,
-                                              const int32_t* hidx, const int32_t* perm, const uint64_t* khi,
-                                              const int32_t* heads, AlignHeader* hdr, uint32_t* tb_all,
-                                              size_t tb_words, Piece* pieces_all, plast_alignment_t* out,
-                                              int32_t* cover) {
+// At most 128 VGPRs (4 wavefronts per SIMD), so that the LDS, not the
+// registers, sets the number of resident workgroups.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_align(
+    AlignArgs A, const int16_t* __restrict__ T, const plast_hit_t* hits, const int32_t* hidx, const int32_t* perm,
+    const uint64_t* khi, const int32_t* heads, AlignHeader* hdr, uint32_t* tb_all, size_t tb_words, Piece* pieces_all,
+    plast_alignment_t* out, int32_t* cover) {
   extern __shared__ __align__(16) uint8_t lds[];
   int16_t* prof = (int16_t*)lds;
-  uint8_t* xb = (uint8_t*)(prof + 21 * 64);
-  uint8_t* yo = xb + ((A.max_len1 + 64 + 15) & ~15);
+  uint8_t* yo = (uint8_t*)(prof + 21 * 64);
   int2* strip = (int2*)(yo + ((A.max_len2 + 136 + 15) & ~15));
   uint32_t* walk = (uint32_t*)strip;  // the trace-back runs after the DP of its side
   const int lane = threadIdx.x;
@@ -654,9 +653,9 @@ __global__ __launch_bounds__(64) void k_align(AlignArgs A, const int16_t* __rest
       const uint8_t* a = A.a_codes + A.a_start[s1];
       const uint8_t* b = A.b_codes + A.b_start[s2];
       const int la = seq_len(A.a_start, s1), lb = seq_len(A.b_start, s2);
-      const SideStats R = align_side(A, a + p1, la - p1, 1, b + p2, lb - p2, 1, +1, p1, p2, h, T, prof, xb, yo, strip,
+      const SideStats R = align_side(A, a + p1, la - p1, 1, b + p2, lb - p2, 1, +1, p1, p2, h, T, prof, yo, strip,
                                      walk, tb, P, np, &hdr->status);
-      const SideStats L = align_side(A, a + p1 - 1, p1, -1, b + p2 - 1, p2, -1, -1, p1, p2, h, T, prof, xb, yo, strip,
+      const SideStats L = align_side(A, a + p1 - 1, p1, -1, b + p2 - 1, p2, -1, -1, p1, p2, h, T, prof, yo, strip,
                                      walk, tb, P, np, &hdr->status);
       if (lane == 0) {
         const unsigned long long o = atomicAdd(&hdr->n_out, 1ull);
@@ -684,9 +683,9 @@ __global__ __launch_bounds__(64) void k_align(AlignArgs A, const int16_t* __rest
 }  // namespace
 
 int align_default_waves(const plast_align_params_t& p, int64_t* waves) {
-  const size_t lds = align_lds_bytes(p.max_len1, p.max_len2);
-  if (lds > kMaxLds) return set_error(PLAST_E_ARG, "max_len1=%d, max_len2=%d need %zu bytes of LDS (limit %zu)",
-                                      p.max_len1, p.max_len2, lds, kMaxLds);
+  const size_t lds = align_lds_bytes(p.max_len2);
+  if (lds > kMaxLds)  // not reached for max_len2 <= 16384; kept against a change of the layout
+    return set_error(PLAST_E_ARG, "max_len2=%d needs %zu bytes of LDS (limit %zu)", p.max_len2, lds, kMaxLds);
   if (p.n_waves > 0) {
     *waves = p.n_waves;
     return PLAST_OK;
@@ -781,7 +780,7 @@ int align_impl(const plast_index_t* a, const plast_index_t* b, const plast_hit_t
     exclusive_scan_i32(pcount, (m + 63) / 64, &hdr->group_total, ws + L.scan_tmp, s);
     hipLaunchKernelGGL(k_align_ngroups, dim3(1), dim3(64), 0, s, hdr);
     hipLaunchKernelGGL(k_align_heads, dim3(mb), dim3(256), 0, s, perm[cur], khi, hdr, (const int32_t*)pcount, heads);
-    const size_t lds = align_lds_bytes(p->max_len1, p->max_len2);
+    const size_t lds = align_lds_bytes(p->max_len2);
     PLAST_HIP(hipFuncSetAttribute((const void*)k_align, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     int16_t* tbl = (int16_t*)(ws + L.tbl);
     hipLaunchKernelGGL(k_align_table, dim3(1), dim3(64), 0, s, A, tbl);

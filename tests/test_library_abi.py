@@ -245,10 +245,12 @@ int main(void) {
     assert lib.plast_align_workspace_bytes(1000, ctypes.byref(ok), ctypes.byref(sz)) == binding.OK
     # per wavefront: 16 strips x 133 dwords of 8 steps x 64 lanes of trace, 4096 pieces of 16 bytes
     assert sz.value >= 64 * (16 * 133 * 64 * 4 + 4096 * 16)
+    # the longest sequences allowed still fit the LDS of one workgroup
+    big = binding.AlignParams(11, 1, 16384, 16384, 64, 4096, None)
+    assert lib.plast_align_workspace_bytes(10, ctypes.byref(big), ctypes.byref(sz)) == binding.OK
     for bad in (binding.AlignParams(11, 0, 1000, 1000, 64, 4096, None),        # extend < 1
                 binding.AlignParams(11, 1, 0, 1000, 64, 4096, None),           # max_len1 < 1
                 binding.AlignParams(11, 1, 1000, 20000, 64, 4096, None),       # max_len2 > 16384
-                binding.AlignParams(11, 1, 16384, 16384, 64, 4096, None),      # LDS bound
                 binding.AlignParams(11, 1, 1000, 1000, 64, 8, None)):          # max_pieces < 16
         assert lib.plast_align_workspace_bytes(1000, ctypes.byref(bad), ctypes.byref(sz)) == binding.E_ARG
     assert lib.plast_align_workspace_bytes(-1, ctypes.byref(ok), ctypes.byref(sz)) == binding.E_ARG
