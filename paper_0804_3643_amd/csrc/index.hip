@@ -3,17 +3,19 @@
 //
 // The sort is a two-pass LSD radix sort on the 14-bit key: the low 7 bits
 // (128 buckets), then the high 7 bits (69 buckets).  Each pass cuts its input
-// into tiles of kIxTile elements, one wavefront each: a counting kernel writes
-// the tile's bucket histogram bucket-major, an exclusive scan over (bucket,
-// tile) gives every tile its first slot in each bucket, and a scattering
-// kernel walks the tile in order, ranking equal buckets among the 64 lanes of
-// a round with one ballot per digit bit.  Both passes are stable, so the order
-// inside a key is the position order: ascending (sequence, position),
-// independent of scheduling.  A tile's writes to one bucket are consecutive
-// slots, so they fill whole cache lines while the tile runs (a one-pass
-// counting sort over 8800 keys wrote one 4-byte entry per line).  Pass 1 reads
-// the codes and writes (position, sequence, key) of every word; pass 2 writes
-// occ, occ_seq and the sorted keys, from which key_off is read off.
+// into tiles of kIxTile elements, one wavefront each (four per workgroup): a
+// counting kernel writes the tile's bucket histogram bucket-major, an
+// exclusive scan over (bucket, tile) gives every tile its first slot in each
+// bucket, and a scattering kernel ranks the tile's elements in order within
+// their bucket (one ballot per digit bit over the 64 lanes of a round) into the
+// tile's own bucket order in LDS, then writes the staged tile out bucket by
+// bucket, consecutive lanes on consecutive slots.  Both passes are stable, so
+// the order inside a key is the position order: ascending (sequence,
+// position), independent of scheduling.  Pass 1 reads the codes (staged in
+// LDS) and writes one 64-bit entry per word (position, key, and the sequence
+// as an offset from the first sequence of the position's tile, which the
+// layout check records per tile); pass 2 writes occ, occ_seq and the sorted
+// keys, from which key_off is read off.
 #include "plast_internal.h"
 
 namespace plast {
