@@ -647,6 +647,7 @@ def main():
     n_hits = int(hits.shape[0])
     n_pass = int(pbuf[:n_hits].sum().item())
     batched_kernel_ms = float(np.mean(stage_ms["ungapped_ms"]))
+    step_dev = np.sum([stage_ms[k] for k in ("index_ms", "plan_ms", "ungapped_ms", "gapped_ms")], axis=0)
     # graph replay == eager calls: same counts, same hit multiset, same gapped pass count
     gh, gg, gp = pipe.outputs(res["n_hits"])
     kg, sg = pair_keys_device(torch, gh)
@@ -761,6 +762,9 @@ def main():
         "autotune": dict(tune_report, wall_s=tune_s) if tune_report is not None else None,
         "n_ext": n_ext, "n_hits": n_hits, "n_gapped_pass": n_pass,
         "stages_device_ms": {k: float(np.mean(v)) for k, v in stage_ms.items()},
+        # per eager step: the sum of the four stages' device times (HIP events in the library)
+        "step_device_ms": {"median": float(np.median(step_dev)), "min": float(np.min(step_dev)),
+                           "max": float(np.max(step_dev)), "steps": len(step_dev)},
         "ungapped": {
             "batched_kernel_ms": batched_kernel_ms,
             "batched_ext_per_s": n_ext / (batched_kernel_ms * 1e-3),
