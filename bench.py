@@ -556,7 +556,7 @@ def main():
                     help="skip stage 3.2 (full gapped alignment of the passing hits, reported apart from the step)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the hot path is single-GPU); "
+        print("bench.py: the benchmark runs on one GPU only (the hot path is single-GPU); "
               "--gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
