@@ -191,12 +191,7 @@ constexpr uint32_t kXRowBytes = 4 * kPairRow;
 static_assert(kPairDwords * 4 < 65536, "table offsets must fit 16 bits");
 
 __device__ __forceinline__ gh2 gmax3(gh2 a, gh2 b, gh2 c) {
-  uint32_t r;
-  asm("v_pk_maximum3_f16 %0, %1, %2, %3"
-      : "=v"(r)
-      : "v"(__builtin_bit_cast(uint32_t, a)), "v"(__builtin_bit_cast(uint32_t, b)),
-        "v"(__builtin_bit_cast(uint32_t, c)));
-  return __builtin_bit_cast(gh2, r);
+  return __builtin_elementwise_maximum(__builtin_elementwise_maximum(a, b), c);
 }
 __device__ __forceinline__ gh2 gmax(gh2 a, gh2 b) { return __builtin_elementwise_maximum(a, b); }
 
