@@ -123,14 +123,8 @@ __device__ __forceinline__ vec2<F16> vmax(vec2<F16> a, vec2<F16> b) {
 template <bool F16>
 __device__ __forceinline__ vec2<F16> vmax3(vec2<F16> a, vec2<F16> b, vec2<F16> c) {
   if constexpr (F16) {
-    // One v_pk_maximum3_f16 (register operands only).  Written out so that the
-    // compiler does not re-associate a chain of maxima into more instructions.
-    uint32_t r;
-    asm("v_pk_maximum3_f16 %0, %1, %2, %3"
-        : "=v"(r)
-        : "v"(__builtin_bit_cast(uint32_t, a)), "v"(__builtin_bit_cast(uint32_t, b)),
-          "v"(__builtin_bit_cast(uint32_t, c)));
-    return __builtin_bit_cast(vec2<F16>, r);
+    // the compiler fuses the nested maxima into one v_pk_maximum3_f16
+    return __builtin_elementwise_maximum(__builtin_elementwise_maximum(a, b), c);
   } else {
     return __builtin_elementwise_max(a, __builtin_elementwise_max(b, c));
   }
