@@ -1,0 +1,68 @@
+"""CPU checks of the benchmark's report helpers on configuration 0, fed with the
+oracle's hits (the helpers take tensors on any device): recall of the planted
+homologs by identity bin, the key-bucket statistics, and the machine record."""
+import os
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+from oracle import coracle as C  # noqa: E402
+from paper_0804_3643_amd import params  # noqa: E402
+
+
+class _Index:
+    """Stands in for a device index: only key_off is read."""
+
+    def __init__(self, key_off):
+        self._k = torch.from_numpy(np.asarray(key_off, dtype=np.int64))
+
+    def key_off(self):
+        return self._k
+
+
+@pytest.fixture(scope="module")
+def cfg0_hits(cfg0):
+    hits, _ = C.ungapped_hits(cfg0.bank1, cfg0.bank2, params.S1)
+    g = C.gapped_scores(cfg0.bank1, cfg0.bank2, hits)
+    return torch.from_numpy(hits.astype(np.int32)), torch.from_numpy((g >= params.S2).astype(np.uint8))
+
+
+def test_plant_recall_counts_and_bins(cfg0, cfg0_hits):
+    h, p = cfg0_hits
+    r = bench.plant_recall(torch, np, cfg0, h, p)
+    assert r["pairs"] == len(cfg0.plants) == 20
+    assert sum(b["pairs"] for b in r["by_realised_identity"]) == r["pairs"]
+    assert sum(b["with_hit"] for b in r["by_realised_identity"]) == r["with_hit"]
+    assert r["passing_gapped"] <= r["with_hit"] <= r["pairs"]
+    assert r["with_hit"] >= 19  # planted pairs at 40% identity share seeds
+    # with no hit at all nothing is found
+    none = bench.plant_recall(torch, np, cfg0, h[:0], p[:0])
+    assert none["with_hit"] == 0 and none["passing_gapped"] == 0
+
+
+def test_key_stats_match_the_index(cfg0):
+    k1, k2 = C.build_index(cfg0.bank1)[0], C.build_index(cfg0.bank2)[0]
+    ks = bench.key_stats(torch, np, _Index(k1), _Index(k2))
+    n2 = np.diff(k2)
+    assert ks["bank2_nonempty_keys"] == int((n2 > 0).sum())
+    assert ks["bank2_max"] == int(n2.max()) and ks["bank2_min_nonempty"] == int(n2[n2 > 0].min())
+    assert sum(ks["bank2_log2_histogram"].values()) == ks["bank2_nonempty_keys"]
+    work = np.diff(k1).astype(np.float64) * n2
+    assert abs(ks["top16_work_share"] - np.sort(work)[-16:].sum() / work.sum()) < 1e-12
+
+
+def test_machine_info_runs_anywhere():
+    m = bench.machine_info()
+    assert m["host_logical_cpus"] >= 1
+    assert "gpu_sclk_levels" in m
+
+
+def test_published_peaks_cover_every_probe():
+    from paper_0804_3643_amd import binding
+    assert set(bench.PUBLISHED_PEAKS) == set(binding.PROBES)
