@@ -403,6 +403,43 @@ def run_serving(args):
     print(json.dumps(out), flush=True)
 
 
+def translated_oracle_checks(B, np, synth, params, w, dnas, res, h, plastx):
+    """CPU-baseline leg of the translated runs (after the timed region): the
+    oracle's six-frame translation of 4 sampled DNA sequences per bank and its
+    hits on 24 sampled keys, against the GPU's."""
+    from oracle import coracle as C
+    from oracle import plast_oracle as O
+
+    rng = np.random.default_rng(3)
+    tr_equal = True
+    frag_banks = []
+    for d_bank, (c_t, s_t, f_t) in zip(dnas, res):
+        fr = f_t.cpu().numpy()
+        st_h = s_t.cpu().numpy()
+        codes_h = c_t.cpu().numpy()
+        for d in rng.choice(d_bank.n_seqs, size=min(4, d_bank.n_seqs), replace=False):
+            frags, table = O.translate6(d_bank.seq(int(d)), np.array([0, int(d_bank.start[d + 1] - d_bank.start[d])]))
+            sel = np.nonzero(fr[:, 0] == d)[0]
+            got = [codes_h[st_h[j]:st_h[j + 1] - B.PAD_LEN] for j in sel]
+            tr_equal &= len(got) == len(frags) and all(np.array_equal(a, b) for a, b in zip(got, frags))
+            tr_equal &= bool(np.array_equal(fr[sel, 1:], table[:, 1:]))
+        frag_banks.append(synth.Bank(codes_h, st_h))
+    bank_a = frag_banks[0] if plastx else w.bank1
+    bank_b = frag_banks[-1]
+    i1, i2 = C.build_index(bank_a), C.build_index(bank_b)
+    work = np.diff(i1[0]) * np.diff(i2[0])
+    keys = np.sort(rng.choice(np.nonzero(work)[0], size=24, replace=False)).astype(np.int32)
+    ref, _ = C.ungapped_hits(bank_a, bank_b, params.S1, keys=keys, idx1=i1, idx2=i2)
+    hh = h.cpu().numpy().astype(np.int64)
+    c1 = bank_a.codes
+    q = bank_a.seq_start[hh[:, 0]] + hh[:, 1]
+    hk = O.seed_key(c1[q].astype(np.int64), c1[q + 1].astype(np.int64), c1[q + 2].astype(np.int64),
+                    c1[q + 3].astype(np.int64))
+    hits_equal = bool(np.array_equal(O.canonical(hh[np.isin(hk, keys)]), ref))
+    return {"translation_equals_oracle_on_sampled_dna": bool(tr_equal),
+            "hits_equal_oracle_on_24_sampled_keys": hits_equal}
+
+
 def run_translated(args, plastx=False):
     """TPLAST-N (configuration 3: 5000 proteins against 2000 DNA sequences of
     50-200 kb) or PLAST-X (200 against 1000 DNA sequences of 20-50 kb, both
@@ -412,8 +449,6 @@ def run_translated(args, plastx=False):
     import numpy as np
     import torch
 
-    from oracle import coracle as C
-    from oracle import plast_oracle as O
     from paper_0804_3643_amd import binding as B
     from paper_0804_3643_amd import params, synth
 
@@ -482,35 +517,11 @@ def run_translated(args, plastx=False):
     stage = np.mean(np.array(stage), axis=0)
     n_hits = int(h.shape[0])
     n_pass = int(pbuf[:n_hits].sum().item())
-    # bit-exact checks: translation of sampled DNA sequences, and hits of sampled keys, against the oracle
-    log("checks against the oracle")
-    rng = np.random.default_rng(3)
-    tr_equal = True
-    frag_banks, frag_tables = [], []
-    for d_bank, (c_t, s_t, f_t) in zip(dnas, res):
-        fr = f_t.cpu().numpy()
-        st_h = s_t.cpu().numpy()
-        codes_h = c_t.cpu().numpy()
-        for d in rng.choice(d_bank.n_seqs, size=min(4, d_bank.n_seqs), replace=False):
-            frags, table = O.translate6(d_bank.seq(int(d)), np.array([0, int(d_bank.start[d + 1] - d_bank.start[d])]))
-            sel = np.nonzero(fr[:, 0] == d)[0]
-            got = [codes_h[st_h[j]:st_h[j + 1] - B.PAD_LEN] for j in sel]
-            tr_equal &= len(got) == len(frags) and all(np.array_equal(a, b) for a, b in zip(got, frags))
-            tr_equal &= bool(np.array_equal(fr[sel, 1:], table[:, 1:]))
-        frag_banks.append(synth.Bank(codes_h, st_h))
-        frag_tables.append(fr)
-    bank_a = frag_banks[0] if plastx else w.bank1
-    bank_b = frag_banks[-1]
-    i1, i2 = C.build_index(bank_a), C.build_index(bank_b)
-    work = np.diff(i1[0]) * np.diff(i2[0])
-    keys = np.sort(rng.choice(np.nonzero(work)[0], size=24, replace=False)).astype(np.int32)
-    ref, _ = C.ungapped_hits(bank_a, bank_b, params.S1, keys=keys, idx1=i1, idx2=i2)
-    hh = h.cpu().numpy().astype(np.int64)
-    c1 = bank_a.codes
-    q = bank_a.seq_start[hh[:, 0]] + hh[:, 1]
-    hk = O.seed_key(c1[q].astype(np.int64), c1[q + 1].astype(np.int64), c1[q + 2].astype(np.int64),
-                    c1[q + 3].astype(np.int64))
-    hits_equal = bool(np.array_equal(O.canonical(hh[np.isin(hk, keys)]), ref))
+    frag_tables = [f_t.cpu().numpy() for (_c, _s, f_t) in res]
+    checks = None
+    if not args.no_cpu_baseline:
+        log("checks against the oracle")
+        checks = translated_oracle_checks(B, np, synth, params, w, dnas, res, h, plastx)
     name = "PLAST-X" if plastx else "TPLAST-N"
     out = {
         "metric": "%s: ungapped extensions/s, whole step including the six-frame translation%s"
@@ -521,8 +532,7 @@ def run_translated(args, plastx=False):
         "n_ext": n_ext, "n_hits": n_hits, "n_gapped_pass": n_pass,
         "n_fragments": [int(f.shape[0]) for f in frag_tables],
         "tuning": tuning.as_dict() if tuning is not None else None,
-        "bit_exact": {"translation_equals_oracle_on_sampled_dna": bool(tr_equal),
-                      "hits_equal_oracle_on_24_sampled_keys": hits_equal},
+        "cpu_baseline": {"kind": "oracle", "checks": checks} if checks is not None else None,
         "config": {"workload": w.description, "dna_nt": [int(d.codes.shape[0]) for d in dnas]},
     }
     print(json.dumps(out, default=float), flush=True)
