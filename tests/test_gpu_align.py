@@ -193,3 +193,23 @@ def test_align_many_gaps_piece_overflow_and_bad_hits(B, cfg0):
     with pytest.raises(B.PlastError) as e:
         B.align(ia0, ib0, bad, g0, p1)
     assert e.value.code == B.E_ARG
+
+
+def test_align_long_pair_one_workgroup_per_cu(B):
+    """A 10,000-letter sequence against a copy with 20% substitutions and a
+    3-letter deletion: the LDS of one workgroup grows with the longest sequence
+    of bank b (about 93 KB here, one workgroup per CU) and each side spans up to
+    157 strips; one alignment covers every hit.  Records and covers equal the
+    oracle's (8 wavefronts keep the trace workspace near 400 MB)."""
+    rng = np.random.default_rng(41)
+    a = rng.integers(0, 20, 10000)
+    b = a.copy()
+    b[rng.choice(10000, 2000, replace=False)] = rng.integers(0, 20, 2000)
+    b = np.concatenate([b[:6000], b[6003:]])
+    bank1, bank2 = _bank([a, rng.integers(0, 20, 300)]), _bank([b, a[:300]])
+    _say("align a 10000-letter pair")
+    ia, ib, hits, gs, ps = _stage31(B, bank1, bank2)
+    rec, _ = _assert_parity(B, bank1, bank2, ia, ib, hits, gs, ps, n_waves=8)
+    F = {k: i for i, k in enumerate(O.ALIGN_FIELDS)}
+    long = rec[(rec[:, F["seq1"]] == 0) & (rec[:, F["seq2"]] == 0)]
+    assert len(long) >= 1 and (long[:, F["end1"]] - long[:, F["start1"]] > 9000).any()
