@@ -12,8 +12,9 @@
 // fragments and amino acids; an exclusive scan over the streams gives each
 // stream its first fragment and first residue; pass 2 writes every amino acid
 // to 20 (fragment + 1) + (residues before it), since the layout is a separator
-// run, fragment 0, a run, fragment 1, ... .  Inside a stream, fragment starts
-// and amino acids are ranked with a workgroup scan per 256-codon chunk.
+// run, fragment 0, a run, fragment 1, ... .  Pass 1 only sums each thread's
+// counts; inside a stream, pass 2 ranks fragment starts and amino acids with a
+// workgroup scan per 1024-codon chunk (four consecutive codons per thread).
 #include "plast_internal.h"
 
 namespace plast {
@@ -113,13 +114,26 @@ __device__ __forceinline__ int block_incl_sum(int v, int* wtot, int* total) {
   return before + incl;
 }
 
+// Workgroup-wide sum (all threads call it; contains barriers).
+__device__ __forceinline__ long long block_sum64(long long v, long long* wsum) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+  __syncthreads();  // wsum may still be read by a previous call
+  if (__lane_id() == 0) wsum[threadIdx.x >> 6] = v;
+  __syncthreads();
+  long long t = 0;
+#pragma unroll
+  for (int k = 0; k < kTrThreads / 64; ++k) t += wsum[k];
+  return t;
+}
+
 // Pass 1: per stream, fragments and amino acids; frame-0 workgroups also check
 // that every nucleotide code is 0..3.
 __global__ __launch_bounds__(kTrThreads) void k_tr_count(const uint8_t* __restrict__ dna,
                                                          const int64_t* __restrict__ dna_start, int32_t n_dna,
                                                          int64_t n_nt, CodonTable T, int64_t* __restrict__ nfrag,
                                                          int64_t* __restrict__ nres, int32_t* __restrict__ err) {
-  __shared__ int wtot[kTrThreads / 64];
+  __shared__ long long wsum[kTrThreads / 64];
   const int s = blockIdx.x;
   const Stream S = stream_of(dna_start, n_dna, n_nt, s, err);
   if (S.frame == 0) {
@@ -127,17 +141,15 @@ __global__ __launch_bounds__(kTrThreads) void k_tr_count(const uint8_t* __restri
     for (int64_t p = threadIdx.x; p < S.len; p += kTrThreads) bad |= dna[S.start + p] > 3;
     if (bad) atomicOr(err, 2);
   }
-  int64_t frags = 0, res = 0;  // identical in every thread after each chunk
-  for (int64_t base = 0; base < S.n_codons; base += kTrThreads) {
-    const int64_t i = base + threadIdx.x;
-    const bool live = i < S.n_codons;
-    const bool aa_ok = live && codon_aa(dna, S, i, T) != kStop;
-    const bool first = aa_ok && (i == 0 || codon_aa(dna, S, i - 1, T) == kStop);
-    int tot = 0;
-    block_incl_sum((first ? 1 << 16 : 0) | (aa_ok ? 1 : 0), wtot, &tot);
-    frags += tot >> 16;
-    res += tot & 0xffff;
+  // each thread counts its own codons; one sum over the workgroup at the end
+  long long frags = 0, res = 0;
+  for (int64_t i = threadIdx.x; i < S.n_codons; i += kTrThreads) {
+    const bool aa_ok = codon_aa(dna, S, i, T) != kStop;
+    frags += (aa_ok && (i == 0 || codon_aa(dna, S, i - 1, T) == kStop)) ? 1 : 0;
+    res += aa_ok ? 1 : 0;
   }
+  frags = block_sum64(frags, wsum);
+  res = block_sum64(res, wsum);
   if (threadIdx.x == 0) {
     nfrag[s] = frags;
     nres[s] = res;
@@ -205,28 +217,45 @@ __global__ __launch_bounds__(kTrThreads) void k_tr_write(const uint8_t* __restri
   const int s = blockIdx.x;
   const Stream S = stream_of(dna_start, n_dna, n_nt, s, err);
   int64_t cf = frag0[s], cr = res0[s];  // fragments and residues before this chunk
-  for (int64_t base = 0; base < S.n_codons; base += kTrThreads) {
-    const int64_t i = base + threadIdx.x;
-    const bool live = i < S.n_codons;
-    const uint8_t aa = live ? codon_aa(dna, S, i, T) : kStop;
-    const bool aa_ok = aa != kStop;
-    const bool first = aa_ok && (i == 0 || codon_aa(dna, S, i - 1, T) == kStop);
-    const int mine = (first ? 1 << 16 : 0) | (aa_ok ? 1 : 0);
+  // Chunks of 4 * kTrThreads codons, four consecutive codons per thread: the
+  // workgroup ranks thread totals (each at most 4, so a chunk's totals fit the
+  // 16-bit halves of the scan), then every thread walks its own codons.
+  constexpr int kPer = 4;
+  for (int64_t base = 0; base < S.n_codons; base += kPer * kTrThreads) {
+    const int64_t i0 = base + kPer * threadIdx.x;
+    uint8_t aa[kPer];
+    bool first[kPer];
+    uint8_t prev = (i0 == 0 || i0 > S.n_codons) ? kStop : codon_aa(dna, S, i0 - 1, T);
+    int nf = 0, nr = 0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int64_t i = i0 + k;
+      aa[k] = i < S.n_codons ? codon_aa(dna, S, i, T) : kStop;
+      first[k] = aa[k] != kStop && prev == kStop;
+      prev = aa[k];
+      nf += first[k] ? 1 : 0;
+      nr += aa[k] != kStop ? 1 : 0;
+    }
+    const int mine = (nf << 16) | nr;
     int tot = 0;
-    const int incl = block_incl_sum(mine, wtot, &tot);
-    if (aa_ok) {
-      const int64_t j = cf + (incl >> 16) - 1;                 // this codon's fragment
-      const int64_t r = cr + ((incl - mine) & 0xffff);         // residues before it
+    const int excl = block_incl_sum(mine, wtot, &tot) - mine;
+    int64_t j = cf + (excl >> 16) - 1;  // fragment of the last start before this thread's codons
+    int64_t r = cr + (excl & 0xffff);   // residues before them
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      if (aa[k] == kStop) continue;
+      if (first[k]) ++j;
       const int64_t pos = (int64_t)kPadLen * (j + 1) + r;
-      if (j < n_frags && pos < n_padded) {
-        codes[pos] = aa;
-        if (first) {
+      if (j >= 0 && j < n_frags && pos < n_padded) {
+        codes[pos] = aa[k];
+        if (first[k]) {
           seq_start[j] = pos;
           frag[3 * j] = s / 6;
           frag[3 * j + 1] = S.frame;
-          frag[3 * j + 2] = (int32_t)i;
+          frag[3 * j + 2] = (int32_t)(i0 + k);
         }
       }
+      ++r;
     }
     cf += tot >> 16;
     cr += tot & 0xffff;
