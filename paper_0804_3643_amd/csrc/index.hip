@@ -301,13 +301,43 @@ __global__ __launch_bounds__(64 * kIxWaves) void k_ix_scatter1(
   wave_sync();
   int s_cur = s0;
   const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
-  for (int off = 0; beg + off < end; off += 64) {
-    const int64_t q = beg + off + lane;
-    const int key = word_key_lds(cl, off + lane, q < end, sc);
-    const int s = seq_of<kTileStarts>(st, s_cur, s0, q, lane);
-    const int l = rank_in_tile(key & (kD0 - 1), key >= 0, cur, below);
-    if (key >= 0 && (unsigned)l < (unsigned)kIxTile) stage[l] = (uint32_t)key | ((uint32_t)(off + lane) << 14) | ((uint32_t)min(s - s0, 127) << 25);
-    s_cur = __shfl(s, 63);
+  auto entry = [&](int key, int off, int s) {
+    return (uint32_t)key | ((uint32_t)(off + lane) << 14) | ((uint32_t)min(s - s0, 127) << 25);
+  };
+  if (nt <= kIxTile / 2) {
+    // Sparse tile (translated fragments: most positions are separators): the
+    // words are first compacted in position order into the upper half of the
+    // stage, then ranked from there into the lower half, ceil(nt / 64) rounds
+    // instead of one per 64 positions; the halves do not overlap.
+    uint32_t* comp = stage + kIxTile / 2;
+    int nw = 0;
+    for (int off = 0; beg + off < end; off += 64) {
+      const int64_t q = beg + off + lane;
+      const int key = word_key_lds(cl, off + lane, q < end, sc);
+      const int s = seq_of<kTileStarts>(st, s_cur, s0, q, lane);
+      const uint64_t w = __ballot(key >= 0);
+      const int at = nw + __popcll(w & below);
+      if (key >= 0 && at < kIxTile / 2) comp[at] = entry(key, off, s);
+      nw += __popcll(w);
+      s_cur = __shfl(s, 63);
+    }
+    wave_sync();
+    nw = min(nw, kIxTile / 2);
+    for (int c = 0; c < nw; c += 64) {
+      const bool valid = c + lane < nw;
+      const uint32_t e = valid ? comp[c + lane] : 0u;
+      const int l = rank_in_tile((int)(e & (kD0 - 1)), valid, cur, below);
+      if (valid && (unsigned)l < (unsigned)(kIxTile / 2)) stage[l] = e;
+    }
+  } else {
+    for (int off = 0; beg + off < end; off += 64) {
+      const int64_t q = beg + off + lane;
+      const int key = word_key_lds(cl, off + lane, q < end, sc);
+      const int s = seq_of<kTileStarts>(st, s_cur, s0, q, lane);
+      const int l = rank_in_tile(key & (kD0 - 1), key >= 0, cur, below);
+      if (key >= 0 && (unsigned)l < (unsigned)kIxTile) stage[l] = entry(key, off, s);
+      s_cur = __shfl(s, 63);
+    }
   }
   wave_sync();
   for (int l = lane; l < min(nt, kIxTile); l += 64) {
