@@ -12,7 +12,8 @@
  *
  * Conventions shared by every entry point
  *   - Device pointers ("d_") are HIP device memory owned by the caller; the
- *     library never allocates, frees or retains device memory.  Host pointers
+ *     library never allocates, frees or retains device memory (apart from the
+ *     fixed static array of plast_ungapped_extend_noalloc).  Host pointers
  *     ("h_") are ordinary host memory.
  *   - Every call returns a status (PLAST_OK or a negative PLAST_E_* code);
  *     nothing throws or aborts across the ABI.  plast_strerror() maps a code to
@@ -177,6 +178,29 @@ int plast_ungapped_workspace_bytes(const plast_index_t* a, const plast_index_t* 
 int plast_ungapped_extend(const plast_index_t* a, const plast_index_t* b, const plast_ungapped_params_t* p,
                           int32_t mode, void* d_ws, size_t ws_bytes, plast_hit_t* d_hits, int64_t capacity,
                           int64_t* h_n_hits, int64_t* h_n_ext, void* stream);
+
+/*
+ * Allocation-free variant of plast_ungapped_extend, for callers that cannot
+ * allocate device memory or pass a workspace (tight serving loops, harnesses
+ * that forbid hipMalloc).  Same computation, arguments, outputs and errors as
+ * plast_ungapped_extend in PLAST_BATCHED mode, except that the workspace is a
+ * static device array of PLAST_NOALLOC_SCRATCH_BYTES inside the library: each
+ * GPU the library runs on holds one copy until the process ends, its address is
+ * looked up once per device (on the first call with that device current), and
+ * the call allocates nothing.  Runs on the current device; `stream` must
+ * belong to it.
+ * Limit: the work list must fit the array (about 520,000 items of the tuning in
+ * p->tuning; plast_ungapped_workspace_bytes reports the length in *n_items).  A
+ * longer list returns PLAST_E_WORKSPACE with the length in plast_last_error()
+ * and writes no hits.
+ * All calls on one GPU share its array, which keeps the last call's contents:
+ * calls that overlap on one GPU (other streams, other host threads) race and
+ * must be serialised by the caller.  Synchronises `stream`.
+ */
+#define PLAST_NOALLOC_SCRATCH_BYTES ((size_t)8 << 20)
+int plast_ungapped_extend_noalloc(const plast_index_t* a, const plast_index_t* b, const plast_ungapped_params_t* p,
+                                  plast_hit_t* d_hits, int64_t capacity, int64_t* h_n_hits, int64_t* h_n_ext,
+                                  void* stream);
 
 /*
  * Stage 3.1, small gapped filter (Sec. 3.3.4; Sec. 5.2.2: one extension on each

@@ -30,7 +30,8 @@ EXPORTS = ("plast_index_bytes", "plast_build_index", "plast_ungapped_workspace_b
            "plast_pipeline_result", "plast_pipeline_index", "plast_pipeline_destroy",
            "plast_search_workspace_bytes", "plast_search_enqueue", "plast_search_result",
            "plast_translate_ws_bytes", "plast_translate_count", "plast_translate_write",
-           "plast_align_workspace_bytes", "plast_align", "plast_probe_peak", "plast_strerror", "plast_last_error")
+           "plast_align_workspace_bytes", "plast_align", "plast_probe_peak", "plast_ungapped_extend_noalloc",
+           "plast_strerror", "plast_last_error")
 
 # plast_probe_peak kinds and the unit of each rate
 PROBES = {"valu_i32": (0, "op/s"), "valu_pk_i16": (1, "op/s"), "valu_pk_f16": (2, "op/s"),
@@ -173,6 +174,8 @@ def load():
         lib.plast_align_workspace_bytes.argtypes = [i64, AP, ctypes.POINTER(sz)]
         lib.plast_align.argtypes = [IV, IV, P, P, P, i64, AP, P, sz, P, P, ctypes.POINTER(i64), P]
         lib.plast_probe_peak.argtypes = [i32, P, sz, i32, ctypes.POINTER(ctypes.c_double), P]
+        lib.plast_ungapped_extend_noalloc.argtypes = [IV, IV, ctypes.POINTER(UngappedParams), P, i64,
+                                                      ctypes.POINTER(i64), ctypes.POINTER(i64), P]
         for f in EXPORTS[:-2]:
             getattr(lib, f).restype = ctypes.c_int
         lib.plast_strerror.argtypes = [ctypes.c_int]
@@ -349,6 +352,26 @@ class Extender:
 def ungapped_extend(ia, ib, s1, mode="batched", capacity=None, matrix=None, stream=None, tuning=None):
     """Stage 2: returns (hits int32[n, 5] device tensor in unspecified order, n_ext)."""
     return Extender(ia, ib, s1, mode, capacity, matrix, stream, tuning).run()
+
+
+NOALLOC_SCRATCH_BYTES = 8 << 20
+
+
+def ungapped_extend_noalloc(ia, ib, s1, hits, matrix=None, stream=None, tuning=None):
+    """Stage 2, BATCHED, through ``plast_ungapped_extend_noalloc`` (the library's
+    static scratch instead of a workspace): ``hits`` is the caller's int32[cap, 5]
+    device tensor; returns (hits[:n], n_ext).  Raises PlastError (E_CAPACITY
+    with the required count in the message, E_WORKSPACE when the work list does
+    not fit the static scratch)."""
+    t, tp = _tuning(tuning)
+    m, mp = _matrix_ptr(matrix)
+    params = UngappedParams(NBR, int(s1), mp, tp)
+    n_hits, n_ext = ctypes.c_int64(0), ctypes.c_int64(0)
+    rc = load().plast_ungapped_extend_noalloc(ctypes.byref(ia.view), ctypes.byref(ib.view), ctypes.byref(params),
+                                              _ptr(hits), hits.shape[0], ctypes.byref(n_hits), ctypes.byref(n_ext),
+                                              _stream(stream))
+    _check(rc, "plast_ungapped_extend_noalloc")
+    return hits[:n_hits.value], n_ext.value
 
 
 def gapped_filter(ia, ib, hits, s2, window=64, band=16, gap_open=11, gap_extend=1, matrix=None, stream=None,

@@ -253,6 +253,18 @@ int plast_ungapped_extend(const plast_index_t* a, const plast_index_t* b, const 
                               (hipStream_t)stream);
 }
 
+int plast_ungapped_extend_noalloc(const plast_index_t* a, const plast_index_t* b, const plast_ungapped_params_t* p,
+                                  plast_hit_t* d_hits, int64_t capacity, int64_t* h_n_hits, int64_t* h_n_ext,
+                                  void* stream) {
+  g_last_error[0] = 0;
+  int rc;
+  if ((rc = check_index(a, "a")) || (rc = check_index(b, "b"))) return rc;
+  if (!p || !h_n_hits || capacity < 0 || (capacity > 0 && !d_hits))
+    return set_error(PLAST_E_ARG, "null pointer or negative capacity");
+  if ((rc = check_uparams(p))) return rc;
+  return ungapped_extend_noalloc_impl(a, b, p, d_hits, capacity, h_n_hits, h_n_ext, (hipStream_t)stream);
+}
+
 int plast_gapped_filter(const plast_index_t* a, const plast_index_t* b, const plast_hit_t* d_hits, int64_t n_hits,
                         const plast_gapped_params_t* g, int32_t* d_gscore, uint8_t* d_pass, void* stream) {
   g_last_error[0] = 0;

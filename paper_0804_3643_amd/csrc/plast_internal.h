@@ -110,6 +110,11 @@ struct WorkItem {
 int ungapped_extend_impl(const plast_index_t* a, const plast_index_t* b, const plast_ungapped_params_t* p,
                          int32_t mode, void* d_ws, size_t ws_bytes, plast_hit_t* d_hits, int64_t capacity,
                          int64_t* h_n_hits, int64_t* h_n_ext, hipStream_t stream);
+// plast_ungapped_extend_noalloc: the BATCHED schedule with its workspace in a
+// static device array (PLAST_NOALLOC_SCRATCH_BYTES per device).
+int ungapped_extend_noalloc_impl(const plast_index_t* a, const plast_index_t* b, const plast_ungapped_params_t* p,
+                                 plast_hit_t* d_hits, int64_t capacity, int64_t* h_n_hits, int64_t* h_n_ext,
+                                 hipStream_t stream);
 int ungapped_ws_bytes_impl(const plast_index_t* a, const plast_index_t* b, int32_t mode, const plast_tuning_t& t,
                            size_t* bytes, int64_t* n_ext, int64_t* n_items, hipStream_t stream);
 

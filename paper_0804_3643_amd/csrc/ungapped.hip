@@ -42,6 +42,7 @@
 #include <stddef.h>
 #include <string.h>
 
+#include <mutex>
 #include <type_traits>
 #include <vector>
 
@@ -801,13 +802,62 @@ int ungapped_extend_impl(const plast_index_t* a, const plast_index_t* b, const p
     if (rc != PLAST_OK) return rc;
     PLAST_HIP(hipMemcpyAsync(&c, d_ws, sizeof(c), hipMemcpyDeviceToHost, stream));
     PLAST_HIP(hipStreamSynchronize(stream));
-    if (c.overflow) return set_error(PLAST_E_WORKSPACE, "workspace too small for the work list");
+    if (c.overflow == 1)
+      return set_error(PLAST_E_WORKSPACE, "work list of %llu items exceeds the %lld that %zu workspace bytes hold",
+                       c.n_items64, (long long)ungapped_ws_max_items(ws_bytes), ws_bytes);
+    if (c.overflow) return set_error(PLAST_E_WORKSPACE, "work list not built (index error flag)");
   }
   *h_n_hits = (int64_t)c.n_hits;
   if (h_n_ext) *h_n_ext = (int64_t)c.n_ext;
   if ((int64_t)c.n_hits > capacity)
     return set_error(PLAST_E_CAPACITY, "%lld hits > capacity %lld", (long long)c.n_hits, (long long)capacity);
   return PLAST_OK;
+}
+
+// ---------------------------------------------------------------- allocation-free variant
+// The BATCHED workspace (counters, per-key item counts, scan scratch, work
+// list) of plast_ungapped_extend_noalloc lives in this fixed device array
+// instead of caller memory.  Every GPU the library runs on holds its own copy
+// until the process ends.  In host code the name `scratch` is only a host-side
+// stand-in: the address kernels need comes from hipGetSymbolAddress, taken once
+// per device with that device current and kept in g_scratch_dev.
+namespace {
+constexpr size_t kStaticScratchBytes = PLAST_NOALLOC_SCRATCH_BYTES;
+static_assert(kStaticScratchBytes % 256 == 0, "scratch size");
+__device__ __align__(256) uint8_t scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device.
+int static_scratch(void** out) {
+  int dev = -1;
+  PLAST_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return set_error(PLAST_E_ARG, "device %d outside 0..%d", dev, kMaxDevices - 1);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    PLAST_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p || ((uintptr_t)p & 255)) return set_error(PLAST_E_HIP, "static scratch address %p unusable", p);
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return PLAST_OK;
+}
+}  // namespace
+
+int ungapped_extend_noalloc_impl(const plast_index_t* a, const plast_index_t* b, const plast_ungapped_params_t* p,
+                                 plast_hit_t* d_hits, int64_t capacity, int64_t* h_n_hits, int64_t* h_n_ext,
+                                 hipStream_t stream) {
+  void* ws = nullptr;
+  const int rc = static_scratch(&ws);
+  if (rc != PLAST_OK) return rc;
+  // The schedule's first kernel clears the counter header; the per-key counts,
+  // the scan scratch and the work list are written in full before being read,
+  // so what an earlier call left in the array does not matter.
+  return ungapped_extend_impl(a, b, p, PLAST_BATCHED, ws, kStaticScratchBytes, d_hits, capacity, h_n_hits, h_n_ext,
+                              stream);
 }
 
 }  // namespace plast
