@@ -77,9 +77,10 @@ def _matrix(matrix):
 
 
 def ungapped_hits(bank1, bank2, s1, keys=None, idx1=None, idx2=None, nthreads=None,
-                  matrix=O.BLOSUM62, nbr=O.NBR, right=O.RIGHT, canonicalize=True):
+                  matrix=O.BLOSUM62, nbr=O.NBR, right=O.RIGHT, canonicalize=True, capacity=None):
     """Hit rows int64[n, 5] (canonical order unless ``canonicalize=False``) and
-    the number of pairs scored."""
+    the number of pairs scored.  ``capacity`` is the first guess of the hit
+    count (the call runs again with the exact count when the guess is short)."""
     lib = load()
     c1, st1 = _bank_arrays(bank1)
     c2, st2 = _bank_arrays(bank2)
@@ -90,7 +91,7 @@ def ungapped_hits(bank1, bank2, s1, keys=None, idx1=None, idx2=None, nthreads=No
     karr = None if keys is None else np.ascontiguousarray(np.asarray(keys, dtype=np.int32))
     kp = None if karr is None else _ptr(karr)
     nk = 0 if karr is None else len(karr)
-    cap = 1 << 16
+    cap = max(1, int(capacity)) if capacity else 1 << 16
     while True:
         out = np.zeros((cap, 5), dtype=np.int32)
         n_ext = ctypes.c_int64(0)

@@ -1,5 +1,6 @@
 """GPU parity: the HIP library, called through its C ABI, against the CPU oracle
 on the same seeded inputs.  Integer work, so every comparison is exact."""
+import os
 import sys
 
 import numpy as np
@@ -9,6 +10,9 @@ import torch
 from oracle import coracle as C
 from oracle import plast_oracle as O
 from paper_0804_3643_amd import params, synth
+
+sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+import fullsize  # noqa: E402
 
 pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
@@ -264,6 +268,52 @@ def test_gapped_custom_matrix(B, wide):
     assert np.array_equal(ps.cpu().numpy().astype(bool), ref >= 40)
 
 
+def _edge_matrix(rng, m):
+    """Mismatch-heavy integer matrix: +m on the diagonal, off it mostly in
+    [-m, -1] (10% in [1, m/2]) with -m present, so that |M| = m exactly and the
+    DP cells of unrelated windows run deep into negative values."""
+    M = rng.integers(-m, 0, size=(20, 20))
+    pos = rng.random((20, 20)) < 0.1
+    M[pos] = rng.integers(1, m // 2 + 1, size=int(pos.sum()))
+    np.fill_diagonal(M, m)
+    M[3, 7] = -m
+    return M
+
+
+# The packed-binary16 kernel is taken iff band == 16, window <= 64 and
+# 64 |M| + 3 (open + extend) + 280 extend <= 2000: each pair below sits on the
+# last admitted value (1998, 1999) and the first rejected one (2001, 2002).
+@pytest.mark.parametrize("m,go,ge,bound", [(26, 17, 1, 1998), (26, 18, 1, 2001), (20, 51, 2, 1999),
+                                           (20, 52, 2, 2002)])
+def test_gapped_at_the_binary16_bound(B, m, go, ge, bound):
+    assert 64 * m + 3 * (go + ge) + 280 * ge == bound
+    _say("gapped at the f16 bound |M|=%d open=%d ext=%d (%d)" % (m, go, ge, bound))
+    rng = np.random.default_rng(bound)
+    M = _edge_matrix(rng, m)
+    # gap-heavy pairs: bank 2 holds copies of bank-1 sequences with a letter
+    # deleted every 5 (or inserted every 7) letters, and random sequences
+    b1 = synth.random_bank(rng, 60, 150, 400)
+    seqs2 = []
+    for i in range(b1.n_seqs):
+        s = b1.seq(i).copy()
+        if i % 2:
+            seqs2.append(np.delete(s, np.arange(4, len(s), 5)))
+        else:
+            seqs2.append(np.insert(s, np.arange(6, len(s), 7), rng.integers(0, 20, size=len(range(6, len(s), 7)))))
+    seqs2 += [rng.integers(0, 20, size=int(n)).astype(np.uint8) for n in rng.integers(100, 400, size=60)]
+    b2 = synth.Bank.from_seqs(seqs2)
+    ia, ib = _index(B, b1), _index(B, b2)
+    hits, _ = B.ungapped_extend(ia, ib, 3 * m, mode="batched", matrix=M)
+    assert hits.shape[0] > 10000
+    gs, ps = B.gapped_filter(ia, ib, hits, 200, gap_open=go, gap_extend=ge, matrix=M)
+    h = hits.cpu().numpy().astype(np.int64)
+    ref = C.gapped_scores(b1, b2, h, gap_open=go, gap_extend=ge, matrix=M)
+    assert np.array_equal(gs.cpu().numpy().astype(np.int64), ref)
+    assert np.array_equal(ps.cpu().numpy().astype(bool), ref >= 200)
+    # alignments through the gaps of the edited copies score far above the seed
+    assert (ref >= 200).sum() > 1000
+
+
 def test_gapped_sequence_ends_and_bad_records(B):
     _say("gapped edges")
     rng = np.random.default_rng(4)
@@ -298,9 +348,11 @@ def _sorted_by_pair(h):
 @pytest.mark.timeout(600)
 def test_config1_full_size_plain_batched_and_sampled_keys(B):
     """Full-size configuration 1 (10,000 x 100,000 proteins), in the launch
-    configuration the benchmark times: PLAIN == BATCHED exactly, the number of
-    extensions equals the oracle's, and the hits of sampled keys (heavy, light
-    and random) equal the oracle's computed key by key."""
+    configuration the benchmark times: the whole hit list and every gapped
+    score equal the oracle's full-size golden (count and 64-bit multiset
+    digests, whole run and per block of 80 keys), PLAIN == BATCHED exactly, the
+    number of extensions equals the oracle's, and the hits of sampled keys
+    (heavy, light and random) equal the oracle's computed key by key."""
     _say("cfg1 generate")
     w = synth.make_workload(1)
     assert w.bank1.lengths.max() < 2048 and w.bank2.lengths.max() < 2048  # 11-bit positions in _pair_keys
@@ -308,6 +360,13 @@ def test_config1_full_size_plain_batched_and_sampled_keys(B):
     ia, ib = _index(B, w.bank1), _index(B, w.bank2)
     _say("cfg1 batched")
     hb, n_ext = B.ungapped_extend(ia, ib, params.S1, mode="batched")
+    _say("cfg1 gapped filter, whole run against the oracle's full-size golden")
+    gs, _ = B.gapped_filter(ia, ib, hb, params.S2)
+    got = fullsize.device_summary(hb, gs, params.S2, w.bank1, n_ext)
+    golden = fullsize.load(1)
+    assert golden is not None and golden["bank_sha256"] == [w.bank1.sha256(), w.bank2.sha256()]
+    assert fullsize.compare(golden, got) == [], fullsize.compare(golden, got)
+    del gs
     hb = hb.cpu().numpy()
     _say("cfg1 plain")
     hp, n_ext_p = B.ungapped_extend(ia, ib, params.S1, mode="plain")
