@@ -43,9 +43,23 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "ungapped extensions/sec and bank-vs-bank wall time (plain vs batched, bit-exact)"
-OPS_PER_EXT = 88           # 44 scan steps x (1 add + 1 max), int16
+# Ungapped extension, per candidate pair: 44 scan steps, each one substitution
+# lookup, one addition and one maximum.  The kernel serves the lookups from an
+# LDS profile (2 bytes per step), so its VALU work is the 88 additions and
+# maxima and its LDS work is 88 bytes; counting the lookups as ALU operations
+# too gives 132 operations per pair.
+OPS_PER_EXT = 88
+OPS_PER_EXT_WITH_LOOKUPS = 132
+LDS_BYTES_PER_EXT = 88
 # MI355X: 256 CUs x 64 VALU lanes x 2 int16 ops per packed instruction x 2.4 GHz
 PEAK_INT16_TOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+# LDS, 8-byte reads: 256 bytes per CU per clock (one 64-lane ds_read_b64 every
+# two clocks); the 64-bit LDS probe sustains 226 bytes per CU per clock
+# (rocprofv3 counters), above the 128 of earlier CDNA parts
+PEAK_LDS_TBS = 256 * 256 * 2.4e9 / 1e12
+# Gapped filter: about 8 operations per DP cell (E: 2, F: 2, H: lookup, add and
+# two maxima, best: 1), packed 16-bit
+GAPPED_OPS_PER_CELL = 8
 # Stage 3.2: 7 int32 operations per DP cell (E: subtract, max; F: subtract, max;
 # diagonal add; two maxima for H) against 256 CUs x 64 VALU lanes x 2.4 GHz
 ALIGN_OPS_PER_CELL = 7
@@ -58,22 +72,65 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash():
-    with open(KERNEL_SRC, "rb") as f:
+def kernel_source_hash(src=KERNEL_SRC):
+    with open(src, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def recorded_traffic():
-    """HBM bytes per launch of the ungapped kernel from the committed rocprofv3
-    counter summary, if it was taken on the current kernel source."""
-    if not os.path.exists(TRAFFIC_FILE):
+def recorded_traffic(path, src=KERNEL_SRC):
+    """HBM bytes per launch of a kernel from a committed rocprofv3 counter
+    summary, if it was taken on the current kernel source."""
+    if not os.path.exists(path):
         return None
-    txt = open(TRAFFIC_FILE).read()
+    txt = open(path).read()
     m = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", txt)
     b = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
-    if not m or not b or m.group(1) != kernel_source_hash():
+    if not m or not b or m.group(1) != kernel_source_hash(src):
         return None
     return float(b.group(1))
+
+
+def traffic_file(kernel, cfg):
+    return os.path.join(ROOT, "profiles", "%s_cfg%s_traffic.md" % (kernel, cfg))
+
+
+def golden_check(cfg, hits, gscore, s2, n_ext, bank1, banks_sha):
+    """The whole run against the oracle's full-size golden of workload ``cfg``
+    (tests/golden/fullsize.py): counts and 64-bit multiset digests of the hit
+    records and their gapped scores, whole run and per block of 80 keys."""
+    sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
+    import fullsize
+    golden = fullsize.load(cfg)
+    if golden is None:
+        return {"golden": None, "equal": False, "mismatch": ["no stored golden for workload %s" % cfg]}
+    if golden["bank_sha256"] != banks_sha:
+        return {"golden": os.path.basename(fullsize.golden_path(cfg)), "equal": False,
+                "mismatch": ["generated banks differ from the golden's"]}
+    got = fullsize.device_summary(hits, gscore, s2, bank1, n_ext)
+    bad = fullsize.compare(golden, got)
+    return {"golden": os.path.basename(fullsize.golden_path(cfg)), "equal": not bad, "mismatch": bad,
+            "n_hits": got["n_hits"], "n_pass": got["n_pass"], "digest": got["hits_gscore"]}
+
+
+def gapped_cells(np, bank1, bank2, hits, window=64, band=16):
+    """DP cells of the gapped filter over a hit list (host int arrays): both
+    sides of every hit, each the cells (i, j) != (0, 0), 0 <= i <= lx,
+    0 <= j <= ly, |i - j| <= band of its clipped windows (at most 1872 per
+    side)."""
+    lx = np.arange(window + 1)[:, None]
+    ly = np.arange(window + 1)[None, :]
+    table = np.zeros((window + 1, window + 1), dtype=np.int64)
+    for i in range(window + 1):
+        lo, hi = max(0, i - band), i + band
+        row = np.clip(np.minimum(ly, hi) - lo + 1, 0, None)           # cells of row i when ly is given
+        table += np.where(lx >= i, row, 0)
+    h = np.asarray(hits, dtype=np.int64)
+    la = np.diff(bank1.seq_start) - 20
+    lb = np.diff(bank2.seq_start) - 20
+    s1, p1, s2, p2 = h[:, 0], h[:, 1], h[:, 2], h[:, 3]
+    right = table[np.minimum(window, la[s1] - p1), np.minimum(window, lb[s2] - p2)]
+    left = table[np.minimum(window, p1), np.minimum(window, p2)]
+    return int(right.sum() + left.sum()) - 2 * len(h)   # the anchor cell (0, 0) of each side is given
 
 
 def copy_calibration(torch, dev):
@@ -95,8 +152,11 @@ def pair_keys_device(torch, hits):
     return k, h[o, 4]
 
 
-def cpu_baseline(w, gpu_hits_host, n_ext_total, sample_ext, s1, s2):
-    """Oracle (plain C) on a seeded key sample; returns the JSON object."""
+def cpu_baseline(w, gpu_hits_host, gpu_gscore_host, n_ext_total, sample_ext, s1, s2):
+    """Oracle (plain C) on a seeded key sample; returns the JSON object.  The
+    GPU's hits and gapped scores of the sampled keys are compared with the
+    oracle's (``oracle_hits_equal_gpu_on_sample``,
+    ``oracle_gapped_equal_gpu_on_sample``)."""
     import numpy as np
 
     from oracle import coracle as C
@@ -132,8 +192,12 @@ def cpu_baseline(w, gpu_hits_host, n_ext_total, sample_ext, s1, s2):
     q = w.bank1.seq_start[gpu_hits_host[:, 0]] + gpu_hits_host[:, 1]
     hk = O.seed_key(c[q].astype(np.int64), c[q + 1].astype(np.int64), c[q + 2].astype(np.int64),
                     c[q + 3].astype(np.int64))
-    mine = O.canonical(gpu_hits_host[np.isin(hk, keys)])
-    equal = bool(np.array_equal(mine, ref))
+    sel = np.isin(hk, keys)
+    mine_h, mine_g = gpu_hits_host[sel], gpu_gscore_host[sel]
+    order = np.lexsort(mine_h.T[::-1])
+    mine_h, mine_g = mine_h[order], mine_g[order]
+    equal = bool(np.array_equal(mine_h, ref))
+    g_equal = bool(equal and np.array_equal(mine_g, g))
     t_job = t_index + (t_ung + t_gap) * (n_ext_total / max(1, n_ext_s))
     # one thread, ungapped loop only, on a sixteenth of the sampled keys
     t0 = time.perf_counter()
@@ -157,7 +221,8 @@ def cpu_baseline(w, gpu_hits_host, n_ext_total, sample_ext, s1, s2):
                    "(%d extensions, %.1f%% of the job; ungapped %.2f s, gapped on its %d hits %.2f s), "
                    "scaled to all %d extensions" % (cores, t_index, len(keys), n_ext_s, 100.0 * n_ext_s /
                                                     n_ext_total, t_ung, len(ref), t_gap, n_ext_total)),
-        "oracle_hits_equal_gpu_on_sample": equal, "n_gapped_pass_sample": int((g >= s2).sum()),
+        "oracle_hits_equal_gpu_on_sample": equal, "oracle_gapped_equal_gpu_on_sample": g_equal,
+        "n_gapped_pass_sample": int((g >= s2).sum()),
         "single_thread": {"ext_per_s": n_ext_1 / t_1,
                           "sample": "ungapped loop, 1 thread, %d of the sampled keys (%d extensions) in %.2f s"
                                     % (len(keys_1t), n_ext_1, t_1)},
@@ -167,9 +232,10 @@ def cpu_baseline(w, gpu_hits_host, n_ext_total, sample_ext, s1, s2):
 
 # Published MI355X figures the measured peaks stand for: 256 CUs at up to
 # 2.4 GHz, 64 int32 / 128 packed 16-bit lane operations per clock per CU, LDS
-# 128 bytes (32 lookups of 4 bytes) per clock per CU, HBM3E 8 TB/s.
+# 32 lookups of 4 bytes and 256 bytes of 8-byte reads per clock per CU, HBM3E
+# 8 TB/s.
 PUBLISHED_PEAKS = {"valu_i32": 256 * 64 * 2.4e9, "valu_pk_i16": 256 * 128 * 2.4e9, "valu_pk_f16": 256 * 128 * 2.4e9,
-                   "lds_lookup": 256 * 32 * 2.4e9, "hbm_copy": 8e12}
+                   "lds_lookup": 256 * 32 * 2.4e9, "hbm_copy": 8e12, "lds_b64": 256 * 256 * 2.4e9}
 
 
 def machine_info():
@@ -320,20 +386,25 @@ def run_stage32(B, torch, np, w, ia, ib, hits, gs, ps, reps, cpu):
     return out
 
 
-def run_serving(args):
-    """Serving workload (config 4): a resident bank of 1M proteins indexed once in
-    HBM, 1000 query banks of 1-500 proteins with Poisson arrivals at 0.7 x the
-    measured saturation throughput, continuous batching over several slots."""
+def serving_leg(args, n_requests=None, oracle_checks=True):
+    """Serving workload (config 4): a resident bank of 1M proteins indexed once
+    in HBM, query banks of 1-500 proteins with Poisson arrivals at 0.7 x the
+    saturation throughput measured first, continuous batching over several
+    slots.  Checks, asserted by the caller: sampled requests give the same
+    matches alone as in the mix, and the smallest requests' matches equal the
+    oracle's (ungapped hits that pass the gapped filter, with both scores)."""
     import numpy as np
     import torch
 
     from paper_0804_3643_amd import binding as B
+    from paper_0804_3643_amd import params
     from paper_0804_3643_amd import serving as S
     from paper_0804_3643_amd import synth
 
     B.load()
-    log("generating the serving workload (scale %.3g)" % args.serving_scale)
-    w = synth.make_serving(n_requests=args.serving_requests, scale=args.serving_scale)
+    n_requests = n_requests or args.serving_requests
+    log("generating the serving workload (scale %.3g, %d requests)" % (args.serving_scale, n_requests))
+    w = synth.make_serving(n_requests=n_requests, scale=args.serving_scale)
     log("indexing the resident bank (%d proteins, %d residues)" % (w.resident.n_seqs, w.resident.n_residues))
     t1 = time.perf_counter()
     res = S.Resident(w.resident.codes, w.resident.seq_start)
@@ -344,7 +415,7 @@ def run_serving(args):
     def reqs(arrivals):
         return [S.Request(i, b.codes, b.seq_start, arrival=float(t)) for i, (b, t) in enumerate(zip(w.requests, arrivals))]
 
-    n_sat = min(len(w.requests), 200)
+    n_sat = min(len(w.requests), max(1, len(w.requests) // 2))
     log("saturation run (%d requests at t=0)" % n_sat)
     srv.run(reqs([0.0] * len(w.requests))[:n_sat])  # warm-up
     sat = reqs([0.0] * len(w.requests))[:n_sat]
@@ -378,9 +449,25 @@ def run_serving(args):
         mk = mix[int(i)].matches[:, 0].astype(np.int64) * (1 << 21) + mix[int(i)].matches[:, 2]
         found += int(np.isin(h[:, 0] * (1 << 21) + h[:, 1], mk).sum())
         planted += len(h)
-    out = {
-        "metric": "serving: p50/p99 request latency and extensions/s under Poisson arrivals",
-        "value": ext / busy, "unit": "ext/s", "n_gpus": 1, "higher_is_better": True,
+    bit_exact = {"alone_equals_mix_on_%d_sampled_requests" % len(pick): same}
+    if oracle_checks:
+        from oracle import coracle as C
+        small = np.argsort([b.n_seqs for b in w.requests], kind="stable")[:3]
+        log("oracle on the %d smallest requests" % len(small))
+        idx_res = C.build_index(w.resident)
+        eq = True
+        for i in small:
+            q = w.requests[int(i)]
+            hq, _ = C.ungapped_hits(q, w.resident, params.S1, idx2=idx_res,
+                                    nthreads=min(16, os.cpu_count() or 1))
+            gq = C.gapped_scores(q, w.resident, hq, nthreads=min(16, os.cpu_count() or 1))
+            ok = gq >= params.S2
+            ref = S.canonical(np.column_stack([hq[ok], gq[ok]]))
+            eq &= bool(np.array_equal(ref, S.canonical(mix[int(i)].matches)))
+        bit_exact["oracle_equals_gpu_on_%d_smallest_requests" % len(small)] = eq
+    bit_exact["all"] = all(bit_exact.values())
+    return {
+        "value": ext / busy, "unit": "ext/s",
         "p50_ms": stats["p50_ms"], "p99_ms": stats["p99_ms"], "mean_ms": stats["mean_ms"], "max_ms": stats["max_ms"],
         "requests": len(mix), "arrival_rate_rps": rate, "saturation_rps": cap_rps, "saturation_ext_per_s": sat_ext,
         "batches": srv.batches - b0, "splits": srv.splits - s0,
@@ -393,13 +480,26 @@ def run_serving(args):
                         "device_ms": float(blog[:, 4].mean()), "host_split_ms": float(blog[:, 5].mean()),
                         "device_ext_per_s": float(blog[:, 1].sum() / (blog[:, 4].sum() * 1e-3))},
         "slots": args.serving_slots, "resident_index_s": index_s,
-        "bit_exact": {"alone_equals_mix_on_%d_sampled_requests" % len(pick): same},
+        "bit_exact": bit_exact,
         "planted_homologs_found_on_sampled_requests": "%d/%d" % (found, planted),
         "matches_per_request_mean": float(np.mean([len(r.matches) for r in mix])),
-        "dtype": "f16", "data": "synthetic",
-        "config": {"workload": w.description, "resident_residues": w.resident.n_residues,
-                   "query_proteins": int(sum(b.n_seqs for b in w.requests))},
+        "workload": w.description, "resident_residues": w.resident.n_residues,
+        "query_proteins": int(sum(b.n_seqs for b in w.requests)),
     }
+
+
+def run_serving(args):
+    """``--serving``: the serving workload alone, as its own JSON line."""
+    leg = serving_leg(args, oracle_checks=not args.no_cpu_baseline)
+    if not leg["bit_exact"]["all"]:
+        log("MISMATCH in the serving run: %s" % leg["bit_exact"])
+        sys.exit(1)
+    out = {"metric": "serving: p50/p99 request latency and extensions/s under Poisson arrivals",
+           "n_gpus": 1, "higher_is_better": True, "dtype": "int16 (exact, carried in binary16)",
+           "data": "synthetic", "config": {"workload": leg.pop("workload"),
+                                           "resident_residues": leg.pop("resident_residues"),
+                                           "query_proteins": leg.pop("query_proteins")}}
+    out.update(leg)
     print(json.dumps(out), flush=True)
 
 
@@ -543,9 +643,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", type=int, default=1,
-                    help="synthetic workload (1 = 10,000 x 100,000 proteins; 2 = skewed 20,000 x 300,000; "
-                         "3 = TPLAST-N, 5,000 proteins x 2,000 DNA sequences)")
+    ap.add_argument("--config", type=int, default=2,
+                    help="synthetic workload (2 = skewed 20,000 x 300,000 proteins, the default; 1 = 10,000 x "
+                         "100,000; 3 = TPLAST-N, 5,000 proteins x 2,000 DNA sequences)")
     ap.add_argument("--plain-reps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-ext", type=float, default=1.5e9)
@@ -560,8 +660,14 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=1000)
     ap.add_argument("--serving-scale", type=float, default=1.0, help="resident bank size factor (1 = 1M proteins)")
     ap.add_argument("--serving-slots", type=int, default=3)
+    ap.add_argument("--serving-leg-requests", type=int, default=200,
+                    help="requests of the serving leg of the default run (1M resident proteins)")
+    ap.add_argument("--no-serving-leg", dest="serving_leg", action="store_false",
+                    help="skip the serving leg of the default run")
     ap.add_argument("--plastx", action="store_true",
                     help="PLAST-X: both banks nucleotide, translated on the device in six frames")
+    ap.add_argument("--probes-only", action="store_true",
+                    help="only the measured peaks (plast_probe_peak), e.g. under rocprofv3 counters")
     ap.add_argument("--no-stage32", dest="stage32", action="store_false",
                     help="skip stage 3.2 (full gapped alignment of the passing hits, reported apart from the step)")
     args = ap.parse_args()
@@ -579,6 +685,10 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.probes_only:
+        B.load()
+        print(json.dumps({"measured_peaks": measured_peaks(B, torch, dev), "machine": machine_info()}), flush=True)
+        return
     if args.serving:
         run_serving(args)
         return
@@ -665,7 +775,15 @@ def main():
     graph_eq = bool(res["n_ext"] == n_ext and res["n_hits"] == n_hits and torch.equal(kg, ke) and
                     torch.equal(sg, se) and int(gp.sum().item()) == n_pass)
     assert graph_eq, "graph replay and eager calls differ"
-    del kg, sg, ke, se, gh, gg, gp
+    del kg, sg, ke, se
+    # the whole run against the oracle's full-size golden, before any time is reported
+    log("whole run against the oracle's golden")
+    golden = golden_check(str(args.config), gh, gg, params.S2, res["n_ext"], w.bank1,
+                          [w.bank1.sha256(), w.bank2.sha256()])
+    if not golden["equal"]:
+        log("MISMATCH against the oracle's golden: %s" % golden["mismatch"])
+        sys.exit(1)
+    del gh, gg, gp
 
     # ---- PLAIN vs BATCHED (ungapped stage only), same output required
     log("plain vs batched")
@@ -705,6 +823,7 @@ def main():
     plain_eq = bool(ne_p == ne_b == n_ext and torch.equal(kp, kb) and torch.equal(sp, sbat))
     assert plain_eq, "PLAIN and BATCHED hit lists differ"
     no_dups = bool((kb[1:] != kb[:-1]).all().item()) if kb.numel() > 1 else True
+    assert no_dups, "a candidate pair is reported twice"
     del kp, sp, kb, sbat, hp
     B.timing_enable(False)
 
@@ -744,6 +863,11 @@ def main():
     peaks = measured_peaks(B, torch, dev)
 
     achieved = n_ext * OPS_PER_EXT / (batched_kernel_ms * 1e-3) / 1e12
+    lds_achieved = n_ext * LDS_BYTES_PER_EXT / (batched_kernel_ms * 1e-3) / 1e12
+    gapped_kernel_ms = float(np.mean(stage_ms["gapped_ms"]))
+    h_host = host_b[0].numpy()
+    cells = gapped_cells(np, w.bank1, w.bank2, h_host)
+    gapped_achieved = cells * GAPPED_OPS_PER_CELL / (gapped_kernel_ms * 1e-3) / 1e12
     out = {
         "metric": METRIC,
         "value": n_ext / (ms_per_step * 1e-3),
@@ -755,9 +879,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f16",
-        "dtype_note": ("integer scores carried exactly in packed binary16 (every value an integer of magnitude "
-                       "< 2048); an int16 ungapped path and an int32 gapped path serve matrices outside that range"),
+        "dtype": "int16 (exact, carried in binary16)",
+        "dtype_note": ("exact integer arithmetic: every score and partial sum is an integer of magnitude < 2048, "
+                       "carried in packed binary16 registers where that is exact (BLOSUM62); an int16 ungapped path "
+                       "and an int32 gapped path serve matrices outside that range"),
         "data": "synthetic",
         "config": {
             "workload": "PLAST-P configuration %d: %s; seeded lognormal lengths (mean 300, clamped 50-1000), "
@@ -790,10 +915,30 @@ def main():
                       "graph_equals_eager": graph_eq},
         "roofline": {
             "bound": "alu", "achieved": achieved, "peak": PEAK_INT16_TOPS, "unit": "TOP/s",
-            "frac": achieved / PEAK_INT16_TOPS, "traffic": recorded_traffic(),
+            "frac": achieved / PEAK_INT16_TOPS,
+            "traffic": recorded_traffic(traffic_file("ungapped_persistent", args.config)),
             "kernel": "k_ungapped_persistent", "ops_per_ext": OPS_PER_EXT,
+            "kernel_ms": batched_kernel_ms, "extensions_per_launch": n_ext,
             "measured_peak": peaks["valu_pk_f16"]["rate"] / 1e12,
             "frac_of_measured_peak": achieved / (peaks["valu_pk_f16"]["rate"] / 1e12),
+            "with_lookups_as_alu_ops": {
+                "ops_per_ext": OPS_PER_EXT_WITH_LOOKUPS,
+                "achieved": achieved * OPS_PER_EXT_WITH_LOOKUPS / OPS_PER_EXT,
+                "frac": achieved * OPS_PER_EXT_WITH_LOOKUPS / OPS_PER_EXT / PEAK_INT16_TOPS,
+                "note": "counts the 44 substitution lookups per pair as ALU operations; the kernel serves them "
+                        "from LDS (one ds_read_b64 gives 4 rows), so this fraction can exceed 1 and the VALU "
+                        "(88 ops) and LDS (88 bytes) fractions are the binding ones"},
+            "lds": {"bound": "lds", "achieved": lds_achieved, "peak": PEAK_LDS_TBS, "unit": "TB/s",
+                    "frac": lds_achieved / PEAK_LDS_TBS, "bytes_per_ext": LDS_BYTES_PER_EXT,
+                    "measured_peak": peaks["lds_b64"]["rate"] / 1e12,
+                    "frac_of_measured_peak": lds_achieved / (peaks["lds_b64"]["rate"] / 1e12),
+                    "note": "profile lookups: 44 scores of 2 bytes per pair, read 4 rows at a time with "
+                            "ds_read_b64, against 256 B per CU per clock"},
+            "gapped": {"bound": "alu", "kernel": "k_gapped_f16", "achieved": gapped_achieved,
+                       "peak": PEAK_INT16_TOPS, "unit": "TOP/s", "frac": gapped_achieved / PEAK_INT16_TOPS,
+                       "kernel_ms": gapped_kernel_ms, "dp_cells": cells, "ops_per_cell": GAPPED_OPS_PER_CELL,
+                       "traffic": recorded_traffic(traffic_file("gapped", args.config),
+                                                   os.path.join(ROOT, "paper_0804_3643_amd", "csrc", "gapped.hip"))},
         },
         "cpu_baseline": None,
         "stage32": stage32,
@@ -806,12 +951,32 @@ def main():
         r = stage32["roofline"]
         r["measured_peak"] = peaks["valu_i32"]["rate"] / 1e12
         r["frac_of_measured_peak"] = r["achieved"] / r["measured_peak"]
+    out["bit_exact"]["oracle_golden_whole_run"] = golden
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a key sample)")
         hh = host_b[0].numpy().astype(np.int64)
-        cb_ = cpu_baseline(w, hh, n_ext, args.cpu_sample_ext, params.S1, params.S2)
+        cb_ = cpu_baseline(w, hh, host_b[1].numpy().astype(np.int64), n_ext, args.cpu_sample_ext, params.S1,
+                           params.S2)
         out["bit_exact"]["oracle_equals_gpu_on_sample_keys"] = cb_.pop("oracle_hits_equal_gpu_on_sample")
+        out["bit_exact"]["oracle_gapped_equals_gpu_on_sample_keys"] = cb_.pop("oracle_gapped_equal_gpu_on_sample")
         out["cpu_baseline"] = cb_
+        if not (out["bit_exact"]["oracle_equals_gpu_on_sample_keys"] and
+                out["bit_exact"]["oracle_gapped_equals_gpu_on_sample_keys"]):
+            log("MISMATCH against the oracle on the sampled keys")
+            sys.exit(1)
+    if stage32 is not None and "oracle_equals_gpu_on_sample_pairs" in stage32 and \
+            not stage32["oracle_equals_gpu_on_sample_pairs"]:
+        log("MISMATCH of stage 3.2 against the oracle on the sampled sequence pairs")
+        sys.exit(1)
+    if args.serving_leg:
+        del host_b, h_fin, g_fin, p_fin, ext, ext_p, pipe
+        torch.cuda.empty_cache()
+        log("serving leg")
+        out["serving"] = serving_leg(args, n_requests=args.serving_leg_requests,
+                                     oracle_checks=not args.no_cpu_baseline)
+        if not out["serving"]["bit_exact"]["all"]:
+            log("MISMATCH in the serving leg: %s" % out["serving"]["bit_exact"])
+            sys.exit(1)
     print(json.dumps(out), flush=True)
 
 

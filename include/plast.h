@@ -69,7 +69,9 @@ typedef struct {
   const int64_t* key_off;    /* PLAST_NKEYS + 1: occurrences of key k are [key_off[k], key_off[k+1]) */
   const int32_t* occ;        /* n_words: offset in codes of the first seed letter */
   const int32_t* occ_seq;    /* n_words: sequence id of that occurrence */
-  const uint8_t* scan_codes; /* internal copy of codes scaled for table addressing, with tail slack */
+  const uint8_t* scan_codes; /* INTERNAL (in the index buffer): the letters scaled to table offsets,
+                                with tail slack; kernels read it instead of codes.  Callers only
+                                pass the view on and must not rely on its contents. */
   int64_t n_words;           /* host copy of key_off[PLAST_NKEYS] */
 } plast_index_t;
 
@@ -456,6 +458,8 @@ int plast_align(const plast_index_t* a, const plast_index_t* b, const plast_hit_
  *   PLAST_PROBE_VALU_PK_F16  the same on packed binary16: operations/s (4 per update)
  *   PLAST_PROBE_LDS          conflict-free 32-bit LDS lookups/s
  *   PLAST_PROBE_HBM_COPY     copy of the first half of d_buf to the second: bytes/s read + written
+ *   PLAST_PROBE_LDS_B64      8-byte LDS reads with the ungapped kernel's profile access (lanes spread
+ *                            over 21 entries 8 bytes apart): bytes/s
  * d_buf: caller device memory, 256-byte aligned, at least 2 MiB for the compute
  * probes (each thread writes one int32) and 1 MiB for the copy, whose size is
  * buf_bytes (1 GiB or more gives a stable figure).  Synchronises the stream.
@@ -467,7 +471,8 @@ enum {
   PLAST_PROBE_VALU_PK_I16 = 1,
   PLAST_PROBE_VALU_PK_F16 = 2,
   PLAST_PROBE_LDS = 3,
-  PLAST_PROBE_HBM_COPY = 4
+  PLAST_PROBE_HBM_COPY = 4,
+  PLAST_PROBE_LDS_B64 = 5
 };
 int plast_probe_peak(int32_t kind, void* d_buf, size_t buf_bytes, int32_t reps, double* rate, void* stream);
 

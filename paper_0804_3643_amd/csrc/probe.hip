@@ -6,7 +6,12 @@
 // * VALU, packed 16-bit integer and packed binary16: the same chains on
 //   two-element vectors, two operations per lane per instruction.
 // * LDS: 32-bit table lookups, each 64-lane read on 64 consecutive words (no
-//   bank conflict), the access pattern of the per-lane score profiles.
+//   bank conflict), the access pattern of the per-lane score profiles of the
+//   alignment kernel.
+// * LDS, 64-bit: the access of the ungapped kernel's profile: per step, one
+//   bit-field extract of the lane's letter and eight 8-byte reads, each
+//   64-lane read spread over the 21 letter entries of one step (8 bytes
+//   apart), so lanes with equal letters share an address.
 // * HBM: a copy between the two halves of a buffer, four 16-byte loads in
 //   flight per lane.
 //
@@ -91,6 +96,51 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_lds(int32_t* __restrict
   out[(int64_t)blockIdx.x * blockDim.x + threadIdx.x] = s;
 }
 
+constexpr int kL64Steps = 16;
+constexpr int kL64Letters = 21;
+
+// Per iteration 16 steps x 8 reads of 8 bytes; the letters rotate every
+// iteration so that no read can be hoisted out of the loop.
+__global__ __launch_bounds__(kProbeThreads) void k_probe_lds_b64(int32_t* __restrict__ out, int iters, int seed) {
+  __shared__ uint2 tbl[kChains][kL64Steps][kL64Letters];
+  uint2* flat = &tbl[0][0][0];
+  for (int i = threadIdx.x; i < kChains * kL64Steps * kL64Letters; i += blockDim.x)
+    flat[i] = make_uint2((uint32_t)(i * 3 + seed), (uint32_t)(i ^ seed));
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  uint32_t let[4];  // 16 letters as (letter * 8) bytes
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    uint32_t w = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) w |= (uint32_t)(((lane * 5 + (4 * j + b) * 7 + seed) % kL64Letters) * 8) << (8 * b);
+    let[j] = w;
+  }
+  uint2 acc[kChains];
+#pragma unroll
+  for (int k = 0; k < kChains; ++k) acc[k] = make_uint2(0u, 0u);
+  const uint8_t* base = (const uint8_t*)flat;
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int t = 0; t < kL64Steps; ++t) {
+      const uint32_t c8 = __builtin_amdgcn_ubfe(let[t >> 2], 8 * (t & 3), 8);
+      const uint8_t* p = base + c8 + t * (kL64Letters * 8);
+#pragma unroll
+      for (int k = 0; k < kChains; ++k) {
+        const uint2 v = *(const uint2*)(p + k * (kL64Steps * kL64Letters * 8));
+        acc[k].x ^= v.x;
+        acc[k].y += v.y;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) let[j] = __builtin_amdgcn_alignbit(let[j], let[j], 8);
+  }
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kChains; ++k) s ^= acc[k].x + acc[k].y;
+  out[(int64_t)blockIdx.x * blockDim.x + threadIdx.x] = (int32_t)s;
+}
+
 // Four independent 16-byte loads in flight per lane before their stores.
 __global__ __launch_bounds__(kProbeThreads) void k_probe_copy(const int4* __restrict__ src, int4* __restrict__ dst,
                                                               int64_t n) {
@@ -115,7 +165,7 @@ extern "C" int plast_probe_peak(int32_t kind, void* d_buf, size_t buf_bytes, int
   using namespace plast;
   hipStream_t stream = (hipStream_t)stream_;
   if (!d_buf || !rate) return set_error(PLAST_E_ARG, "plast_probe_peak: null pointer");
-  if (kind < PLAST_PROBE_VALU_I32 || kind > PLAST_PROBE_HBM_COPY)
+  if (kind < PLAST_PROBE_VALU_I32 || kind > PLAST_PROBE_LDS_B64)
     return set_error(PLAST_E_ARG, "plast_probe_peak: unknown kind %d", (int)kind);
   if (reps < 1 || reps > 100) return set_error(PLAST_E_ARG, "plast_probe_peak: reps must be in 1..100");
   if ((uintptr_t)d_buf & 255) return set_error(PLAST_E_ARG, "plast_probe_peak: buffer must be 256-byte aligned");
@@ -124,7 +174,7 @@ extern "C" int plast_probe_peak(int32_t kind, void* d_buf, size_t buf_bytes, int
   if (buf_bytes < need)
     return set_error(PLAST_E_WORKSPACE, "plast_probe_peak: buffer of %zu bytes, needs at least %zu", buf_bytes, need);
   // about 3.5 ms per launch at the published peaks (1.7 ms for the LDS probe)
-  const int iters = kind == PLAST_PROBE_LDS ? 8192 : 16384;
+  const int iters = kind == PLAST_PROBE_LDS ? 8192 : kind == PLAST_PROBE_LDS_B64 ? 512 : 16384;
   const double threads = (double)kProbeBlocks * kProbeThreads;
   double work = 0.0;  // operations, lookups or bytes per launch
   int64_t n16 = 0;
@@ -133,6 +183,7 @@ extern "C" int plast_probe_peak(int32_t kind, void* d_buf, size_t buf_bytes, int
     case PLAST_PROBE_VALU_PK_I16:
     case PLAST_PROBE_VALU_PK_F16: work = threads * iters * kChains * 4.0; break;
     case PLAST_PROBE_LDS: work = threads * iters * kChains; break;
+    case PLAST_PROBE_LDS_B64: work = threads * iters * kL64Steps * kChains * 8.0; break;
     default:
       n16 = (int64_t)(buf_bytes / 2 / 16);
       work = 2.0 * 16.0 * (double)n16;
@@ -159,6 +210,9 @@ extern "C" int plast_probe_peak(int32_t kind, void* d_buf, size_t buf_bytes, int
         break;
       case PLAST_PROBE_LDS:
         hipLaunchKernelGGL(k_probe_lds, dim3(kProbeBlocks), dim3(kProbeThreads), 0, stream, out, iters, r + 1);
+        break;
+      case PLAST_PROBE_LDS_B64:
+        hipLaunchKernelGGL(k_probe_lds_b64, dim3(kProbeBlocks), dim3(kProbeThreads), 0, stream, out, iters, r + 1);
         break;
       default: {
         const int4* src = (const int4*)d_buf;

@@ -66,3 +66,32 @@ def test_machine_info_runs_anywhere():
 def test_published_peaks_cover_every_probe():
     from paper_0804_3643_amd import binding
     assert set(bench.PUBLISHED_PEAKS) == set(binding.PROBES)
+
+
+def test_gapped_cells_equals_a_cell_by_cell_count(cfg0, cfg0_hits):
+    """DP cells of the gapped filter (the roofline's work count) against a plain
+    count of the in-band cells of both clipped windows of every hit."""
+    h = cfg0_hits[0].numpy().astype(np.int64)[:300]
+    la = np.diff(cfg0.bank1.seq_start) - 20
+    lb = np.diff(cfg0.bank2.seq_start) - 20
+    want = 0
+    for s1, p1, s2, p2, _ in h:
+        for lx, ly in ((min(64, la[s1] - p1), min(64, lb[s2] - p2)), (min(64, p1), min(64, p2))):
+            want += sum(1 for i in range(lx + 1) for j in range(ly + 1) if abs(i - j) <= 16) - 1
+    assert bench.gapped_cells(np, cfg0.bank1, cfg0.bank2, h) == want
+
+
+def test_golden_check_accepts_the_oracle_and_rejects_a_slip(cfg0, cfg0_hits):
+    h, _ = cfg0_hits
+    g = torch.from_numpy(C.gapped_scores(cfg0.bank1, cfg0.bank2, h.numpy()).astype(np.int32))
+    n_ext = int(sum(np.diff(C.build_index(cfg0.bank1)[0]) * np.diff(C.build_index(cfg0.bank2)[0])))
+    sha = [cfg0.bank1.sha256(), cfg0.bank2.sha256()]
+    p = torch.randperm(h.shape[0])
+    ok = bench.golden_check("0", h[p], g[p], params.S2, n_ext, cfg0.bank1, sha)
+    assert ok["equal"] and ok["mismatch"] == []
+    g2 = g.clone()
+    g2[5] += 1
+    bad = bench.golden_check("0", h, g2, params.S2, n_ext, cfg0.bank1, sha)
+    assert not bad["equal"] and "hits_gscore" in bad["mismatch"]
+    assert not bench.golden_check("0", h, g, params.S2, n_ext + 1, cfg0.bank1, sha)["equal"]
+    assert not bench.golden_check("0", h, g, params.S2, n_ext, cfg0.bank1, sha[::-1])["equal"]
