@@ -39,7 +39,11 @@
 // an x letter against two consecutive y letters, i.e. of two neighbouring cells
 // of a row, so one lookup per side serves two cells.  The workgroup size is a
 // launch-shape parameter (128, 256 or 512 threads); each resident workgroup
-// builds the 37 KB table once and strides over the hits.
+// builds the 37 KB table once and strides over the hits.  The last four blocks
+// of rows are peeled at compile time and skip their cells right of column 64,
+// which no window reaches (about 5% of the band).
+#include <type_traits>
+
 #include "plast_internal.h"
 
 namespace plast {
@@ -190,6 +194,20 @@ constexpr int kPairDwords = kNLet * kPairRow;   // 9261 (37 KB of LDS)
 constexpr uint32_t kXRowBytes = 4 * kPairRow;
 static_assert(kPairDwords * 4 < 65536, "table offsets must fit 16 bits");
 
+// The last kTailBlocks blocks of the fast path (up to row 64) are peeled at
+// compile time, so that their cells right of column 64 are not computed.
+constexpr int kTailBlocks = 4;
+
+// Cell d (band index, column j = i + d - 16) of row r of block blk (rows
+// 4 blk + 1 ..): true when it lies left of column 0 or right of column 64.
+// Such a cell is outside every window (windows hold at most 64 letters): a cell
+// left of column 0 is -inf and feeds only cells left of column 0, and a cell
+// right of column 64 feeds only cells right of column 64, so neither changes a
+// cell inside.  blk < 0 (the generic body) skips nothing.
+__host__ __device__ constexpr bool gapped_skip_cell(int blk, int r, int d) {
+  return blk >= 0 && ((4 * blk + r + 1) + d - kGMaxBand < 0 || (4 * blk + r + 1) + d - kGMaxBand > kGMaxWin);
+}
+
 __device__ __forceinline__ gh2 gmax3(gh2 a, gh2 b, gh2 c) {
   return __builtin_elementwise_maximum(__builtin_elementwise_maximum(a, b), c);
 }
@@ -328,7 +346,12 @@ __device__ __forceinline__ void gapped_hit_f16(const GappedArgs& G, const uint32
   for (int t = 0; t < kAcc; ++t) acc[t] = NEG;
   int i0 = 1;
   const char* tb = (const char*)tbl;
-  for (; __builtin_amdgcn_readfirstlane(__ballot(i0 <= rows) != 0); i0 += kFBlock) {
+  // One block of kFBlock rows starting at row i0.  BLK >= 0 names the block
+  // (rows 4 BLK + 1 ..) at compile time: its cells outside every window are
+  // skipped (gapped_skip_cell); BLK < 0 is the generic body that computes every
+  // cell.
+  auto block = [&](auto blk_c) {
+    constexpr int BLK = decltype(blk_c)::value;
     // raw letters of the next block (x rows, and the y indices entering the band),
     // decoded after this block's rows
     const uint32_t nx4R = load4(L.A, L.qa + i0 + kFBlock - 1), nx4L = load4(L.A, L.qa - i0 - kFBlock - 3);
@@ -343,6 +366,7 @@ __device__ __forceinline__ void gapped_hit_f16(const GappedArgs& G, const uint32
     uint32_t A[kSeq], B[kSeq];
     auto issue = [&](int q) {
       const int r = q / kPairs, p = q % kPairs;
+      if (gapped_skip_cell(BLK, r, 2 * p) && gapped_skip_cell(BLK, r, 2 * p + 1)) return;
       const uint32_t yy = YY[2 * p + r];
       A[q] = *(const uint32_t*)(tb + xbR[r] + (yy & 0xffffu));
       B[q] = *(const uint32_t*)(tb + xbL[r] + (yy >> 16));
@@ -359,21 +383,27 @@ __device__ __forceinline__ void gapped_hit_f16(const GappedArgs& G, const uint32
       for (int c = 0; c < 2; ++c) {
         const int d = 2 * p + c;
         if (d < kGCells) {
-          const gh2 sc = __builtin_bit_cast(gh2, __builtin_amdgcn_perm(B[q], A[q], c ? 0x07060302u : 0x05040100u));
-          const gh2 diag = H[d] + sc;
-          const gh2 f = d + 1 < kGCells ? F[d + 1] : NEG;
-          const gh2 hh = gmax3(diag, e, f);
           // cell (i0 + r, d) lies on anti-diagonal 2 i0 - 16 + (2 r + d); in an odd
           // row it shares it with cell d + 2 of the row above, still in H[d + 2]
           const int t = 2 * r + d;
-          if (r & 1)
-            acc[t] = d + 2 < kGCells ? gmax3(acc[t], hh, H[d + 2]) : gmax(acc[t], hh);
-          else if (d < 2)
-            acc[t] = gmax(acc[t], hh);
-          const gh2 ho = hh - OP;
-          e = gmax(e, ho);
-          F[d] = gmax(f, ho);
-          H[d] = hh;
+          const bool own = !gapped_skip_cell(BLK, r, d);
+          const bool above = (r & 1) && d + 2 < kGCells && !gapped_skip_cell(BLK, r - 1, d + 2);
+          if (own) {
+            const gh2 sc = __builtin_bit_cast(gh2, __builtin_amdgcn_perm(B[q], A[q], c ? 0x07060302u : 0x05040100u));
+            const gh2 diag = H[d] + sc;
+            const gh2 f = d + 1 < kGCells ? F[d + 1] : NEG;
+            const gh2 hh = gmax3(diag, e, f);
+            if (r & 1)
+              acc[t] = above ? gmax3(acc[t], hh, H[d + 2]) : gmax(acc[t], hh);
+            else if (d < 2)
+              acc[t] = gmax(acc[t], hh);
+            const gh2 ho = hh - OP;
+            e = gmax(e, ho);
+            F[d] = gmax(f, ho);
+            H[d] = hh;
+          } else if (above) {
+            acc[t] = gmax(acc[t], H[d + 2]);
+          }
         }
       }
     }
@@ -404,7 +434,28 @@ __device__ __forceinline__ void gapped_hit_f16(const GappedArgs& G, const uint32
       xbR[t] = (xr / kScale) * kXRowBytes;
       xbL[t] = (xl / kScale) * kXRowBytes;
     }
-  }
+    i0 = i1;
+  };
+  // The generic body runs the blocks up to row 4 (kNBlocks - kTailBlocks), the
+  // peeled bodies the tail blocks; every block runs only while a lane of the
+  // wavefront still has rows.  Scheduling barriers keep each peeled block's
+  // instructions inside it.  (Peeling the head blocks too, whose cells left of
+  // column 0 are wasted, made the register allocation spill.)
+  static_assert(kFBlock == 4 && kGMaxWin == 64 && kTailBlocks <= 4, "peeled blocks assume 4-row blocks over 64 rows");
+  constexpr int kNBlocks = kGMaxWin / kFBlock;
+  auto more = [&]() { return __builtin_amdgcn_readfirstlane(__ballot(i0 <= rows) != 0) != 0; };
+  auto peeled = [&](auto blk_c) {
+    if (more()) {
+      __builtin_amdgcn_sched_barrier(0);
+      block(blk_c);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  };
+  while (i0 <= kFBlock * (kNBlocks - kTailBlocks) && more()) block(std::integral_constant<int, -1>{});
+  if constexpr (kTailBlocks >= 4) peeled(std::integral_constant<int, kNBlocks - 4>{});
+  if constexpr (kTailBlocks >= 3) peeled(std::integral_constant<int, kNBlocks - 3>{});
+  if constexpr (kTailBlocks >= 2) peeled(std::integral_constant<int, kNBlocks - 2>{});
+  if constexpr (kTailBlocks >= 1) peeled(std::integral_constant<int, kNBlocks - 1>{});
   {
     const _Float16 base = (_Float16)(2 * i0 - kGMaxBand);
 #pragma unroll

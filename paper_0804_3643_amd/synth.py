@@ -351,6 +351,31 @@ def make_workload(cfg: int, plants: bool = True, scale: float = 1.0) -> Workload
     return Workload(cfg, Bank.from_seqs(s1), Bank.from_seqs(s2), planted, spec.description, pools)
 
 
+def shared_repeat_variant(w: Workload, frac: float = 0.01, letters=(0, 9), run=(100, 400),
+                          seed: int = 6513) -> Workload:
+    """A variant of a workload in which ``frac`` of the sequences of each bank
+    carry one run (length U[run], clamped to the sequence) drawn from the same
+    small alphabet ``letters`` (default A and L) in both banks, so that the few
+    seed keys of that alphabet are heavy in both banks at once.  The banks are
+    copied; the workload's own streams are not touched (the runs come from
+    SeedSequence(seed))."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed)))
+    alpha = np.asarray(letters, dtype=np.uint8)
+    banks = []
+    for bank in (w.bank1, w.bank2):
+        codes = bank.codes.copy()
+        lens = bank.lengths
+        chosen = rng.choice(bank.n_seqs, size=max(1, int(round(frac * bank.n_seqs))), replace=False)
+        for i in np.sort(chosen):
+            L = min(int(rng.integers(run[0], run[1] + 1)), int(lens[i]))
+            off = int(rng.integers(0, int(lens[i]) - L + 1))
+            a = int(bank.seq_start[i]) + off
+            codes[a:a + L] = rng.choice(alpha, size=L)
+        banks.append(Bank(codes, bank.seq_start.copy()))
+    return Workload(w.cfg, banks[0], banks[1], w.plants, w.description + "; %.0f%% of each bank's sequences carry a "
+                    "run over the same %d letters" % (100 * frac, len(alpha)), w.repeat_pools)
+
+
 def random_bank(rng, n, lo=1, hi=60, alphabet_size=20) -> Bank:
     """Small random bank for tests: ``n`` sequences of length U[lo, hi]."""
     lens = rng.integers(lo, hi + 1, size=n)

@@ -1,8 +1,11 @@
 """Full-size skewed configuration 2 (20,000 x 300,000 proteins, 5% carrying
 low-complexity repeats) on the GPU: index parity, the number of extensions,
-PLAIN == BATCHED == other launch shapes == graph replay, and the hits and gapped
-scores of sampled keys (the 32 heaviest, the 4 lightest, 256 random) against
-the oracle."""
+the whole hit list and every gapped score of the graph replay against the
+oracle's full-size golden (count and 64-bit multiset digests, whole run and per
+block of 80 keys), PLAIN == BATCHED == other launch shapes == graph replay, and
+the hits and gapped scores of sampled keys (the 32 heaviest, the 4 lightest,
+256 random) against the oracle computed key by key."""
+import os
 import sys
 
 import numpy as np
@@ -12,6 +15,9 @@ import torch
 from oracle import coracle as C
 from oracle import plast_oracle as O
 from paper_0804_3643_amd import params, synth
+
+sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+import fullsize  # noqa: E402
 
 pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
@@ -72,6 +78,12 @@ def test_config2_full_size():
     k, s = _pair_sorted(gh)
     assert torch.equal(k, kb) and torch.equal(s, sb_)
     del k, s
+    _say("cfg2 whole run against the oracle's full-size golden")
+    golden = fullsize.load(2)
+    assert golden is not None and golden["bank_sha256"] == [w.bank1.sha256(), w.bank2.sha256()]
+    got = fullsize.device_summary(gh, gg, params.S2, w.bank1, r["n_ext"])
+    assert fullsize.compare(golden, got) == [], fullsize.compare(golden, got)
+    assert int(gp.sum().item()) == golden["n_pass"]
     # sampled keys against the oracle: 32 heaviest (6.5e9 extensions), 4 lightest, 256 random
     work = np.diff(idx1[0]) * n2
     nz = np.nonzero(work)[0]
@@ -92,3 +104,50 @@ def test_config2_full_size():
     assert np.array_equal(gg.cpu().numpy()[sel].astype(np.int64), g_ref)
     assert np.array_equal(gp.cpu().numpy()[sel].astype(bool), g_ref >= params.S2)
     pl.close()
+
+
+@pytest.mark.timeout(900)
+def test_config2_keys_heavy_in_both_banks():
+    """Configuration 2 with 1% of each bank's sequences carrying a run over the
+    same two letters (A, L), so that 16 seed keys hold 4,000-6,600 bank-1 and
+    60,000-177,000 bank-2 occurrences at once: the load balance of the
+    persistent schedule on keys heavy on both sides.  S1 is raised to 120 for
+    this test only, so that the repeat-against-repeat pairs (nearly all above
+    38) give about 3M hits.  PLAIN == BATCHED == other launch shapes exactly, the
+    number of extensions equals the oracle's, and the hits of the 4 heaviest
+    keys (2.3e9 extensions) and of 32 random keys equal the oracle's."""
+    from paper_0804_3643_amd import binding as B
+    B.load()
+    s1 = 120
+    _say("cfg2 shared-repeat variant generate")
+    w = synth.shared_repeat_variant(synth.make_workload(2))
+    idx1, idx2 = C.build_index(w.bank1), C.build_index(w.bank2)
+    work = np.diff(idx1[0]) * np.diff(idx2[0])
+    ia = B.build_index(*B.bank_to_device(w.bank1, "cuda"))
+    ib = B.build_index(*B.bank_to_device(w.bank2, "cuda"))
+    _say("cfg2 variant batched (tuned-like shape)")
+    hb, n_ext = B.ungapped_extend(ia, ib, s1, mode="batched",
+                                  tuning={"item_cols": [2048, 8192, 16384, 16384], "xcd_queues": 8})
+    assert n_ext == int(work.sum())
+    kb, sb_ = _pair_sorted(hb)
+    assert bool((kb[1:] != kb[:-1]).all())
+    for t in ({"item_cols": [1024, 4096, 4096, 4096], "xcd_queues": 1}, None):
+        mode = "plain" if t is None else "batched"
+        _say("cfg2 variant %s %s" % (mode, t))
+        h, ne = B.ungapped_extend(ia, ib, s1, mode=mode, tuning=t)
+        k, s = _pair_sorted(h)
+        assert ne == n_ext and torch.equal(k, kb) and torch.equal(s, sb_), (mode, t)
+        del h, k, s
+    order = np.argsort(work)[::-1]
+    heavy = order[:4]
+    assert (np.diff(idx1[0])[heavy] > 4000).all() and (np.diff(idx2[0])[heavy] > 80000).all()
+    rng = np.random.default_rng(5)
+    keys = np.unique(np.concatenate([heavy, rng.choice(np.nonzero(work)[0], 32, replace=False)])).astype(np.int32)
+    _say("cfg2 variant oracle on %d keys (%.3g extensions)" % (len(keys), work[keys].sum()))
+    ref, _ = C.ungapped_hits(w.bank1, w.bank2, s1, keys=keys, idx1=idx1, idx2=idx2)
+    hh = hb.cpu().numpy().astype(np.int64)
+    c = w.bank1.codes
+    q = w.bank1.seq_start[hh[:, 0]] + hh[:, 1]
+    hk = O.seed_key(c[q].astype(np.int64), c[q + 1].astype(np.int64), c[q + 2].astype(np.int64),
+                    c[q + 3].astype(np.int64))
+    assert np.array_equal(O.canonical(hh[np.isin(hk, keys)]), ref)

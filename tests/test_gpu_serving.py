@@ -25,7 +25,8 @@ def setup():
     from paper_0804_3643_amd import binding as B
     from paper_0804_3643_amd import serving as S
     B.load()
-    w = synth.make_serving(n_resident=1_000_000, n_requests=24, max_query=60, scale=0.02)
+    # 10% of the serving resident bank: 100,000 proteins (about 30M residues)
+    w = synth.make_serving(n_resident=1_000_000, n_requests=24, max_query=60, scale=0.1)
     res = S.Resident(w.resident.codes, w.resident.seq_start)
     return B, S, w, res
 
