@@ -1,6 +1,10 @@
 // Stage 0, bank indexing (Sec. 3.3.1): subset-seed key of every word, then a
 // stable sort by key into CSR form (key_off, occ, occ_seq).
 //
+// Pass 1's counting kernel also validates the bank against its layout and
+// writes the scan codes (the letters scaled to table offsets) that the
+// extension kernels read.
+//
 // The sort is a two-pass LSD radix sort on the 14-bit key: the low 7 bits
 // (128 buckets), then the high 7 bits (69 buckets).  Each pass cuts its input
 // into tiles of kIxTile elements, one wavefront each (four per workgroup): a
@@ -99,74 +103,6 @@ __device__ __forceinline__ int seq_of(const int64_t* st, int s_cur, int s0, int6
   return s;
 }
 
-// Validation and scan codes, position-parallel (so that banks of many short
-// sequences, such as translated fragments, keep every lane busy).  Each
-// wavefront takes kCheckChunk consecutive positions of [0, scan_len), two
-// tiles: it takes the sequence holding its first position from the tile table,
-// loads the starts its positions can meet into LDS and walks its positions in
-// order.  Position p is a residue iff some
-// sequence s has seq_start[s] <= p < seq_start[s + 1] - kPadLen; every other
-// position below n_padded must hold the separator code, and the tail slack is
-// set to it.
-constexpr int64_t kCheckChunk = 2 * kIxTile;
-constexpr int kCheckStarts = 4;  // 256 starts: a chunk holds at most 205
-
-__global__ __launch_bounds__(64 * kIxWaves) void k_codes_check(const uint8_t* __restrict__ codes,
-                                                              const int64_t* __restrict__ seq_start, int32_t n_seqs,
-                                                              int64_t n_padded, const int32_t* __restrict__ tile_seq,
-                                                              int64_t tiles, uint8_t* __restrict__ scan,
-                                                              int64_t scan_len, int32_t* __restrict__ err) {
-  __shared__ int64_t st_all[kIxWaves][64 * kCheckStarts];
-  const int lane = lane_id();
-  const int64_t chunk = (int64_t)blockIdx.x * kIxWaves + (threadIdx.x >> 6);
-  const int64_t beg = chunk * kCheckChunk;
-  if (beg >= scan_len || (*err & 1)) return;  // no walk over a bad layout
-  const int64_t end = min(beg + kCheckChunk, scan_len);
-  int64_t* st = st_all[threadIdx.x >> 6];
-  // s0: the last sequence with seq_start <= beg (-1 before the first one)
-  int s0 = n_seqs - 1;
-  if (beg < n_padded && n_seqs > 0) {
-    s0 = min(max(tile_seq[beg / kIxTile], 0), n_seqs - 1);
-    if (seq_start[s0] > beg) s0 = -1;
-  }
-  load_starts<kCheckStarts>(seq_start, n_seqs, s0, st, lane);
-  wave_sync();
-  int s_cur = s0;
-  bool bad = false;
-  // 256 positions per round, four consecutive ones per lane (scan is 256-byte
-  // aligned and scan_len a multiple of 256, so each lane writes one dword)
-  for (int64_t base = beg; base < end; base += 256) {
-    const int64_t p = base + 4 * lane;
-    // sequence holding p: a 256-position window meets at most 13 starts, so
-    // lanes 0..15 read the next 16 from the table and every lane counts them
-    const int64_t nxt = lane < 16 ? st[min(s_cur - s0 + lane, 64 * kCheckStarts - 1)] : INT64_MAX;
-    int s = s_cur;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) s += p >= __shfl(nxt, k) ? 1 : 0;
-    // starts of sequences s + 1 and s + 2 (seq_start[n_seqs] == n_padded); at
-    // most one of the lane's four positions begins a sequence
-    const int64_t e0 = s + 1 < n_seqs ? st[min(s - s0, 64 * kCheckStarts - 1)] : n_padded;
-    const int64_t e1 = s + 2 < n_seqs ? st[min(s + 1 - s0, 64 * kCheckStarts - 1)] : n_padded;
-    uint32_t out = 0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int64_t q = p + k;
-      uint32_t c = kPadCode;
-      if (q < n_padded) {
-        const bool next = q >= e0;
-        const bool residue = s + (next ? 1 : 0) >= 0 && q < (next ? e1 : e0) - kPadLen;
-        c = codes[q];
-        bad |= residue ? (c >= 20) : (c != kPadCode);
-        if (!(residue && c < 20)) c = kPadCode;
-      }
-      out |= (c * kScale) << (8 * k);
-    }
-    *(uint32_t*)(scan + p) = out;
-    s_cur = __shfl(s + (p + 3 >= e0 ? 1 : 0), 63);
-  }
-  if (bad) atomicOr(err, 2);
-}
-
 // Lanes of the wavefront holding a valid element with the same 7-bit digit.
 __device__ __forceinline__ uint64_t digit_peers(int d, bool valid) {
   uint64_t peers = __ballot(valid);
@@ -177,30 +113,6 @@ __device__ __forceinline__ uint64_t digit_peers(int d, bool valid) {
     peers &= bit ? m : ~m;
   }
   return peers;
-}
-
-// Pass 1, counting: histogram of the low digit of the words starting in the
-// tile's positions.
-__global__ __launch_bounds__(64 * kIxWaves) void k_ix_count1(const uint8_t* __restrict__ codes, int64_t n_padded,
-                                                            int64_t tiles, SeedClasses sc,
-                                                            int32_t* __restrict__ hist) {
-  __shared__ int32_t cnt_all[kIxWaves][kD0];
-  const int lane = lane_id();
-  const int64_t tile = (int64_t)blockIdx.x * kIxWaves + (threadIdx.x >> 6);
-  if (tile >= tiles) return;
-  int32_t* cnt = cnt_all[threadIdx.x >> 6];
-  cnt[lane] = 0;
-  cnt[lane + 64] = 0;
-  wave_sync();
-  const int64_t beg = tile * kIxTile;
-  const int64_t end = min(beg + kIxTile, n_padded - (kSeed - 1));
-  for (int64_t q = beg + lane; q < end; q += 64) {
-    const int key = word_key(codes, q, end, sc);
-    if (key >= 0) atomicAdd(&cnt[key & (kD0 - 1)], 1);
-  }
-  wave_sync();
-  hist[(int64_t)lane * tiles + tile] = cnt[lane];
-  hist[(int64_t)(lane + 64) * tiles + tile] = cnt[lane + 64];
 }
 
 // A tile's bucket tables from the scanned histogram (bucket-major over
@@ -270,6 +182,95 @@ __device__ __forceinline__ int word_key_lds(const uint8_t* cl, int off, bool in_
   const int w0 = cl[off], w1 = cl[off + 1], w2 = cl[off + 2], w3 = cl[off + 3];
   if (w0 >= 20 || w1 >= 20 || w2 >= 20 || w3 >= 20) return -1;
   return seed_key_dev(sc, w0, w1, w2, w3);
+}
+
+// Pass 1, counting, fused with the validation of the bank and the writing of
+// the scan codes: one wavefront per tile of kIxTile positions (tiles past the
+// bank write the scan codes' tail slack only).  The tile's codes (and the 64
+// after it) are staged in LDS once.  Validation: position p is a residue iff
+// some sequence s has seq_start[s] <= p < seq_start[s + 1] - kPadLen; residues
+// must be < 20 and every other position below n_padded the separator (the
+// starts the tile's positions can meet are loaded into LDS; a 256-position
+// round meets at most 13 of them).  The scan codes are the validated codes
+// times kScale.  The histogram counts the low digit of the key of every word
+// starting in the tile, from the raw codes, as the scattering pass does: on a
+// valid bank a word of four codes < 20 lies inside one sequence.  After a
+// layout error nothing is validated or written but the histogram.
+__global__ __launch_bounds__(64 * kIxWaves) void k_ix_check_count1(
+    const uint8_t* __restrict__ codes, const int64_t* __restrict__ seq_start, int32_t n_seqs, int64_t n_padded,
+    const int32_t* __restrict__ tile_seq, int64_t tiles, uint8_t* __restrict__ scan, int64_t scan_len, SeedClasses sc,
+    int32_t* __restrict__ hist, int32_t* __restrict__ err) {
+  __shared__ int64_t st_all[kIxWaves][64 * kTileStarts];
+  __shared__ int32_t cnt_all[kIxWaves][kD0];
+  __shared__ __align__(16) uint8_t cl_all[kIxWaves][kIxTile + 64];  // read as dwords
+  const int lane = lane_id(), wv = threadIdx.x >> 6;
+  const int64_t tile = (int64_t)blockIdx.x * kIxWaves + wv;
+  const int64_t beg = tile * kIxTile;
+  if (tile >= tiles && beg >= scan_len) return;
+  int32_t* cnt = cnt_all[wv];
+  int64_t* st = st_all[wv];
+  uint8_t* cl = cl_all[wv];
+  const int64_t cend = min(beg + kIxTile + 64, n_padded);  // codes staged [beg, cend), separators after
+#pragma unroll 4
+  for (int r = 0; r < kIxTile / 64 + 1; ++r) {
+    const int64_t p = beg + r * 64 + lane;
+    cl[r * 64 + lane] = p < cend ? codes[p] : (uint8_t)kPadCode;
+  }
+  cnt[lane] = 0;
+  cnt[lane + 64] = 0;
+  const bool layout_ok = !(*err & 1);
+  int s0 = n_seqs - 1;  // the last sequence with seq_start <= beg (-1 before the first one)
+  if (layout_ok && beg < n_padded && n_seqs > 0) {
+    s0 = min(max(tile_seq[min(tile, tiles - 1)], 0), n_seqs - 1);
+    if (seq_start[s0] > beg) s0 = -1;
+  }
+  if (layout_ok) load_starts<kTileStarts>(seq_start, n_seqs, s0, st, lane);
+  wave_sync();
+  if (layout_ok) {
+    int s_cur = s0;
+    bool bad = false;
+    const int64_t vend = min(beg + kIxTile, scan_len);
+    // 256 positions per round, four consecutive ones per lane (scan is
+    // 256-byte aligned and scan_len a multiple of 256: one dword per lane)
+    for (int64_t base = beg; base < vend; base += 256) {
+      const int64_t p = base + 4 * lane;
+      const int64_t nxt = lane < 16 ? st[min(s_cur - s0 + lane, 64 * kTileStarts - 1)] : INT64_MAX;
+      int s = s_cur;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) s += p >= __shfl(nxt, k) ? 1 : 0;
+      // starts of sequences s + 1 and s + 2 (seq_start[n_seqs] == n_padded); at
+      // most one of the lane's four positions begins a sequence
+      const int64_t e0 = s + 1 < n_seqs ? st[min(s - s0, 64 * kTileStarts - 1)] : n_padded;
+      const int64_t e1 = s + 2 < n_seqs ? st[min(s + 1 - s0, 64 * kTileStarts - 1)] : n_padded;
+      const uint32_t raw = *(const uint32_t*)(cl + (p - beg));
+      uint32_t out = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int64_t q = p + k;
+        uint32_t c = kPadCode;
+        if (q < n_padded) {
+          const bool next = q >= e0;
+          const bool residue = s + (next ? 1 : 0) >= 0 && q < (next ? e1 : e0) - kPadLen;
+          c = (raw >> (8 * k)) & 0xffu;
+          bad |= residue ? (c >= 20) : (c != kPadCode);
+          if (!(residue && c < 20)) c = kPadCode;
+        }
+        out |= (c * kScale) << (8 * k);
+      }
+      *(uint32_t*)(scan + p) = out;
+      s_cur = __shfl(s + (p + 3 >= e0 ? 1 : 0), 63);
+    }
+    if (bad) atomicOr(err, 2);
+  }
+  if (tile >= tiles) return;
+  const int64_t end = min(beg + kIxTile, n_padded - (kSeed - 1));  // word starts [beg, end)
+  for (int off = 0; beg + off < end; off += 64) {
+    const int key = word_key_lds(cl, off + lane, beg + off + lane < end, sc);
+    if (key >= 0) atomicAdd(&cnt[key & (kD0 - 1)], 1);
+  }
+  wave_sync();
+  hist[(int64_t)lane * tiles + tile] = cnt[lane];
+  hist[(int64_t)(lane + 64) * tiles + tile] = cnt[lane + 64];
 }
 
 __global__ __launch_bounds__(64 * kIxWaves) void k_ix_scatter1(
@@ -628,15 +629,15 @@ int index_enqueue(const uint8_t* d_codes, const int64_t* d_seq_start, int32_t n_
   hipLaunchKernelGGL(k_clear2, dim3(1), dim3(64), 0, stream, d_err);
   hipLaunchKernelGGL(k_layout_check, dim3((unsigned)((n_seqs + 1 + 255) / 256)), dim3(256), 0, stream, d_seq_start,
                      n_seqs, n_padded, tile_seq, W.tiles1, d_err);
-  const int64_t chunks = (scan_len + kCheckChunk - 1) / kCheckChunk;
-  hipLaunchKernelGGL(k_codes_check, dim3((unsigned)((chunks + kIxWaves - 1) / kIxWaves)), dim3(64 * kIxWaves), 0,
-                     stream, d_codes, d_seq_start, n_seqs, n_padded, (const int32_t*)tile_seq, W.tiles1, scan,
-                     scan_len, d_err);
   // After a layout error the passes that read the tile table or the word
   // arrays return at once and key_off says the index holds no word.
   const unsigned g1 = (unsigned)((W.tiles1 + kIxWaves - 1) / kIxWaves);
   const unsigned g2 = (unsigned)((W.tiles2 + kIxWaves - 1) / kIxWaves);
-  hipLaunchKernelGGL(k_ix_count1, dim3(g1), dim3(64 * kIxWaves), 0, stream, d_codes, n_padded, W.tiles1, sc, hist1);
+  const int64_t tiles_scan = (scan_len + kIxTile - 1) / kIxTile;  // tiles covering the scan codes and their slack
+  const int64_t tiles_c = tiles_scan > W.tiles1 ? tiles_scan : W.tiles1;
+  hipLaunchKernelGGL(k_ix_check_count1, dim3((unsigned)((tiles_c + kIxWaves - 1) / kIxWaves)), dim3(64 * kIxWaves), 0,
+                     stream, d_codes, d_seq_start, n_seqs, n_padded, (const int32_t*)tile_seq, W.tiles1, scan,
+                     scan_len, sc, hist1, d_err);
   exclusive_scan_i32(hist1, kD0 * W.tiles1, total, tmp, stream);
   hipLaunchKernelGGL(k_ix_scatter1, dim3(g1), dim3(64 * kIxWaves), 0, stream, d_codes, d_seq_start, n_seqs,
                      n_padded, W.tiles1, sc, (const int32_t*)tile_seq, (const int32_t*)d_err, (const int32_t*)hist1,
