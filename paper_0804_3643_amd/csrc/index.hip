@@ -88,20 +88,6 @@ __device__ __forceinline__ void load_starts(const int64_t* __restrict__ seq_star
   }
 }
 
-// The sequence holding position q, for a window of 64 consecutive positions
-// whose first one lies in sequence s_cur (or before the first one, -1).  Every
-// sequence takes at least kPadLen positions (its separator run), so a window
-// meets at most 4 sequence starts: lanes 0..7 read the next 8 from the table
-// (st[k] is start s0 + 1 + k) and every lane counts those at or before q.
-template <int K>
-__device__ __forceinline__ int seq_of(const int64_t* st, int s_cur, int s0, int64_t q, int lane) {
-  const int j = min(s_cur - s0 + lane, 64 * K - 1);
-  const int64_t nxt = lane < 8 ? st[j] : INT64_MAX;
-  int s = s_cur;
-#pragma unroll
-  for (int k = 0; k < 8; ++k) s += q >= __shfl(nxt, k) ? 1 : 0;
-  return s;
-}
 
 // Lanes of the wavefront holding a valid element with the same 7-bit digit.
 __device__ __forceinline__ uint64_t digit_peers(int d, bool valid) {
@@ -281,6 +267,7 @@ __global__ __launch_bounds__(64 * kIxWaves) void k_ix_scatter1(
   __shared__ int64_t st_all[kIxWaves][64 * kTileStarts];
   __shared__ uint32_t stage_all[kIxWaves][kIxTile];
   __shared__ uint8_t cl_all[kIxWaves][kIxTile + 64];
+  __shared__ uint32_t sbits_all[kIxWaves][kIxTile / 32], spre_all[kIxWaves][kIxTile / 32];
   const int lane = lane_id(), wv = threadIdx.x >> 6;
   const int64_t tile = (int64_t)blockIdx.x * kIxWaves + wv;
   if (tile >= tiles || n_seqs == 0 || (*err & 1)) return;
@@ -288,6 +275,7 @@ __global__ __launch_bounds__(64 * kIxWaves) void k_ix_scatter1(
   int64_t* st = st_all[wv];
   uint32_t* stage = stage_all[wv];
   uint8_t* cl = cl_all[wv];
+  uint32_t *sbits = sbits_all[wv], *spre = spre_all[wv];
   const int64_t beg = tile * kIxTile;
   const int64_t end = min(beg + kIxTile, n_padded - (kSeed - 1));  // word starts [beg, end)
   const int64_t cend = min(beg + kIxTile + 64, n_padded);          // codes staged [beg, cend)
@@ -298,9 +286,34 @@ __global__ __launch_bounds__(64 * kIxWaves) void k_ix_scatter1(
   }
   const int s0 = min(max(tile_seq[tile], 0), n_seqs - 1);
   load_starts<kTileStarts>(seq_start, n_seqs, s0, st, lane);
+  sbits[lane] = 0;
   const int nt = tile_tables<kD0>(offs, tiles, tile, (int64_t)err[1], gst, lst, cur, lane);
   wave_sync();
-  int s_cur = s0;
+  // The sequence of a position, s0 + the number of sequence starts in the tile
+  // at or before it: a bitmap of the starts (one 32-bit word per lane; at most
+  // 103 starts fall in a tile, all after its first position) and the count of
+  // starts before each word.
+#pragma unroll
+  for (int k = 0; k < kTileStarts; ++k) {
+    const int64_t o = st[k * 64 + lane] - beg;
+    if (o > 0 && o < kIxTile) atomicOr(&sbits[o >> 5], 1u << (o & 31));
+  }
+  wave_sync();
+  {
+    const uint32_t b = sbits[lane];
+    int incl = __popc(b);
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int t = __shfl_up(incl, o);
+      if (lane >= o) incl += t;
+    }
+    spre[lane] = (uint32_t)(incl - __popc(b));
+  }
+  wave_sync();
+  auto seq_at = [&](int off) {  // off = position - beg, in [0, kIxTile)
+    const int w = off >> 5;
+    return s0 + (int)spre[w] + __popc(sbits[w] & (~0u >> (31 - (off & 31))));
+  };
   const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
   auto entry = [&](int key, int off, int s) {
     return (uint32_t)key | ((uint32_t)(off + lane) << 14) | ((uint32_t)min(s - s0, 127) << 25);
@@ -315,12 +328,10 @@ __global__ __launch_bounds__(64 * kIxWaves) void k_ix_scatter1(
     for (int off = 0; beg + off < end; off += 64) {
       const int64_t q = beg + off + lane;
       const int key = word_key_lds(cl, off + lane, q < end, sc);
-      const int s = seq_of<kTileStarts>(st, s_cur, s0, q, lane);
       const uint64_t w = __ballot(key >= 0);
       const int at = nw + __popcll(w & below);
-      if (key >= 0 && at < kIxTile / 2) comp[at] = entry(key, off, s);
+      if (key >= 0 && at < kIxTile / 2) comp[at] = entry(key, off, seq_at(off + lane));
       nw += __popcll(w);
-      s_cur = __shfl(s, 63);
     }
     wave_sync();
     nw = min(nw, kIxTile / 2);
@@ -334,10 +345,8 @@ __global__ __launch_bounds__(64 * kIxWaves) void k_ix_scatter1(
     for (int off = 0; beg + off < end; off += 64) {
       const int64_t q = beg + off + lane;
       const int key = word_key_lds(cl, off + lane, q < end, sc);
-      const int s = seq_of<kTileStarts>(st, s_cur, s0, q, lane);
       const int l = rank_in_tile(key & (kD0 - 1), key >= 0, cur, below);
-      if (key >= 0 && (unsigned)l < (unsigned)kIxTile) stage[l] = entry(key, off, s);
-      s_cur = __shfl(s, 63);
+      if (key >= 0 && (unsigned)l < (unsigned)kIxTile) stage[l] = entry(key, off, seq_at(off + lane));
     }
   }
   wave_sync();
