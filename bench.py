@@ -618,17 +618,53 @@ def run_translated(args, plastx=False):
     n_hits = int(h.shape[0])
     n_pass = int(pbuf[:n_hits].sum().item())
     frag_tables = [f_t.cpu().numpy() for (_c, _s, f_t) in res]
+    # the whole run against the oracle's full-size golden: the fragment banks
+    # byte for byte, then every hit and gapped score
+    log("whole run against the oracle's golden")
+    sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
+    import fullsize
+    gkey = "x" if plastx else "3"
+    golden = fullsize.load(gkey)
+    frag_banks = [synth.Bank(c_t.cpu().numpy(), s_t.cpu().numpy()) for (c_t, s_t, _f) in res]
+    if plastx:
+        banks_sha = [fullsize.sha256_arrays(w.dna1.codes, w.dna1.start), fullsize.sha256_arrays(w.dna2.codes, w.dna2.start)]
+    else:
+        banks_sha = [w.bank1.sha256(), fullsize.sha256_arrays(w.dna.codes, w.dna.start)]
+    if golden is None:
+        gcheck = {"golden": None, "equal": False, "mismatch": ["no stored golden"]}
+    elif golden["bank_sha256"] != banks_sha:
+        gcheck = {"golden": os.path.basename(fullsize.golden_path(gkey)), "equal": False,
+                  "mismatch": ["generated banks differ from the golden's"]}
+    else:
+        bad = []
+        for fb, ft, ref in zip(frag_banks, frag_tables, golden["fragments"]):
+            if (ft.shape[0] != ref["n"] or fullsize.sha256_arrays(fb.codes) != ref["codes_sha256"] or
+                    fullsize.sha256_arrays(fb.seq_start.astype(np.int64)) != ref["seq_start_sha256"] or
+                    fullsize.sha256_arrays(np.ascontiguousarray(ft, dtype=np.int32)) != ref["table_sha256"]):
+                bad.append("fragment bank")
+        got = fullsize.device_summary(h, gbuf[:n_hits], params.S2, frag_banks[0] if plastx else w.bank1, n_ext)
+        bad += fullsize.compare(golden, got)
+        gcheck = {"golden": os.path.basename(fullsize.golden_path(gkey)), "equal": not bad, "mismatch": bad,
+                  "n_hits": got["n_hits"], "n_pass": got["n_pass"], "digest": got["hits_gscore"]}
+    if not gcheck["equal"]:
+        log("MISMATCH against the oracle's golden: %s" % gcheck["mismatch"])
+        sys.exit(1)
     checks = None
     if not args.no_cpu_baseline:
         log("checks against the oracle")
         checks = translated_oracle_checks(B, np, synth, params, w, dnas, res, h, plastx)
+        if not (checks["translation_equals_oracle_on_sampled_dna"] and checks["hits_equal_oracle_on_24_sampled_keys"]):
+            log("MISMATCH against the oracle on the sampled DNA sequences or keys: %s" % checks)
+            sys.exit(1)
     name = "PLAST-X" if plastx else "TPLAST-N"
     out = {
         "metric": "%s: ungapped extensions/s, whole step including the six-frame translation%s"
                   % (name, " of both banks" if plastx else ""),
         "value": n_ext / (ms * 1e-3), "unit": "ext/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms, "higher_is_better": True, "dtype": "f16", "data": "synthetic",
+        "ms_per_step": ms, "higher_is_better": True, "dtype": "int16 (exact, carried in binary16)",
+        "data": "synthetic",
         "stages_device_ms": {"translate": stage[0], "index": stage[1], "ungapped": stage[2], "gapped": stage[3]},
+        "bit_exact": {"oracle_golden_whole_run": gcheck},
         "n_ext": n_ext, "n_hits": n_hits, "n_gapped_pass": n_pass,
         "n_fragments": [int(f.shape[0]) for f in frag_tables],
         "tuning": tuning.as_dict() if tuning is not None else None,
@@ -636,6 +672,54 @@ def run_translated(args, plastx=False):
         "config": {"workload": w.description, "dna_nt": [int(d.codes.shape[0]) for d in dnas]},
     }
     print(json.dumps(out, default=float), flush=True)
+
+
+def run_index_only(args):
+    """``--index-only``: stage 0 alone on the banks of configuration 1, 2 or 3
+    (for 3, the protein bank and the device translation of the DNA bank): each
+    index built once to set up and ``--steps`` times timed with the library's
+    HIP events, the CSR of the protein banks checked against the oracle's.
+    One JSON line; a profiling aid, not a headline."""
+    import numpy as np
+    import torch
+
+    from oracle import coracle as C
+    from paper_0804_3643_amd import binding as B
+    from paper_0804_3643_amd import synth
+
+    B.load()
+    dev = torch.device("cuda:0")
+    banks = []
+    if args.config == 3:
+        w = synth.make_tplastn()
+        codes, starts, _ = B.translate(*B.dna_to_device(w.dna, dev))
+        banks = [("proteins", w.bank1, B.bank_to_device(w.bank1, dev)), ("fragments", None, (codes, starts))]
+    else:
+        w = synth.make_workload(args.config)
+        banks = [("bank1", w.bank1, B.bank_to_device(w.bank1, dev)), ("bank2", w.bank2, B.bank_to_device(w.bank2, dev))]
+    out = {"metric": "index build (stage 0) device time per bank", "unit": "ms", "config": args.config, "banks": {}}
+    for name, host, (c, st) in banks:
+        ib, wb = B.index_bytes(c.numel(), st.numel() - 1)
+        buf, ws = B._alloc(ib, dev), B._alloc(wb, dev)
+        ix = B.build_index(c, st, workspace=ws, out_buf=buf)
+        B.timing_enable(True)
+        ms = []
+        for _ in range(args.steps):
+            ix = B.build_index(c, st, workspace=ws, out_buf=buf)
+            ms.append(B.timing_read()["index_ms"])
+        B.timing_enable(False)
+        rec = {"positions": int(c.numel()), "sequences": int(st.numel() - 1), "words": ix.n_words,
+               "ms_min": float(np.min(ms)), "ms_median": float(np.median(ms))}
+        if host is not None and not args.no_cpu_baseline:
+            k, o, q = C.build_index(host)
+            rec["csr_equals_oracle"] = bool(np.array_equal(ix.key_off().cpu().numpy(), k) and
+                                            np.array_equal(ix.occ_seq().cpu().numpy().astype(np.int64), o))
+            if not rec["csr_equals_oracle"]:
+                log("MISMATCH: index of %s differs from the oracle's" % name)
+                sys.exit(1)
+        out["banks"][name] = rec
+        log("%s: %d positions, %d words, %.3f ms" % (name, rec["positions"], rec["words"], rec["ms_min"]))
+    print(json.dumps(out), flush=True)
 
 
 def main():
@@ -666,6 +750,8 @@ def main():
                     help="skip the serving leg of the default run")
     ap.add_argument("--plastx", action="store_true",
                     help="PLAST-X: both banks nucleotide, translated on the device in six frames")
+    ap.add_argument("--index-only", action="store_true",
+                    help="only stage 0: time the index builds of the configuration's banks")
     ap.add_argument("--probes-only", action="store_true",
                     help="only the measured peaks (plast_probe_peak), e.g. under rocprofv3 counters")
     ap.add_argument("--no-stage32", dest="stage32", action="store_false",
@@ -685,6 +771,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.index_only:
+        run_index_only(args)
+        return
     if args.probes_only:
         B.load()
         print(json.dumps({"measured_peaks": measured_peaks(B, torch, dev), "machine": machine_info()}), flush=True)
@@ -725,8 +814,12 @@ def main():
     gbuf = torch.empty(cap, dtype=torch.int32, device=dev)
     pbuf = torch.empty(cap, dtype=torch.uint8, device=dev)
 
+    index_a_ms = []
+
     def step():
         xa = B.build_index(ca, sa, workspace=ws_idx, out_buf=buf_a)
+        if B.timing_on():  # the build synchronised its stream: bank a's index time is final
+            index_a_ms.append(B.timing_read()["index_ms"])
         xb = B.build_index(cb, sb, workspace=ws_idx, out_buf=buf_b)
         h, ne = ext.run(xa, xb)
         B.gapped_filter(xa, xb, h, params.S2, out=(gbuf, pbuf), tuning=tuning)
@@ -757,9 +850,11 @@ def main():
     stage_ms = {"index_ms": [], "plan_ms": [], "ungapped_ms": [], "gapped_ms": []}
     log("timing %d eager steps" % args.steps)
     t0 = time.perf_counter()
+    index_a_ms.clear()
     for _ in range(args.steps):
         hits, n_ext = step()
         t = B.timing_read()  # waits for this step's last kernel
+        t["index_ms"] += index_a_ms[-1]  # both banks' builds
         for k in stage_ms:
             stage_ms[k].append(t[k])
     torch.cuda.synchronize()

@@ -493,8 +493,18 @@ def canonical_hits(hits):
     return h[np.lexsort(h.T[::-1])]
 
 
+_timing = False
+
+
+def timing_on():
+    """Whether timing_enable(True) is in force (as last set through this module)."""
+    return _timing
+
+
 def timing_enable(on=True):
+    global _timing
     _check(load().plast_timing_enable(1 if on else 0), "plast_timing_enable")
+    _timing = bool(on)
 
 
 def probe_peak(kind, buf, reps=3, stream=None):
