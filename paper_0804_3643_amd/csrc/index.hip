@@ -18,8 +18,8 @@
 // position), independent of scheduling.  Pass 1 reads the codes (staged in
 // LDS) and writes one 64-bit entry per word (position, key, and the sequence
 // as an offset from the first sequence of the position's tile, which the
-// layout check records per tile); pass 2 writes occ, occ_seq and the sorted
-// keys, from which key_off is read off.
+// layout check records per tile); pass 2 writes occ and occ_seq, and key_off
+// follows from the two scanned histograms.
 #include "plast_internal.h"
 
 namespace plast {
@@ -382,14 +382,13 @@ __global__ __launch_bounds__(64 * kIxWaves) void k_ix_count2(const uint64_t* __r
 
 // Pass 2, scattering: the tile's words ranked within their high digit into
 // the tile's bucket order in LDS, eight rounds of loads in flight ahead of
-// the ranking, then written out bucket by bucket as occ, occ_seq and the
-// sorted key.
+// the ranking, then written out bucket by bucket as occ and occ_seq.
 constexpr int kBatch = 8;
 
 __global__ __launch_bounds__(64 * kIxWaves) void k_ix_scatter2(
     const uint64_t* __restrict__ words, const int32_t* __restrict__ tile_seq, int64_t tiles1,
     const int32_t* __restrict__ err, int64_t cap, int64_t tiles, const int32_t* __restrict__ offs, int32_t* __restrict__ occ,
-    int32_t* __restrict__ occ_seq, uint16_t* __restrict__ fkey) {
+    int32_t* __restrict__ occ_seq) {
   __shared__ int32_t gst_all[kIxWaves][kD0], lst_all[kIxWaves][kD0], cur_all[kIxWaves][kD0];
   __shared__ uint64_t stage_all[kIxWaves][kIxTile];
   const int lane = lane_id(), wv = threadIdx.x >> 6;
@@ -434,7 +433,6 @@ __global__ __launch_bounds__(64 * kIxWaves) void k_ix_scatter2(
     const uint32_t pos = (uint32_t)e;
     occ[slot] = (int32_t)pos;
     occ_seq[slot] = (int64_t)(pos >> 11) < tiles1 ? tile_seq[pos >> 11] + (int)((e >> 32) & 127u) : -1;
-    fkey[slot] = (uint16_t)key;
   }
 }
 
@@ -442,29 +440,44 @@ __global__ void k_clear2(int32_t* __restrict__ p) {
   if (threadIdx.x < 2) p[threadIdx.x] = 0;
 }
 
-// key_off from the sorted keys: the first slot of every key, and for keys with
-// no word the first slot of the next key that has one (n_words past the last).
-// After a layout error the index holds no word.  A fixed grid strides over the
-// words (their count is known only on the device).
-constexpr int kKeyOffBlocks = 4096;
-
-__global__ __launch_bounds__(256) void k_ix_key_off(const uint16_t* __restrict__ fkey,
+// key_off from the two scanned histograms, with no pass over the sorted words.
+// After pass 1 the word array is ordered by the low digit: the words whose low
+// digit is below lo are its first offs1[lo * tiles1] entries.  Pass 2 cuts that
+// array into tiles of kIxTile entries, and its scanned histogram holds, for
+// high digit d and tile t, the words of high digit below d plus those of high
+// digit d in the tiles before t.  So the words with key below k = d * 128 + lo
+// number offs2[d * tiles2 + t] for the tile t holding entry offs1[lo * tiles1],
+// plus the words of high digit d in that tile before the entry, which one
+// workgroup per low digit counts (fewer than kIxTile entries).  A key with no
+// word gets the first slot of the next key that has one, n_words past the
+// last.  After a layout error the index holds no word.
+__global__ __launch_bounds__(256) void k_ix_key_off(const uint64_t* __restrict__ words,
+                                                    const int32_t* __restrict__ offs1, int64_t tiles1,
+                                                    const int32_t* __restrict__ offs2, int64_t tiles2,
                                                     const int32_t* __restrict__ err, int64_t cap,
                                                     int64_t* __restrict__ key_off) {
-  const int64_t n = (err[0] & 1) ? 0 : min((int64_t)err[1], cap);
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < max(n, (int64_t)kNKeys + 1); i += stride) {
-    if (n == 0) {
-      key_off[i] = 0;  // i <= kNKeys here
-      continue;
+  __shared__ int32_t cnt[kD1];
+  const int lo = blockIdx.x;
+  const bool none = (err[0] & 1) != 0;
+  const int64_t n = none ? 0 : min((int64_t)err[1], cap);
+  for (int d = threadIdx.x; d < kD1; d += blockDim.x) cnt[d] = 0;
+  __syncthreads();
+  const int64_t start = none ? 0 : min(max((int64_t)offs1[(int64_t)lo * tiles1], (int64_t)0), n);
+  const int64_t t = start / kIxTile;
+  for (int64_t i = t * kIxTile + threadIdx.x; i < start; i += blockDim.x)
+    atomicAdd(&cnt[min((int)(words[i] >> (39 + kD0Bits)), kD1 - 1)], 1);
+  __syncthreads();
+  for (int d = threadIdx.x; d < kD1; d += blockDim.x) {
+    const int k = d * kD0 + lo;
+    if (k >= kNKeys) continue;
+    int64_t v = 0;
+    if (!none) {
+      const int64_t idx = (int64_t)d * tiles2 + t;
+      v = min((idx < (int64_t)kD1 * tiles2 ? (int64_t)offs2[idx] : n) + cnt[d], n);
     }
-    if (i >= n) continue;
-    const int key = min((int)fkey[i], kNKeys - 1);
-    const int prev = i > 0 ? min((int)fkey[i - 1], kNKeys - 1) : -1;
-    for (int k = prev + 1; k <= key; ++k) key_off[k] = i;
-    if (i == n - 1)
-      for (int k = key + 1; k <= kNKeys; ++k) key_off[k] = n;
+    key_off[k] = v;
   }
+  if (lo == 0 && threadIdx.x == 0) key_off[kNKeys] = n;
 }
 
 // ---------------------------------------------------------------- scan
@@ -576,13 +589,13 @@ IndexLayout index_layout(int64_t n_padded) {
 }
 
 // Workspace: [error words (256 B)] [tile table] [pass-1 histogram] [pass-2 histogram]
-// [scan scratch] [word entries between the passes (64-bit)] [sorted keys].
+// [scan scratch] [word entries between the passes (64-bit)].
 // The word arrays hold n_padded - kPadLen entries, a bound on the residues of any valid
 // layout that grows with n_padded alone, so a workspace sized for the largest
 // bank serves every smaller one whatever its number of sequences.
 struct IxWs {
   int64_t tiles1, tiles2, cap;
-  size_t tile_seq, hist1, hist2, tmp, words, fkey, total;
+  size_t tile_seq, hist1, hist2, tmp, words, total;
 };
 
 IxWs ix_ws(int64_t n_padded) {
@@ -604,8 +617,6 @@ IxWs ix_ws(int64_t n_padded) {
   off = align_up(off + scan_tmp_bytes(scan_n), 256);
   w.words = off;
   off = align_up(off + sizeof(uint64_t) * (size_t)w.cap, 256);
-  w.fkey = off;
-  off = align_up(off + sizeof(uint16_t) * (size_t)w.cap, 256);
   w.total = off;
   return w;
 }
@@ -630,7 +641,6 @@ int index_enqueue(const uint8_t* d_codes, const int64_t* d_seq_start, int32_t n_
   int32_t* hist2 = (int32_t*)(ws + W.hist2);
   void* tmp = ws + W.tmp;
   uint64_t* words = (uint64_t*)(ws + W.words);
-  uint16_t* fkey = (uint16_t*)(ws + W.fkey);
 
   SeedClasses sc = seed_classes();
   timing_mark(kStageIndex, false, stream);
@@ -656,11 +666,9 @@ int index_enqueue(const uint8_t* d_codes, const int64_t* d_seq_start, int32_t n_
   exclusive_scan_i32(hist2, kD1 * W.tiles2, nullptr, tmp, stream);
   hipLaunchKernelGGL(k_ix_scatter2, dim3(g2), dim3(64 * kIxWaves), 0, stream, (const uint64_t*)words,
                      (const int32_t*)tile_seq, W.tiles1, (const int32_t*)d_err, W.cap, W.tiles2,
-                     (const int32_t*)hist2, occ,
-                     occ_seq, fkey);
-  const int64_t nb = (W.cap > kNKeys ? W.cap : kNKeys + 1) / 256 + 1;
-  hipLaunchKernelGGL(k_ix_key_off, dim3((unsigned)(nb < kKeyOffBlocks ? nb : kKeyOffBlocks)), dim3(256), 0, stream,
-                     (const uint16_t*)fkey, (const int32_t*)d_err, W.cap, key_off);
+                     (const int32_t*)hist2, occ, occ_seq);
+  hipLaunchKernelGGL(k_ix_key_off, dim3(kD0), dim3(256), 0, stream, (const uint64_t*)words, (const int32_t*)hist1,
+                     W.tiles1, (const int32_t*)hist2, W.tiles2, (const int32_t*)d_err, W.cap, key_off);
   timing_mark(kStageIndex, true, stream);
   PLAST_HIP(hipGetLastError());
 
