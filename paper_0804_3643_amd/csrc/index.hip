@@ -28,14 +28,6 @@ namespace {
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
-__device__ __forceinline__ int word_key(const uint8_t* __restrict__ codes, int64_t q, int64_t end,
-                                        const SeedClasses& sc) {
-  if (q >= end) return -1;
-  int w0 = codes[q], w1 = codes[q + 1], w2 = codes[q + 2], w3 = codes[q + 3];
-  if ((w0 | w1 | w2 | w3) >= 32 || w0 >= 20 || w1 >= 20 || w2 >= 20 || w3 >= 20) return -1;
-  return seed_key_dev(sc, w0, w1, w2, w3);
-}
-
 constexpr int kIxTile = 2048;                       // elements per tile (32 rounds of 64)
 constexpr int kIxWaves = 4;                         // tiles (one per wavefront) per workgroup
 constexpr int kD0Bits = 7;                          // pass-1 digit: key & 127
@@ -163,11 +155,44 @@ __device__ __forceinline__ uint64_t word_entry(int64_t q, int seq_off, int key) 
 constexpr int kTileStarts = 2;  // 128 starts
 static_assert(kIxTile == 2048, "word staging packs a position offset in 11 bits");
 
-__device__ __forceinline__ int word_key_lds(const uint8_t* cl, int off, bool in_range, const SeedClasses& sc) {
-  if (!in_range) return -1;
-  const int w0 = cl[off], w1 = cl[off + 1], w2 = cl[off + 2], w3 = cl[off + 3];
-  if (w0 >= 20 || w1 >= 20 || w2 >= 20 || w3 >= 20) return -1;
-  return seed_key_dev(sc, w0, w1, w2, w3);
+
+// A tile's codes [beg, beg + kIxTile + 64) into LDS as dwords (separators past
+// n_padded), with dword loads when the codes are 4-byte aligned.
+__device__ __forceinline__ void stage_codes(const uint8_t* __restrict__ codes, int64_t beg, int64_t n_padded,
+                                            uint32_t* cl32, int lane) {
+  const int nb = (int)max(min(n_padded - beg, (int64_t)(kIxTile + 64)), (int64_t)0);  // code bytes in range
+  const bool aligned = (reinterpret_cast<uintptr_t>(codes) & 3) == 0;
+#pragma unroll
+  for (int r = 0; r < ((kIxTile + 64) / 4 + 63) / 64; ++r) {
+    const int j = r * 64 + lane;
+    if (j < (kIxTile + 64) / 4) {
+      const int o = 4 * j;
+      uint32_t v;
+      if (aligned && o + 4 <= nb) {
+        v = *(const uint32_t*)(codes + beg + o);
+      } else {
+        v = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v |= (uint32_t)(o + k < nb ? codes[beg + o + k] : (uint8_t)kPadCode) << (8 * k);
+      }
+      cl32[j] = v;
+    }
+  }
+}
+
+// Seed key of the word whose four codes are the bytes of w, or -1 unless all
+// four are residues (< 20).  ((w + 108 per byte) | w) has a byte's top bit set
+// iff that byte is >= 20; a carry out of a byte comes only from a byte >= 148,
+// which has its own top bit set.
+__device__ __forceinline__ int word_key4(uint32_t w, const SeedClasses& sc) {
+  if (((w + 0x6C6C6C6Cu) | w) & 0x80808080u) return -1;
+  return seed_key_dev(sc, (int)(w & 0xffu), (int)((w >> 8) & 0xffu), (int)((w >> 16) & 0xffu), (int)(w >> 24));
+}
+
+// Seed key of the word starting at byte off of the staged codes (-1 unless all
+// four codes are residues): two aligned dword reads and a funnel shift.
+__device__ __forceinline__ int word_key_at(const uint32_t* cl32, int off, const SeedClasses& sc) {
+  return word_key4(__builtin_amdgcn_alignbyte(cl32[(off >> 2) + 1], cl32[off >> 2], (uint32_t)(off & 3)), sc);
 }
 
 // Pass 1, counting, fused with the validation of the bank and the writing of
@@ -175,84 +200,110 @@ __device__ __forceinline__ int word_key_lds(const uint8_t* cl, int off, bool in_
 // bank write the scan codes' tail slack only).  The tile's codes (and the 64
 // after it) are staged in LDS once.  Validation: position p is a residue iff
 // some sequence s has seq_start[s] <= p < seq_start[s + 1] - kPadLen; residues
-// must be < 20 and every other position below n_padded the separator (the
-// starts the tile's positions can meet are loaded into LDS; a 256-position
-// round meets at most 13 of them).  The scan codes are the validated codes
-// times kScale.  The histogram counts the low digit of the key of every word
-// starting in the tile, from the raw codes, as the scattering pass does: on a
-// valid bank a word of four codes < 20 lies inside one sequence.  After a
+// must be < 20 and every other position below n_padded the separator.  The
+// residue positions of the tile come as a bitmap: the state at the tile's first
+// position, toggled at every sequence start and every residue end inside the
+// tile (a sequence with no residue toggles twice at one position), resolved by
+// a prefix xor within each lane's 32 positions and a prefix parity across the
+// lanes.  The scan codes are the validated codes times kScale.  The histogram
+// counts the low digit of the key of every word starting in the tile, from the
+// raw codes, as the scattering pass does (four word starts per lane and round):
+// on a valid bank a word of four codes < 20 lies inside one sequence.  After a
 // layout error nothing is validated or written but the histogram.
 __global__ __launch_bounds__(64 * kIxWaves) void k_ix_check_count1(
     const uint8_t* __restrict__ codes, const int64_t* __restrict__ seq_start, int32_t n_seqs, int64_t n_padded,
     const int32_t* __restrict__ tile_seq, int64_t tiles, uint8_t* __restrict__ scan, int64_t scan_len, SeedClasses sc,
     int32_t* __restrict__ hist, int32_t* __restrict__ err) {
-  __shared__ int64_t st_all[kIxWaves][64 * kTileStarts];
   __shared__ int32_t cnt_all[kIxWaves][kD0];
-  __shared__ __align__(16) uint8_t cl_all[kIxWaves][kIxTile + 64];  // read as dwords
+  __shared__ uint32_t rb_all[kIxWaves][kIxTile / 32];
+  __shared__ uint32_t cl_all[kIxWaves][(kIxTile + 64) / 4];
   const int lane = lane_id(), wv = threadIdx.x >> 6;
   const int64_t tile = (int64_t)blockIdx.x * kIxWaves + wv;
   const int64_t beg = tile * kIxTile;
   if (tile >= tiles && beg >= scan_len) return;
   int32_t* cnt = cnt_all[wv];
-  int64_t* st = st_all[wv];
-  uint8_t* cl = cl_all[wv];
-  const int64_t cend = min(beg + kIxTile + 64, n_padded);  // codes staged [beg, cend), separators after
-#pragma unroll 4
-  for (int r = 0; r < kIxTile / 64 + 1; ++r) {
-    const int64_t p = beg + r * 64 + lane;
-    cl[r * 64 + lane] = p < cend ? codes[p] : (uint8_t)kPadCode;
-  }
+  uint32_t* rb = rb_all[wv];
+  uint32_t* cl32 = cl_all[wv];
+  stage_codes(codes, beg, n_padded, cl32, lane);
   cnt[lane] = 0;
   cnt[lane + 64] = 0;
+  rb[lane] = 0;
   const bool layout_ok = !(*err & 1);
-  int s0 = n_seqs - 1;  // the last sequence with seq_start <= beg (-1 before the first one)
-  if (layout_ok && beg < n_padded && n_seqs > 0) {
-    s0 = min(max(tile_seq[min(tile, tiles - 1)], 0), n_seqs - 1);
-    if (seq_start[s0] > beg) s0 = -1;
-  }
-  if (layout_ok) load_starts<kTileStarts>(seq_start, n_seqs, s0, st, lane);
   wave_sync();
   if (layout_ok) {
-    int s_cur = s0;
+    // s0: the last sequence with seq_start <= beg (-1 before the first one)
+    int s0 = n_seqs - 1;
+    if (beg < n_padded && n_seqs > 0) {
+      s0 = min(max(tile_seq[min(tile, tiles - 1)], 0), n_seqs - 1);
+      if (seq_start[s0] > beg) s0 = -1;
+    }
+    const bool init = s0 >= 0 && beg < (s0 + 1 < n_seqs ? seq_start[s0 + 1] : n_padded) - kPadLen;
+    // Toggles from the starts s0 + 1 .. s0 + 128 (n_padded standing for
+    // seq_start[n_seqs]): a start inside the tile, and the residue end kPadLen
+    // before it.  A valid layout puts at most 104 of them within kIxTile + kPadLen
+    // of beg, since consecutive starts are at least kPadLen apart.
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int64_t idx = (int64_t)s0 + 1 + k * 64 + lane;
+      if (idx <= n_seqs) {
+        const int64_t v = idx < n_seqs ? seq_start[idx] : n_padded;
+        const int64_t e = v - kPadLen;
+        if (idx < n_seqs && v > beg && v < beg + kIxTile) atomicXor(&rb[(v - beg) >> 5], 1u << ((v - beg) & 31));
+        if (e > beg && e < beg + kIxTile) atomicXor(&rb[(e - beg) >> 5], 1u << ((e - beg) & 31));
+      }
+    }
+    wave_sync();
+    {
+      const uint32_t tog = rb[lane];
+      uint32_t x = tog;
+      x ^= x << 1;
+      x ^= x << 2;
+      x ^= x << 4;
+      x ^= x << 8;
+      x ^= x << 16;
+      const uint64_t odd = __ballot(__popc(tog) & 1);
+      const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+      const bool flip = ((__popcll(odd & below) & 1) != 0) != init;
+      rb[lane] = flip ? ~x : x;
+    }
+    wave_sync();
     bool bad = false;
     const int64_t vend = min(beg + kIxTile, scan_len);
     // 256 positions per round, four consecutive ones per lane (scan is
     // 256-byte aligned and scan_len a multiple of 256: one dword per lane)
     for (int64_t base = beg; base < vend; base += 256) {
-      const int64_t p = base + 4 * lane;
-      const int64_t nxt = lane < 16 ? st[min(s_cur - s0 + lane, 64 * kTileStarts - 1)] : INT64_MAX;
-      int s = s_cur;
-#pragma unroll
-      for (int k = 0; k < 16; ++k) s += p >= __shfl(nxt, k) ? 1 : 0;
-      // starts of sequences s + 1 and s + 2 (seq_start[n_seqs] == n_padded); at
-      // most one of the lane's four positions begins a sequence
-      const int64_t e0 = s + 1 < n_seqs ? st[min(s - s0, 64 * kTileStarts - 1)] : n_padded;
-      const int64_t e1 = s + 2 < n_seqs ? st[min(s + 1 - s0, 64 * kTileStarts - 1)] : n_padded;
-      const uint32_t raw = *(const uint32_t*)(cl + (p - beg));
+      const int off = (int)(base - beg) + 4 * lane;
+      const uint32_t raw = cl32[off >> 2];
+      const uint32_t res = (rb[off >> 5] >> (off & 31)) & 15u;
       uint32_t out = 0;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        const int64_t q = p + k;
         uint32_t c = kPadCode;
-        if (q < n_padded) {
-          const bool next = q >= e0;
-          const bool residue = s + (next ? 1 : 0) >= 0 && q < (next ? e1 : e0) - kPadLen;
+        if (beg + off + k < n_padded) {
+          const bool residue = (res >> k) & 1u;
           c = (raw >> (8 * k)) & 0xffu;
           bad |= residue ? (c >= 20) : (c != kPadCode);
           if (!(residue && c < 20)) c = kPadCode;
         }
         out |= (c * kScale) << (8 * k);
       }
-      *(uint32_t*)(scan + p) = out;
-      s_cur = __shfl(s + (p + 3 >= e0 ? 1 : 0), 63);
+      *(uint32_t*)(scan + beg + off) = out;
     }
     if (bad) atomicOr(err, 2);
   }
   if (tile >= tiles) return;
-  const int64_t end = min(beg + kIxTile, n_padded - (kSeed - 1));  // word starts [beg, end)
-  for (int off = 0; beg + off < end; off += 64) {
-    const int key = word_key_lds(cl, off + lane, beg + off + lane < end, sc);
-    if (key >= 0) atomicAdd(&cnt[key & (kD0 - 1)], 1);
+  const int nw = (int)(min(beg + kIxTile, n_padded - (kSeed - 1)) - beg);  // word starts [beg, beg + nw)
+#pragma unroll 2
+  for (int r = 0; r < kIxTile / 256; ++r) {
+    const int o = r * 256 + 4 * lane;
+    if (o < nw) {
+      const uint32_t lo = cl32[o >> 2], hi = cl32[(o >> 2) + 1];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int key = word_key4(__builtin_amdgcn_alignbyte(hi, lo, k), sc);
+        if (o + k < nw && key >= 0) atomicAdd(&cnt[key & (kD0 - 1)], 1);
+      }
+    }
   }
   wave_sync();
   hist[(int64_t)lane * tiles + tile] = cnt[lane];
@@ -266,7 +317,7 @@ __global__ __launch_bounds__(64 * kIxWaves) void k_ix_scatter1(
   __shared__ int32_t gst_all[kIxWaves][kD0], lst_all[kIxWaves][kD0], cur_all[kIxWaves][kD0];
   __shared__ int64_t st_all[kIxWaves][64 * kTileStarts];
   __shared__ uint32_t stage_all[kIxWaves][kIxTile];
-  __shared__ uint8_t cl_all[kIxWaves][kIxTile + 64];
+  __shared__ uint32_t cl_all[kIxWaves][(kIxTile + 64) / 4];
   __shared__ uint32_t sbits_all[kIxWaves][kIxTile / 32], spre_all[kIxWaves][kIxTile / 32];
   const int lane = lane_id(), wv = threadIdx.x >> 6;
   const int64_t tile = (int64_t)blockIdx.x * kIxWaves + wv;
@@ -274,16 +325,11 @@ __global__ __launch_bounds__(64 * kIxWaves) void k_ix_scatter1(
   int32_t *gst = gst_all[wv], *lst = lst_all[wv], *cur = cur_all[wv];
   int64_t* st = st_all[wv];
   uint32_t* stage = stage_all[wv];
-  uint8_t* cl = cl_all[wv];
+  uint32_t* cl32 = cl_all[wv];
   uint32_t *sbits = sbits_all[wv], *spre = spre_all[wv];
   const int64_t beg = tile * kIxTile;
   const int64_t end = min(beg + kIxTile, n_padded - (kSeed - 1));  // word starts [beg, end)
-  const int64_t cend = min(beg + kIxTile + 64, n_padded);          // codes staged [beg, cend)
-#pragma unroll 4
-  for (int r = 0; r < kIxTile / 64 + 1; ++r) {
-    const int64_t p = beg + r * 64 + lane;
-    cl[r * 64 + lane] = p < cend ? codes[p] : (uint8_t)kPadCode;
-  }
+  stage_codes(codes, beg, n_padded, cl32, lane);
   const int s0 = min(max(tile_seq[tile], 0), n_seqs - 1);
   load_starts<kTileStarts>(seq_start, n_seqs, s0, st, lane);
   sbits[lane] = 0;
@@ -327,7 +373,7 @@ __global__ __launch_bounds__(64 * kIxWaves) void k_ix_scatter1(
     int nw = 0;
     for (int off = 0; beg + off < end; off += 64) {
       const int64_t q = beg + off + lane;
-      const int key = word_key_lds(cl, off + lane, q < end, sc);
+      const int key = q < end ? word_key_at(cl32, off + lane, sc) : -1;
       const uint64_t w = __ballot(key >= 0);
       const int at = nw + __popcll(w & below);
       if (key >= 0 && at < kIxTile / 2) comp[at] = entry(key, off, seq_at(off + lane));
@@ -344,7 +390,7 @@ __global__ __launch_bounds__(64 * kIxWaves) void k_ix_scatter1(
   } else {
     for (int off = 0; beg + off < end; off += 64) {
       const int64_t q = beg + off + lane;
-      const int key = word_key_lds(cl, off + lane, q < end, sc);
+      const int key = q < end ? word_key_at(cl32, off + lane, sc) : -1;
       const int l = rank_in_tile(key & (kD0 - 1), key >= 0, cur, below);
       if (key >= 0 && (unsigned)l < (unsigned)kIxTile) stage[l] = entry(key, off, seq_at(off + lane));
     }
