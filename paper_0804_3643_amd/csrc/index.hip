@@ -369,15 +369,38 @@ __global__ __launch_bounds__(64 * kIxWaves) void k_ix_scatter1(
     // words are first compacted in position order into the upper half of the
     // stage, then ranked from there into the lower half, ceil(nt / 64) rounds
     // instead of one per 64 positions; the halves do not overlap.
+    // Four consecutive word starts per lane and round (two aligned dword reads);
+    // a word's place is the valid words of the lanes below plus those of its
+    // own lane before it, and its sequence the bitmap count at its position
+    // (the four positions share one 32-bit word of the bitmap).
     uint32_t* comp = stage + kIxTile / 2;
     int nw = 0;
-    for (int off = 0; beg + off < end; off += 64) {
-      const int64_t q = beg + off + lane;
-      const int key = q < end ? word_key_at(cl32, off + lane, sc) : -1;
-      const uint64_t w = __ballot(key >= 0);
-      const int at = nw + __popcll(w & below);
-      if (key >= 0 && at < kIxTile / 2) comp[at] = entry(key, off, seq_at(off + lane));
-      nw += __popcll(w);
+    const int nwp = (int)(end - beg);  // word starts in the tile (none if <= 0)
+    for (int o0 = 0; o0 < nwp; o0 += 256) {
+      const int o = o0 + 4 * lane;
+      const uint32_t lo = cl32[o >> 2], hi = cl32[(o >> 2) + 1];
+      int key[4];
+      uint64_t bal[4];
+      int before = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        key[k] = o + k < nwp ? word_key4(__builtin_amdgcn_alignbyte(hi, lo, (uint32_t)k), sc) : -1;
+        bal[k] = __ballot(key[k] >= 0);
+        before += __popcll(bal[k] & below);
+      }
+      const uint32_t sb = sbits[o >> 5];
+      const int sp = s0 + (int)spre[o >> 5];
+      int at = nw + before;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (key[k] >= 0) {
+          const int s = sp + __popc(sb & (~0u >> (31 - ((o + k) & 31))));
+          if (at < kIxTile / 2)
+            comp[at] = (uint32_t)key[k] | ((uint32_t)(o + k) << 14) | ((uint32_t)min(s - s0, 127) << 25);
+          ++at;
+        }
+      }
+      nw += __popcll(bal[0]) + __popcll(bal[1]) + __popcll(bal[2]) + __popcll(bal[3]);
     }
     wave_sync();
     nw = min(nw, kIxTile / 2);
