@@ -451,7 +451,8 @@ __global__ __launch_bounds__(64 * kIxWaves) void k_ix_count2(const uint64_t* __r
 
 // Pass 2, scattering: the tile's words ranked within their high digit into
 // the tile's bucket order in LDS, eight rounds of loads in flight ahead of
-// the ranking, then written out bucket by bucket as occ and occ_seq.
+// the ranking, then written out bucket by bucket as occ and occ_seq, eight
+// slots per lane at a time.
 constexpr int kBatch = 8;
 
 __global__ __launch_bounds__(64 * kIxWaves) void k_ix_scatter2(
@@ -493,15 +494,33 @@ __global__ __launch_bounds__(64 * kIxWaves) void k_ix_scatter2(
     for (int k = 0; k < kBatch; ++k) e_cur[k] = e_nxt[k];
   }
   wave_sync();
-  for (int l = lane; l < min(nt, kIxTile); l += 64) {
-    const uint64_t e = stage[l];
-    const int key = (int)(e >> 39);
-    const int d = min(key >> kD0Bits, kD1 - 1);
-    const int64_t slot = (int64_t)gst[d] + (l - lst[d]);
-    if (slot < 0 || slot >= n) continue;
-    const uint32_t pos = (uint32_t)e;
-    occ[slot] = (int32_t)pos;
-    occ_seq[slot] = (int64_t)(pos >> 11) < tiles1 ? tile_seq[pos >> 11] + (int)((e >> 32) & 127u) : -1;
+  // eight slots per lane at a time, so that their tile-table loads are in
+  // flight together
+  const int nl = min(nt, kIxTile);
+  for (int l0 = 0; l0 < nl; l0 += 64 * kBatch) {
+    uint64_t e[kBatch];
+    int32_t ts[kBatch];
+#pragma unroll
+    for (int k = 0; k < kBatch; ++k) {
+      const int l = l0 + k * 64 + lane;
+      e[k] = l < nl ? stage[l] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < kBatch; ++k) {
+      const uint32_t t1 = (uint32_t)e[k] >> 11;
+      ts[k] = (int64_t)t1 < tiles1 ? tile_seq[t1] : -1;
+    }
+#pragma unroll
+    for (int k = 0; k < kBatch; ++k) {
+      const int l = l0 + k * 64 + lane;
+      if (l >= nl) continue;
+      const int key = (int)(e[k] >> 39);
+      const int d = min(key >> kD0Bits, kD1 - 1);
+      const int64_t slot = (int64_t)gst[d] + (l - lst[d]);
+      if (slot < 0 || slot >= n) continue;
+      occ[slot] = (int32_t)(uint32_t)e[k];
+      occ_seq[slot] = ts[k] >= 0 ? ts[k] + (int)((e[k] >> 32) & 127u) : -1;
+    }
   }
 }
 
