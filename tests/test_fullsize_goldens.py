@@ -65,7 +65,7 @@ def test_stored_cfg0_golden_equals_the_numpy_oracle(cfg0_full):
     assert sum(b[0] for b in gold["blocks"]) == gold["n_hits"] == len(h)
 
 
-@pytest.mark.parametrize("cfg", ["1", "2", "3"])
+@pytest.mark.parametrize("cfg", ["1", "2", "3", "x"])
 def test_stored_goldens_match_generator_and_parameters(cfg):
     gold = fullsize.load(cfg)
     assert gold is not None, "missing golden: python tests/golden/fullsize.py %s" % cfg

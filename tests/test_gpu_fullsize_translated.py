@@ -1,5 +1,6 @@
 """Full-size TPLAST-N (5,000 proteins against 2,000 DNA sequences of 50-200 kb)
-on the GPU, against the oracle's full-size golden: the device six-frame
+and PLAST-X (200 against 1,000 DNA sequences of 20-50 kb, both translated) on
+the GPU, against the oracle's full-size goldens: the device six-frame
 translation equals the oracle's fragment bank and fragment table byte for byte
 (SHA-256), and the whole hit list with every gapped score equals the oracle's
 (count and 64-bit multiset digests, whole run and per block of 80 keys)."""
@@ -66,3 +67,18 @@ def test_tplastn_full_size_against_golden(B):
     ca, sa = B.bank_to_device(w.bank1, "cuda")
     _say("tplastn search")
     _search_checked(B, golden, ca, sa, cb, sb, w.bank1)
+
+
+@pytest.mark.timeout(600)
+def test_plastx_full_size_against_golden(B):
+    golden = fullsize.load("x")
+    assert golden is not None
+    _say("plastx generate")
+    w = synth.make_plastx()
+    assert golden["bank_sha256"] == [fullsize.sha256_arrays(w.dna1.codes, w.dna1.start),
+                                     fullsize.sha256_arrays(w.dna2.codes, w.dna2.start)]
+    _say("plastx translate both banks")
+    ca, sa, bank1 = _translate_checked(B, w.dna1, golden["fragments"][0])
+    cb, sb, _ = _translate_checked(B, w.dna2, golden["fragments"][1])
+    _say("plastx search")
+    _search_checked(B, golden, ca, sa, cb, sb, bank1)
