@@ -18,8 +18,9 @@
 // position), independent of scheduling.  Pass 1 reads the codes (staged in
 // LDS) and writes one 64-bit entry per word (position, key, and the sequence
 // as an offset from the first sequence of the position's tile, which the
-// layout check records per tile); pass 2 writes occ and occ_seq, and key_off
-// follows from the two scanned histograms.
+// layout check records per tile) and, beside it, the byte of its high digit
+// that pass 2's counting kernel reads; pass 2 writes occ and occ_seq, and
+// key_off follows from the two scanned histograms.
 #include "plast_internal.h"
 
 namespace plast {
@@ -313,7 +314,7 @@ __global__ __launch_bounds__(64 * kIxWaves) void k_ix_check_count1(
 __global__ __launch_bounds__(64 * kIxWaves) void k_ix_scatter1(
     const uint8_t* __restrict__ codes, const int64_t* __restrict__ seq_start, int32_t n_seqs, int64_t n_padded,
     int64_t tiles, SeedClasses sc, const int32_t* __restrict__ tile_seq, const int32_t* __restrict__ err,
-    const int32_t* __restrict__ offs, int64_t cap, uint64_t* __restrict__ words) {
+    const int32_t* __restrict__ offs, int64_t cap, uint64_t* __restrict__ words, uint8_t* __restrict__ digits) {
   __shared__ int32_t gst_all[kIxWaves][kD0], lst_all[kIxWaves][kD0], cur_all[kIxWaves][kD0];
   __shared__ int64_t st_all[kIxWaves][64 * kTileStarts];
   __shared__ uint32_t stage_all[kIxWaves][kIxTile];
@@ -424,12 +425,18 @@ __global__ __launch_bounds__(64 * kIxWaves) void k_ix_scatter1(
     const int key = (int)(e & 0x3fffu);
     const int d = key & (kD0 - 1);
     const int64_t slot = (int64_t)gst[d] + (l - lst[d]);
-    if (slot >= 0 && slot < cap) words[slot] = word_entry(beg + ((e >> 14) & 2047u), (int)(e >> 25), key);
+    if (slot >= 0 && slot < cap) {
+      words[slot] = word_entry(beg + ((e >> 14) & 2047u), (int)(e >> 25), key);
+      digits[slot] = (uint8_t)min(key >> kD0Bits, kD1 - 1);
+    }
   }
 }
 
-// Pass 2, counting: histogram of the high digit over the tile's words.
-__global__ __launch_bounds__(64 * kIxWaves) void k_ix_count2(const uint64_t* __restrict__ words,
+// Pass 2, counting: histogram of the high digit over the tile's words, read
+// from the byte per word that pass 1 writes beside each entry (four per lane
+// and round; the array is 256-byte aligned and padded, so a dword that
+// straddles the end stays inside it).
+__global__ __launch_bounds__(64 * kIxWaves) void k_ix_count2(const uint8_t* __restrict__ digits,
                                                             const int32_t* __restrict__ err, int64_t cap,
                                                             int64_t tiles, int32_t* __restrict__ hist) {
   __shared__ int32_t cnt_all[kIxWaves][kD0];
@@ -443,7 +450,12 @@ __global__ __launch_bounds__(64 * kIxWaves) void k_ix_count2(const uint64_t* __r
   const int64_t n = min((int64_t)err[1], cap);
   const int64_t beg = tile * kIxTile;
   const int64_t end = min(beg + kIxTile, n);
-  for (int64_t i = beg + lane; i < end; i += 64) atomicAdd(&cnt[min((int)(words[i] >> (39 + kD0Bits)), kD1 - 1)], 1);
+  for (int64_t i = beg + 4 * lane; i < end; i += 256) {
+    const uint32_t d4 = *(const uint32_t*)(digits + i);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (i + k < end) atomicAdd(&cnt[min((int)((d4 >> (8 * k)) & 0xffu), kD1 - 1)], 1);
+  }
   wave_sync();
   if (lane < kD1) hist[(int64_t)lane * tiles + tile] = cnt[lane];
   if (lane + 64 < kD1) hist[(int64_t)(lane + 64) * tiles + tile] = cnt[lane + 64];
@@ -677,13 +689,13 @@ IndexLayout index_layout(int64_t n_padded) {
 }
 
 // Workspace: [error words (256 B)] [tile table] [pass-1 histogram] [pass-2 histogram]
-// [scan scratch] [word entries between the passes (64-bit)].
+// [scan scratch] [word entries between the passes (64-bit)] [their high digits (8-bit)].
 // The word arrays hold n_padded - kPadLen entries, a bound on the residues of any valid
 // layout that grows with n_padded alone, so a workspace sized for the largest
 // bank serves every smaller one whatever its number of sequences.
 struct IxWs {
   int64_t tiles1, tiles2, cap;
-  size_t tile_seq, hist1, hist2, tmp, words, total;
+  size_t tile_seq, hist1, hist2, tmp, words, digits, total;
 };
 
 IxWs ix_ws(int64_t n_padded) {
@@ -705,6 +717,8 @@ IxWs ix_ws(int64_t n_padded) {
   off = align_up(off + scan_tmp_bytes(scan_n), 256);
   w.words = off;
   off = align_up(off + sizeof(uint64_t) * (size_t)w.cap, 256);
+  w.digits = off;
+  off = align_up(off + (size_t)w.cap, 256);
   w.total = off;
   return w;
 }
@@ -729,6 +743,7 @@ int index_enqueue(const uint8_t* d_codes, const int64_t* d_seq_start, int32_t n_
   int32_t* hist2 = (int32_t*)(ws + W.hist2);
   void* tmp = ws + W.tmp;
   uint64_t* words = (uint64_t*)(ws + W.words);
+  uint8_t* digits = ws + W.digits;
 
   SeedClasses sc = seed_classes();
   timing_mark(kStageIndex, false, stream);
@@ -748,8 +763,8 @@ int index_enqueue(const uint8_t* d_codes, const int64_t* d_seq_start, int32_t n_
   exclusive_scan_i32(hist1, kD0 * W.tiles1, total, tmp, stream);
   hipLaunchKernelGGL(k_ix_scatter1, dim3(g1), dim3(64 * kIxWaves), 0, stream, d_codes, d_seq_start, n_seqs,
                      n_padded, W.tiles1, sc, (const int32_t*)tile_seq, (const int32_t*)d_err, (const int32_t*)hist1,
-                     W.cap, words);
-  hipLaunchKernelGGL(k_ix_count2, dim3(g2), dim3(64 * kIxWaves), 0, stream, (const uint64_t*)words,
+                     W.cap, words, digits);
+  hipLaunchKernelGGL(k_ix_count2, dim3(g2), dim3(64 * kIxWaves), 0, stream, (const uint8_t*)digits,
                      (const int32_t*)d_err, W.cap, W.tiles2, hist2);
   exclusive_scan_i32(hist2, kD1 * W.tiles2, nullptr, tmp, stream);
   hipLaunchKernelGGL(k_ix_scatter2, dim3(g2), dim3(64 * kIxWaves), 0, stream, (const uint64_t*)words,
