@@ -156,7 +156,6 @@ __device__ __forceinline__ uint64_t word_entry(int64_t q, int seq_off, int key) 
 constexpr int kTileStarts = 2;  // 128 starts
 static_assert(kIxTile == 2048, "word staging packs a position offset in 11 bits");
 
-
 // A tile's codes [beg, beg + kIxTile + 64) into LDS as dwords (separators past
 // n_padded), with dword loads when the codes are 4-byte aligned.
 __device__ __forceinline__ void stage_codes(const uint8_t* __restrict__ codes, int64_t beg, int64_t n_padded,
