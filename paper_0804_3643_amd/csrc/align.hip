@@ -39,10 +39,13 @@ namespace {
 constexpr int kANeg = -(1 << 28);
 constexpr int kSortTile = 4096;     // radix-sort elements per tile (one wavefront, 64 per lane)
 constexpr int kTStride = 32;        // entries per row of the LDS score table
-constexpr int kWall = -16384;       // table entry of any pair with the sentinel letter
+constexpr int kWall = -16256;       // table entry of any pair with the sentinel letter (low byte 0x80: -128 as 8 bits)
 constexpr int kYScale = 64 * 2;     // bytes per letter row of the per-lane profile (64 int16)
 constexpr int kWalkDwords = 512;    // trace-back window: 8 dwords (64 steps) x 64 rows
 constexpr size_t kMaxLds = 160 * 1024;
+constexpr int kRowsMax = 4;         // most rows per lane in the multi-row score pass (one profile dword)
+constexpr int kProfLaneBytes = 4;   // profile bytes per lane and letter: the larger of 2 (trace pass) and 4
+static_assert(kRowsMax <= 4, "the score pass's switch and the profile size cover up to 4 rows per lane");
 
 struct AlignHeader {
   int32_t status;                 // bit 1: sequence longer than its max_len; 2: piece list full; 4: bad hit;
@@ -68,7 +71,8 @@ struct AlignArgs {
   int32_t a_nseq, b_nseq;
   int32_t max_len1, max_len2;
   int32_t gap_open, gap_extend;
-  int32_t max_pieces, pad_;
+  int32_t max_pieces;
+  int32_t rows8;  // 1: every score-table entry of two letters fits 8 bits (the multi-row score pass)
   int8_t mat[20 * 20];
 };
 
@@ -141,7 +145,7 @@ size_t strip_bytes(int max_len2) {
 }
 
 size_t align_lds_bytes(int max_len2) {
-  size_t b = sizeof(int16_t) * 21 * 64;
+  size_t b = 21 * 64 * kProfLaneBytes;
   b += align_up((size_t)max_len2 + 136, 16);   // y letters, 64 sentinels before column 0
   b += strip_bytes(max_len2);
   return b;
@@ -426,6 +430,132 @@ __device__ __forceinline__ void side_dp(int lx, int ly, int steps, int ge, int g
   }
 }
 
+// The score pass with R rows per lane, for score tables that fit 8 bits: the
+// same recurrence and values as side_dp over one strip of rows s0 + 1 .. s0 +
+// 64 R.  Lane r holds rows s0 + r R + 1 .. s0 + r R + R, all in the column t
+// - r at step t, so one pair of wavefront shifts per step serves R cells: a
+// row's diagonal and vertical inputs come from the lane's row above (its
+// values of the previous step and of this one), those of the lane's first
+// row from the last row of the lane above, as in side_dp.  The profile holds
+// per y letter and lane the R scores of the lane's rows as bytes of one
+// dword, so each step reads them with one LDS access.  The sentinel's entry
+// is -128 (the low byte of kWall): it only has to make every cell past the
+// matrix lower than some cell inside it, which any negative unshifted score
+// does (see side_dp).  Cell (i, j) of row q at step t8 + k carries the
+// shift (i + j) ext = off0 + (q + k) ext, so the block maximum of H' - k ext,
+// less off0 + q ext, is the row's best over the block.  Each row keeps its
+// best value and the first block that reached it; the lane then keeps, over
+// its rows in order and over the strips, the first row holding its largest
+// value (rows past lx lie below a cell of an earlier row, see side_dp), with
+// the last column of that row's block (bjhi) as the bound for the trace pass.
+template <int R>
+__device__ __forceinline__ void side_score8(int s0, int lx, int ly, int steps, int ge, int go, const int16_t* T,
+                                            uint32_t* prof, const uint8_t* x, int dx, const uint8_t* yo, int2* strip,
+                                            int& best, int& brow, int& bjhi) {
+  const int lane = threadIdx.x;
+  {
+    // each row's line of the score table (entries 0..23, 16-byte aligned);
+    // the low byte of an entry is its 8-bit value, the wall's included
+    uint4 tr[R][3];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int i0 = s0 + lane * R + q;
+      const uint4* line = (const uint4*)(T + (i0 < lx ? (int)x[(int64_t)i0 * dx] : kPadCode) * kTStride);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) tr[q][c] = line[c];
+    }
+#pragma unroll
+    for (int yc = 0; yc < 21; ++yc) {
+      uint32_t w = 0u;
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const uint4 v = tr[q][yc >> 3];
+        const uint32_t d = (yc & 6) == 0 ? v.x : ((yc & 6) == 2 ? v.y : ((yc & 6) == 4 ? v.z : v.w));
+        w |= ((d >> (16 * (yc & 1))) & 255u) << (8 * q);
+      }
+      prof[yc * 64 + lane] = w;
+    }
+  }
+  __syncthreads();
+  int hml[R], el[R], rbest[R], rpos[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    hml[q] = kANeg;
+    el[q] = kANeg;
+    rbest[q] = 0;
+    rpos[q] = -1;
+  }
+  int hup = kANeg, flast = kANeg;
+  const uint8_t* ycol = yo + 64 - lane;
+  const uint32_t* pl = prof + lane;
+  for (int t8 = 0; t8 < steps; t8 += 8) {
+    const int4* sf = (const int4*)(strip + t8);
+    const int4 s0v = sf[0], s1v = sf[1], s2v = sf[2], s3v = sf[3];
+    const int fh[8] = {s0v.x, s0v.z, s1v.x, s1v.z, s2v.x, s2v.z, s3v.x, s3v.z};
+    const int ff[8] = {s0v.y, s0v.w, s1v.y, s1v.w, s2v.y, s2v.w, s3v.y, s3v.w};
+    uint32_t yw[2];
+    __builtin_memcpy(yw, ycol + t8, 8);
+    int bm[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) bm[q] = kANeg;
+    int oh[8], of[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const uint32_t w = pl[__builtin_amdgcn_ubfe(yw[k >> 2], 8 * (k & 3), 8) * 64];
+      const int hdiag = hup;
+      hup = shr1(fh[k], hml[R - 1]);
+      const int fup = shr1(ff[k], flast);
+      int dsrc = hdiag, fa = fup, ha = hup;
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const int sc = (int)(int8_t)(w >> (8 * q));
+        const int e = max(el[q], hml[q]);
+        const int f = max(fa, ha);
+        const int h = max(max(dsrc + sc, e), f);
+        bm[q] = max(bm[q], h - k * ge);
+        dsrc = hml[q];
+        hml[q] = h - go;
+        el[q] = e;
+        fa = f;
+        ha = hml[q];
+      }
+      flast = fa;
+      oh[k] = ha;
+      of[k] = fa;
+    }
+    const int off0 = (s0 + lane * (R - 1) + 1 + t8) * ge;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int u = bm[q] - off0 - q * ge;
+      if (u > rbest[q]) {
+        rbest[q] = u;
+        rpos[q] = t8;
+      }
+    }
+    if (lane == 63) {  // the strip's last row, columns t8 - 63 .. t8 - 56
+      if (t8 >= 63 && t8 - 56 <= ly) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) strip[t8 + k - 63] = make_int2(oh[k], of[k]);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int j = t8 + k - 63;
+          if (j >= 0 && j <= ly) strip[j] = make_int2(oh[k], of[k]);
+        }
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    if (rpos[q] >= 0 && rbest[q] > best) {
+      best = rbest[q];
+      brow = s0 + lane * R + q + 1;
+      bjhi = rpos[q] + 7 - lane;
+    }
+  }
+}
+
 // Letters of a DP over lx x ly: x past lx and y past ly (and column 0) are the
 // sentinel; the row above strip 0 is row 0, shifted: H'(0, 0) = 0 and H'(0, k)
 // = -(open + k ext) + k ext = -open, so hm(0, 0) = -open, hm(0, k) = -2 open,
@@ -457,28 +587,52 @@ __device__ __forceinline__ SideStats align_side(const AlignArgs& A, const uint8_
   const int steps = (ly + 64 + 7) & ~7;
   for (int k = lane; k < ly; k += 64) yo[65 + k] = y[(int64_t)k * dy];
   side_pad(ly, steps, go, yo, strip);
-  int best = 0, bpos = 0;  // bpos = (strip << 16) | (block start + 1); 0: cell (0, 0)
-  side_dp<false>(lx, ly, steps, ge, go, T, prof, x, dx, yo, strip, tb, best, bpos);
-
-  // best over the wavefront: largest value, then first row, then first block
-  // (a row belongs to one lane, so the block decides only within a row)
-  int key = 0;
-  if (bpos != 0) {
-    const int s = bpos >> 16, t8 = (bpos & 0xffff) - 1;
-    key = ((s * 64 + lane + 1) << 16) | (t8 + 64);
+  // the lane's best value, its first row and the last column of the block of
+  // 8 steps where that row first reached it (brow 0: cell (0, 0))
+  int best = 0, brow = 0, bjhi = 0;
+  if (A.rows8) {
+    for (int s0 = 0; s0 < lx;) {  // strips of up to 64 kRowsMax rows, each as narrow as its rows allow
+      const int rows = min(kRowsMax, (lx - s0 + 63) >> 6);
+      switch (rows) {
+#define PLAST_SCORE_CASE(n) \
+  case n:                   \
+    side_score8<n>(s0, lx, ly, steps, ge, go, T, (uint32_t*)prof, x, dx, yo, strip, best, brow, bjhi); \
+    break;
+        PLAST_SCORE_CASE(1)
+        PLAST_SCORE_CASE(2)
+        PLAST_SCORE_CASE(3)
+        PLAST_SCORE_CASE(4)
+#undef PLAST_SCORE_CASE
+        default:
+          break;
+      }
+      s0 += 64 * rows;
+    }
+  } else {
+    int bpos = 0;  // (strip << 16) | (block start + 1)
+    side_dp<false>(lx, ly, steps, ge, go, T, prof, x, dx, yo, strip, tb, best, bpos);
+    if (bpos != 0) {
+      const int s = bpos >> 16, t8 = (bpos & 0xffff) - 1;
+      brow = s * 64 + lane + 1;
+      bjhi = t8 + 7 - lane;
+    }
   }
-  bpos = key;
+
+  // best over the wavefront: largest value, then first row (bjhi goes with
+  // the row)
   for (int o = 32; o >= 1; o >>= 1) {
-    const int ob = __shfl_xor(best, o), op = __shfl_xor(bpos, o);
-    if (ob > best || (ob == best && op < bpos)) {
+    const int ob = __shfl_xor(best, o), orow = __shfl_xor(brow, o), oj = __shfl_xor(bjhi, o);
+    if (ob > best || (ob == best && orow < brow)) {
       best = ob;
-      bpos = op;
+      brow = orow;
+      bjhi = oj;
     }
   }
   best = uni(best);
-  bpos = uni(bpos);
+  brow = uni(brow);
+  bjhi = uni(bjhi);
   st.best = best;
-  st.i_end = bpos >> 16;
+  st.i_end = brow;
   st.j_end = 0;
 
   // The trace of rows 1..i_end up to the end of the best's block (those cells
@@ -486,8 +640,8 @@ __device__ __forceinline__ SideStats align_side(const AlignArgs& A, const uint8_
   // whose H is the best.
   int nu8 = 0;
   if (st.i_end > 0) {
-    const int r_end = (st.i_end - 1) & 63, t8 = (bpos & 0xffff) - 64;
-    const int j_hi = min(ly, t8 + 7 - r_end);
+    const int r_end = (st.i_end - 1) & 63;
+    const int j_hi = min(ly, bjhi);
     const int steps2 = (j_hi + 64 + 7) & ~7;
     side_pad(j_hi, steps2, go, yo, strip);
     int unused0 = 0, unused1 = 0, jf = -1;
@@ -594,15 +748,17 @@ __global__ __launch_bounds__(64) void k_align_table(AlignArgs A, int16_t* __rest
   }
 }
 
-// At most 128 VGPRs (4 wavefronts per SIMD), so that the LDS, not the
-// registers, sets the number of resident workgroups.
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_align(
+// At most 168 VGPRs (3 wavefronts per SIMD, 12 per CU): the LDS of a
+// workgroup (15.1 KB for sequences of up to 1000 letters) holds the number of
+// resident workgroups to 10 per CU, so the registers cost no occupancy, and
+// with fewer the kernel spills.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_align(
     AlignArgs A, const int16_t* __restrict__ T, const plast_hit_t* hits, const int32_t* hidx, const int32_t* perm,
     const uint64_t* khi, const int32_t* heads, AlignHeader* hdr, uint32_t* tb_all, size_t tb_words, Piece* pieces_all,
     plast_alignment_t* out, int32_t* cover) {
   extern __shared__ __align__(16) uint8_t lds[];
   int16_t* prof = (int16_t*)lds;
-  uint8_t* yo = (uint8_t*)(prof + 21 * 64);
+  uint8_t* yo = (uint8_t*)lds + 21 * 64 * kProfLaneBytes;
   int2* strip = (int2*)(yo + ((A.max_len2 + 136 + 15) & ~15));
   uint32_t* walk = (uint32_t*)strip;  // the trace-back runs after the DP of its side
   const int lane = threadIdx.x;
@@ -735,11 +891,15 @@ int align_impl(const plast_index_t* a, const plast_index_t* b, const plast_hit_t
   A.gap_open = p->gap_open;
   A.gap_extend = p->gap_extend;
   A.max_pieces = p->max_pieces;
-  A.pad_ = 0;
   if (p->matrix) {
     for (int k = 0; k < 400; ++k) A.mat[k] = p->matrix[k];
   } else {
     blosum62_code_order(A.mat);
+  }
+  A.rows8 = 1;
+  for (int k = 0; k < 400; ++k) {
+    const int t = (int)A.mat[k] + p->gap_open + 2 * p->gap_extend;
+    if (t < -127 || t > 127) A.rows8 = 0;
   }
 
   const int bp1 = bits_for(p->max_len1), bp2 = bits_for(p->max_len2);

@@ -100,12 +100,14 @@ def test_align_other_gaps_and_matrix(B, cfg0):
     m[np.arange(20), np.arange(20)] += 2
     m[0, 5] = m[5, 0] = 3
     _assert_parity(B, cfg0.bank1, cfg0.bank2, ia, ib, hits, gs, ps, gap_open=5, gap_extend=2, matrix=m)
-    # large entries of the kernel's profile (score + open + 2 extend): a diagonal of 100 with open 25,
-    # and open 120 with extend 2
+    # large entries of the kernel's profile (score + open + 2 extend): a diagonal of 100 with open 25
+    # (largest entry 127, the last that the 8-bit multi-row score pass takes) and 26 (128: the one-row
+    # pass), and open 120 with extend 2
     m100 = O.BLOSUM62.copy()
     m100[np.arange(20), np.arange(20)] = 100
-    _say("align cfg0 with a diagonal of 100 and with open 120")
+    _say("align cfg0 with a diagonal of 100 (open 25 and 26) and with open 120")
     _assert_parity(B, cfg0.bank1, cfg0.bank2, ia, ib, hits, gs, ps, gap_open=25, gap_extend=1, matrix=m100)
+    _assert_parity(B, cfg0.bank1, cfg0.bank2, ia, ib, hits, gs, ps, gap_open=26, gap_extend=1, matrix=m100)
     _assert_parity(B, cfg0.bank1, cfg0.bank2, ia, ib, hits, gs, ps, gap_open=120, gap_extend=2)
 
 
