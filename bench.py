@@ -235,7 +235,8 @@ def cpu_baseline(w, gpu_hits_host, gpu_gscore_host, n_ext_total, sample_ext, s1,
 # 32 lookups of 4 bytes and 256 bytes of 8-byte reads per clock per CU, HBM3E
 # 8 TB/s.
 PUBLISHED_PEAKS = {"valu_i32": 256 * 64 * 2.4e9, "valu_pk_i16": 256 * 128 * 2.4e9, "valu_pk_f16": 256 * 128 * 2.4e9,
-                   "lds_lookup": 256 * 32 * 2.4e9, "hbm_copy": 8e12, "lds_b64": 256 * 256 * 2.4e9}
+                   "lds_lookup": 256 * 32 * 2.4e9, "hbm_copy": 8e12, "lds_b64": 256 * 256 * 2.4e9,
+                   "sclk": 2.4e9}
 
 
 def machine_info():
@@ -272,8 +273,12 @@ def measured_peaks(B, torch, dev):
         out[kind] = {"rate": r, "unit": unit, "published": PUBLISHED_PEAKS[kind],
                      "frac_of_published": r / PUBLISHED_PEAKS[kind]}
     del buf
-    # int32 lane operations per CU per clock if the chip ran at the published 2.4 GHz (64 by the figures)
+    # lane operations per CU per clock at the published 2.4 GHz and at the engine clock the clock probe
+    # measured inside its kernel (64 int32 and 128 packed 16-bit by the published figures)
     out["valu_i32_lane_ops_per_cu_clock_at_2_4_ghz"] = out["valu_i32"]["rate"] / (256 * 2.4e9)
+    sclk = out["sclk"]["rate"]
+    out["per_cu_clock_at_measured_sclk"] = {
+        k: out[k]["rate"] / (256 * sclk) for k in ("valu_i32", "valu_pk_i16", "valu_pk_f16", "lds_lookup", "lds_b64")}
     return out
 
 

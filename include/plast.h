@@ -460,6 +460,11 @@ int plast_align(const plast_index_t* a, const plast_index_t* b, const plast_hit_
  *   PLAST_PROBE_HBM_COPY     copy of the first half of d_buf to the second: bytes/s read + written
  *   PLAST_PROBE_LDS_B64      8-byte LDS reads with the ungapped kernel's profile access (lanes spread
  *                            over 21 entries 8 bytes apart): bytes/s
+ *   PLAST_PROBE_SCLK         the int32 chains with the first wavefront of each workgroup reading the
+ *                            engine-clock counter (s_memtime) and the constant-rate counter
+ *                            (s_memrealtime, hipDeviceAttributeWallClockRate) around its loop: *rate is
+ *                            the engine clock in Hz (median over workgroups of the last launch); d_buf
+ *                            needs 32 KiB more than for the other compute probes
  * d_buf: caller device memory, 256-byte aligned, at least 2 MiB for the compute
  * probes (each thread writes one int32) and 1 MiB for the copy, whose size is
  * buf_bytes (1 GiB or more gives a stable figure).  Synchronises the stream.
@@ -472,7 +477,8 @@ enum {
   PLAST_PROBE_VALU_PK_F16 = 2,
   PLAST_PROBE_LDS = 3,
   PLAST_PROBE_HBM_COPY = 4,
-  PLAST_PROBE_LDS_B64 = 5
+  PLAST_PROBE_LDS_B64 = 5,
+  PLAST_PROBE_SCLK = 6
 };
 int plast_probe_peak(int32_t kind, void* d_buf, size_t buf_bytes, int32_t reps, double* rate, void* stream);
 

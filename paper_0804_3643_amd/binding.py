@@ -35,7 +35,7 @@ EXPORTS = ("plast_index_bytes", "plast_build_index", "plast_ungapped_workspace_b
 
 # plast_probe_peak kinds and the unit of each rate
 PROBES = {"valu_i32": (0, "op/s"), "valu_pk_i16": (1, "op/s"), "valu_pk_f16": (2, "op/s"),
-          "lds_lookup": (3, "lookup/s"), "hbm_copy": (4, "B/s"), "lds_b64": (5, "B/s")}
+          "lds_lookup": (3, "lookup/s"), "hbm_copy": (4, "B/s"), "lds_b64": (5, "B/s"), "sclk": (6, "Hz")}
 
 TUNE_CLASSES = 4
 TUNE_WIDTHS = (1024, 2048, 4096, 8192, 16384)

@@ -14,8 +14,14 @@
 //   apart), so lanes with equal letters share an address.
 // * HBM: a copy between the two halves of a buffer, four 16-byte loads in
 //   flight per lane.
+// * Engine clock: the int32 chains, timed inside the kernel by the
+//   engine-clock and constant-rate counters, so that a rate can be put per
+//   clock of the clock the chip actually ran at.
 //
 // Every compute probe writes one value per thread, so no chain is dead code.
+#include <algorithm>
+#include <vector>
+
 #include "plast_internal.h"
 
 namespace plast {
@@ -42,6 +48,39 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_i32(int32_t* __restrict
 #pragma unroll
   for (int k = 0; k < kChains; ++k) s ^= a[k];
   out[(int64_t)blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
+// The same chains, with the first wavefront of each workgroup reading the
+// engine-clock counter (s_memtime) and the constant-rate counter
+// (s_memrealtime) on both sides of its loop: over the loop, the ratio of the
+// two deltas times the constant rate is the engine clock the chains ran at.
+__global__ __launch_bounds__(kProbeThreads) void k_probe_i32_clock(int32_t* __restrict__ out,
+                                                                   uint64_t* __restrict__ clk, int iters, int seed) {
+  const bool first = threadIdx.x < 64;
+  uint64_t c0 = 0, w0 = 0;
+  if (first) {
+    c0 = __builtin_amdgcn_s_memtime();
+    w0 = __builtin_amdgcn_s_memrealtime();
+  }
+  int a[kChains];
+  const int x = (seed ^ (int)threadIdx.x) & 7, y = -seed;
+#pragma unroll
+  for (int k = 0; k < kChains; ++k) a[k] = (int)threadIdx.x + k * seed;
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int k = 0; k < kChains; ++k) a[k] = max((int)((unsigned)a[k] + (unsigned)x), y + k);
+  }
+  int s = 0;
+#pragma unroll
+  for (int k = 0; k < kChains; ++k) s ^= a[k];
+  out[(int64_t)blockIdx.x * blockDim.x + threadIdx.x] = s;
+  if (first) {
+    const uint64_t c1 = __builtin_amdgcn_s_memtime(), w1 = __builtin_amdgcn_s_memrealtime();
+    if (threadIdx.x == 0) {
+      clk[2 * blockIdx.x] = c1 - c0;
+      clk[2 * blockIdx.x + 1] = w1 - w0;
+    }
+  }
 }
 
 __global__ __launch_bounds__(kProbeThreads) void k_probe_pk_i16(int32_t* __restrict__ out, int iters, int seed) {
@@ -165,12 +204,14 @@ extern "C" int plast_probe_peak(int32_t kind, void* d_buf, size_t buf_bytes, int
   using namespace plast;
   hipStream_t stream = (hipStream_t)stream_;
   if (!d_buf || !rate) return set_error(PLAST_E_ARG, "plast_probe_peak: null pointer");
-  if (kind < PLAST_PROBE_VALU_I32 || kind > PLAST_PROBE_LDS_B64)
+  if (kind < PLAST_PROBE_VALU_I32 || kind > PLAST_PROBE_SCLK)
     return set_error(PLAST_E_ARG, "plast_probe_peak: unknown kind %d", (int)kind);
   if (reps < 1 || reps > 100) return set_error(PLAST_E_ARG, "plast_probe_peak: reps must be in 1..100");
   if ((uintptr_t)d_buf & 255) return set_error(PLAST_E_ARG, "plast_probe_peak: buffer must be 256-byte aligned");
   const size_t out_bytes = sizeof(int32_t) * (size_t)kProbeBlocks * kProbeThreads;
-  const size_t need = kind == PLAST_PROBE_HBM_COPY ? ((size_t)1 << 20) : out_bytes;
+  const size_t clk_bytes = sizeof(uint64_t) * 2 * (size_t)kProbeBlocks;  // the clock probe's counter deltas
+  const size_t need =
+      kind == PLAST_PROBE_HBM_COPY ? ((size_t)1 << 20) : out_bytes + (kind == PLAST_PROBE_SCLK ? clk_bytes : 0);
   if (buf_bytes < need)
     return set_error(PLAST_E_WORKSPACE, "plast_probe_peak: buffer of %zu bytes, needs at least %zu", buf_bytes, need);
   // about 3.5 ms per launch at the published peaks (1.7 ms for the LDS probe)
@@ -179,7 +220,8 @@ extern "C" int plast_probe_peak(int32_t kind, void* d_buf, size_t buf_bytes, int
   double work = 0.0;  // operations, lookups or bytes per launch
   int64_t n16 = 0;
   switch (kind) {
-    case PLAST_PROBE_VALU_I32: work = threads * iters * kChains * 2.0; break;
+    case PLAST_PROBE_VALU_I32:
+    case PLAST_PROBE_SCLK: work = threads * iters * kChains * 2.0; break;
     case PLAST_PROBE_VALU_PK_I16:
     case PLAST_PROBE_VALU_PK_F16: work = threads * iters * kChains * 4.0; break;
     case PLAST_PROBE_LDS: work = threads * iters * kChains; break;
@@ -214,6 +256,10 @@ extern "C" int plast_probe_peak(int32_t kind, void* d_buf, size_t buf_bytes, int
       case PLAST_PROBE_LDS_B64:
         hipLaunchKernelGGL(k_probe_lds_b64, dim3(kProbeBlocks), dim3(kProbeThreads), 0, stream, out, iters, r + 1);
         break;
+      case PLAST_PROBE_SCLK:
+        hipLaunchKernelGGL(k_probe_i32_clock, dim3(kProbeBlocks), dim3(kProbeThreads), 0, stream, out,
+                           (uint64_t*)((uint8_t*)d_buf + out_bytes), iters, r + 1);
+        break;
       default: {
         const int4* src = (const int4*)d_buf;
         int4* dst = (int4*)((uint8_t*)d_buf + (size_t)n16 * 16);
@@ -234,6 +280,23 @@ extern "C" int plast_probe_peak(int32_t kind, void* d_buf, size_t buf_bytes, int
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
+  if (rc == PLAST_OK && kind == PLAST_PROBE_SCLK) {
+    // median over the workgroups of the last launch of (engine cycles /
+    // constant-rate ticks) times the constant rate
+    std::vector<uint64_t> d(2 * (size_t)kProbeBlocks);
+    int dev = 0, khz = 0;
+    if (hipMemcpyAsync(d.data(), (uint8_t*)d_buf + out_bytes, clk_bytes, hipMemcpyDeviceToHost, stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess || hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+      return set_error(PLAST_E_HIP, "plast_probe_peak: reading the clock counters failed");
+    std::vector<double> ratio;
+    for (int b = 0; b < kProbeBlocks; ++b)
+      if (d[2 * b + 1] > 0) ratio.push_back((double)d[2 * b] / (double)d[2 * b + 1]);
+    if (ratio.empty()) return set_error(PLAST_E_HIP, "plast_probe_peak: the constant-rate counter did not advance");
+    std::nth_element(ratio.begin(), ratio.begin() + ratio.size() / 2, ratio.end());
+    best = ratio[ratio.size() / 2] * (double)khz * 1e3;
+  }
   if (rc == PLAST_OK) *rate = best;
   return rc;
 }

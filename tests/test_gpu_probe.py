@@ -12,7 +12,7 @@ pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
 
 PUBLISHED = {"valu_i32": 256 * 64 * 2.4e9, "valu_pk_i16": 256 * 128 * 2.4e9, "valu_pk_f16": 256 * 128 * 2.4e9,
-             "lds_lookup": 256 * 32 * 2.4e9, "hbm_copy": 8e12, "lds_b64": 256 * 256 * 2.4e9}
+             "lds_lookup": 256 * 32 * 2.4e9, "hbm_copy": 8e12, "lds_b64": 256 * 256 * 2.4e9, "sclk": 2.4e9}
 
 
 def test_probes_report_plausible_peaks():

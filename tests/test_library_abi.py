@@ -274,5 +274,7 @@ def test_probe_validation_without_gpu():
     assert lib.plast_probe_peak(0, fake, 1 << 20, 3, ctypes.byref(rate), None) == binding.E_WORKSPACE
     assert lib.plast_probe_peak(4, fake, 1 << 19, 3, ctypes.byref(rate), None) == binding.E_WORKSPACE
     assert b"probe" in lib.plast_last_error()
-    assert set(binding.PROBES) == {"valu_i32", "valu_pk_i16", "valu_pk_f16", "lds_lookup", "hbm_copy", "lds_b64"}
-    assert lib.plast_probe_peak(6, fake, 1 << 30, 3, ctypes.byref(rate), None) == binding.E_ARG
+    assert set(binding.PROBES) == {"valu_i32", "valu_pk_i16", "valu_pk_f16", "lds_lookup", "hbm_copy", "lds_b64",
+                                   "sclk"}
+    # the clock probe needs 32 KiB for its counters beyond the 2 MiB of the compute probes
+    assert lib.plast_probe_peak(6, fake, 2 << 20, 3, ctypes.byref(rate), None) == binding.E_WORKSPACE
