@@ -666,12 +666,28 @@ __device__ __forceinline__ SideStats align_side(const AlignArgs& A, const uint8_
   int prev = 0;            // last move: 0 none, 1 D, 2 E, 3 F
   int run_a = -1, run_b = -1, run_diag = 0;  // current piece: positions in a (inclusive)
   int blk_s = -1, blk_g0 = 0;
+  // the two sequences from their first letter (x and y start at the seed, or
+  // at the letters before it)
+  const uint8_t* aseq = x - (dir > 0 ? p1 : p1 - 1);
+  const uint8_t* bseq = y - (dir > 0 ? p2 : p2 - 1);
+  // a piece ends: its identities are counted by the whole wavefront, 64
+  // letter pairs at a time
   auto close_run = [&]() {
     if (run_a >= 0) {
-      const int k = np;
-      if (k < A.max_pieces) {
-        if (lane == 0) P[k] = Piece{run_diag, min(run_a, run_b), max(run_a, run_b) + 1, owner};
-        np = k + 1;
+      const int lo = min(run_a, run_b), len = max(run_a, run_b) + 1 - lo;
+      int same = 0;
+      for (int k0 = 0; k0 < len; k0 += 64) {
+        const int k = k0 + lane;
+        const bool eq = k < len && aseq[lo + k] == bseq[lo + k - run_diag];
+        same += __popcll(__ballot(eq));
+      }
+      st.ident += same;
+      st.mism += len - same;
+      st.length += len;
+      const int q = np;
+      if (q < A.max_pieces) {
+        if (lane == 0) P[q] = Piece{run_diag, lo, lo + len, owner};
+        np = q + 1;
       } else if (lane == 0) {
         atomicOr(status, 2);
       }
@@ -696,11 +712,10 @@ __device__ __forceinline__ SideStats align_side(const AlignArgs& A, const uint8_
         if (blk_g0 + c < nu8) walk[c * 64 + lane] = src[c * 64 + lane];
       __syncthreads();
     }
-    const uint32_t nib = (walk[(g - blk_g0) * 64 + r] >> ((u & 7) * 4)) & 15u;
+    const uint32_t nib = (uint32_t)uni((int)((walk[(g - blk_g0) * 64 + r] >> ((u & 7) * 4)) & 15u));
     if (state == 0) {
       const uint32_t src = nib & 3u;
       if (src == 0) {
-        const int xa = x[(int64_t)(i - 1) * dx], yc = yo[64 + j];
         const int pa = dir > 0 ? p1 + i - 1 : p1 - i;
         const int pb = dir > 0 ? p2 + j - 1 : p2 - j;
         if (run_a < 0) {
@@ -708,9 +723,6 @@ __device__ __forceinline__ SideStats align_side(const AlignArgs& A, const uint8_
           run_diag = pa - pb;
         }
         run_b = pa;
-        if (xa == yc) st.ident++;
-        else st.mism++;
-        st.length++;
         prev = 1;
         --i;
         --j;
