@@ -17,7 +17,7 @@
 // strips of 64 rows (one row per lane) across the columns as a skewed front:
 // at step t lane r holds column t - r; H (less the gap-opening cost) and F move
 // one lane down per step through a wavefront DPP shift, and the strip's last
-// row waits in LDS for the next strip.  A score pass over the whole matrix
+// row waits in a per-wavefront global buffer for the next strip.  A score pass over the whole matrix
 // finds the best and its end cell; a trace pass over the rectangle up to the
 // end cell stores a 4-bit trace per cell (source of H; whether E and F opened)
 // in a per-wavefront buffer; the trace-back reads it through an LDS window of
@@ -77,10 +77,15 @@ struct AlignArgs {
 };
 
 struct AlignLayout {
-  size_t hdr, tbl, hidx, klo, khi, perm0, perm1, counts, pcount, scan_tmp, heads, tb, pieces, total;
+  size_t hdr, tbl, hidx, klo, khi, perm0, perm1, counts, pcount, scan_tmp, heads, tb, pieces, strip, total;
   int64_t tiles;
   size_t tb_words_per_wave;
 };
+
+// Columns of a wavefront's strip buffer (the row above the current strip, as
+// (H' - open, F') per column, with the columns the front's last steps read),
+// a multiple of 8 so that every wavefront's buffer starts on 64 bytes.
+__host__ __device__ int64_t strip_cols(int max_len2) { return ((int64_t)max_len2 + 72 + 7) & ~(int64_t)7; }
 
 int bits_for(int64_t v) {  // bits needed for values 0..v
   int b = 0;
@@ -128,27 +133,33 @@ AlignLayout align_layout(int64_t n, const plast_align_params_t& p, int64_t waves
   off = align_up(off + sizeof(uint32_t) * L.tb_words_per_wave * (size_t)waves, 256);
   L.pieces = off;
   off = align_up(off + sizeof(Piece) * (size_t)p.max_pieces * (size_t)waves, 256);
+  L.strip = off;
+  off = align_up(off + sizeof(int2) * (size_t)strip_cols(p.max_len2) * (size_t)waves, 256);
   L.total = off;
   return L;
 }
 
 // LDS of one alignment workgroup: the strip's per-lane profile, y letters by
-// column, and the row above the current strip (with padding), whose space the
-// trace-back window reuses once the DP is done.  The score table the profiles
-// are built from and the x letters stay in global memory (read once per strip,
-// and once per step of the trace-back): the kernel is bound by the latency of
-// its per-step chain, so every workgroup more per CU counts (13 per CU at 1000
-// letters of bank b).
-size_t strip_bytes(int max_len2) {
-  const size_t b = sizeof(int2) * ((size_t)max_len2 + 72);
-  return b > sizeof(uint32_t) * kWalkDwords ? b : sizeof(uint32_t) * kWalkDwords;
-}
-
+// column and the trace-back window.  The score table the profiles are built
+// from, the x letters and the row above the current strip stay in global
+// memory (the row above is read one block of 8 columns ahead): the kernel
+// needs as many resident wavefronts as the registers allow (12 per CU), and
+// with the row above in LDS it had 10.
 size_t align_lds_bytes(int max_len2) {
   size_t b = 21 * 64 * kProfLaneBytes;
   b += align_up((size_t)max_len2 + 136, 16);   // y letters, 64 sentinels before column 0
-  b += strip_bytes(max_len2);
+  b += sizeof(uint32_t) * kWalkDwords;         // trace-back window
   return b;
+}
+
+// The row above a strip for the 8 columns of block t8 (all lanes load it; only
+// lane 0 uses it).
+__device__ __forceinline__ void feed_load(const int2* strip, int t8, int4& a, int4& b, int4& c, int4& d) {
+  const int4* sf = (const int4*)(strip + t8);
+  a = sf[0];
+  b = sf[1];
+  c = sf[2];
+  d = sf[3];
 }
 
 __device__ __forceinline__ int seq_len(const int64_t* start, int s) {
@@ -363,14 +374,15 @@ __device__ __forceinline__ void side_dp(int lx, int ly, int steps, int ge, int g
     uint32_t* tbs = tb + (size_t)s * nu8 * 64 + lane;
     const int sbase = s << 16;
     const bool my_row = TRACE && s * 64 + lane + 1 == row;
-    // Only lane 0 uses the block's inputs from LDS (the others take theirs
-    // from the lane above), but every lane loads them: the registers are then
-    // fresh each block and the DPP shifts, whose lane 0 keeps the old value,
-    // write into them without a copy.  The broadcast costs LDS bandwidth the
-    // kernel has to spare (its bound is the latency of the per-step chain).
+    // Only lane 0 uses the block's inputs (the others take theirs from the
+    // lane above), but every lane loads them: the registers are then fresh
+    // each block and the DPP shifts, whose lane 0 keeps the old value, write
+    // into them without a copy.  They are loaded one block ahead.
+    int4 n0, n1, n2, n3;
+    feed_load(strip, 0, n0, n1, n2, n3);
     for (int t8 = 0; t8 < steps; t8 += 8) {
-      const int4* sf = (const int4*)(strip + t8);
-      const int4 s0 = sf[0], s1 = sf[1], s2 = sf[2], s3 = sf[3];
+      const int4 s0 = n0, s1 = n1, s2 = n2, s3 = n3;
+      if (t8 + 8 < steps) feed_load(strip, t8 + 8, n0, n1, n2, n3);
       const int fh[8] = {s0.x, s0.z, s1.x, s1.z, s2.x, s2.z, s3.x, s3.z};
       const int ff[8] = {s0.y, s0.w, s1.y, s1.w, s2.y, s2.w, s3.y, s3.w};
       int sc[8];
@@ -426,6 +438,7 @@ __device__ __forceinline__ void side_dp(int lx, int ly, int steps, int ge, int g
         }
       }
     }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     __syncthreads();
   }
 }
@@ -488,9 +501,11 @@ __device__ __forceinline__ void side_score8(int s0, int lx, int ly, int steps, i
   int hup = kANeg, flast = kANeg;
   const uint8_t* ycol = yo + 64 - lane;
   const uint32_t* pl = prof + lane;
+  int4 n0, n1, n2, n3;  // the row above, one block ahead (see side_dp)
+  feed_load(strip, 0, n0, n1, n2, n3);
   for (int t8 = 0; t8 < steps; t8 += 8) {
-    const int4* sf = (const int4*)(strip + t8);
-    const int4 s0v = sf[0], s1v = sf[1], s2v = sf[2], s3v = sf[3];
+    const int4 s0v = n0, s1v = n1, s2v = n2, s3v = n3;
+    if (t8 + 8 < steps) feed_load(strip, t8 + 8, n0, n1, n2, n3);
     const int fh[8] = {s0v.x, s0v.z, s1v.x, s1v.z, s2v.x, s2v.z, s3v.x, s3v.z};
     const int ff[8] = {s0v.y, s0v.w, s1v.y, s1v.w, s2v.y, s2v.w, s3v.y, s3v.w};
     uint32_t yw[2];
@@ -545,6 +560,7 @@ __device__ __forceinline__ void side_score8(int s0, int lx, int ly, int steps, i
       }
     }
   }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < R; ++q) {
@@ -567,6 +583,7 @@ __device__ __forceinline__ void side_pad(int ly, int steps, int go, uint8_t* yo,
   if (lane == 0) yo[64] = (uint8_t)kPadCode;
   for (int k = lane; k < steps; k += 64)
     strip[k] = make_int2(k == 0 ? -go : (k <= ly ? -2 * go : kANeg), kANeg);
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
   __syncthreads();
 }
 
@@ -767,17 +784,17 @@ __global__ __launch_bounds__(64) void k_align_table(AlignArgs A, int16_t* __rest
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_align(
     AlignArgs A, const int16_t* __restrict__ T, const plast_hit_t* hits, const int32_t* hidx, const int32_t* perm,
     const uint64_t* khi, const int32_t* heads, AlignHeader* hdr, uint32_t* tb_all, size_t tb_words, Piece* pieces_all,
-    plast_alignment_t* out, int32_t* cover) {
+    int2* strip_all, plast_alignment_t* out, int32_t* cover) {
   extern __shared__ __align__(16) uint8_t lds[];
   int16_t* prof = (int16_t*)lds;
   uint8_t* yo = (uint8_t*)lds + 21 * 64 * kProfLaneBytes;
-  int2* strip = (int2*)(yo + ((A.max_len2 + 136 + 15) & ~15));
-  uint32_t* walk = (uint32_t*)strip;  // the trace-back runs after the DP of its side
+  uint32_t* walk = (uint32_t*)(yo + ((A.max_len2 + 136 + 15) & ~15));
   const int lane = threadIdx.x;
   __syncthreads();
 
   uint32_t* tb = tb_all + (size_t)blockIdx.x * tb_words;
   Piece* P = pieces_all + (size_t)blockIdx.x * A.max_pieces;
+  int2* strip = strip_all + (size_t)blockIdx.x * (size_t)strip_cols(A.max_len2);
   const int64_t m = (int64_t)hdr->n_pass;
   const int64_t n_groups = (int64_t)hdr->n_groups;
   for (;;) {
@@ -958,7 +975,8 @@ int align_impl(const plast_index_t* a, const plast_index_t* b, const plast_hit_t
     hipLaunchKernelGGL(k_align_table, dim3(1), dim3(64), 0, s, A, tbl);
     timing_mark(kStageAlign, false, s);
     hipLaunchKernelGGL(k_align, dim3((unsigned)waves), dim3(64), lds, s, A, (const int16_t*)tbl, d_hits, hidx,
-                       perm[cur], khi, heads, hdr, tb, L.tb_words_per_wave, pieces, d_out, d_cover);
+                       perm[cur], khi, heads, hdr, tb, L.tb_words_per_wave, pieces, (int2*)(ws + L.strip), d_out,
+                       d_cover);
     timing_mark(kStageAlign, true, s);
     PLAST_HIP(hipGetLastError());
     PLAST_HIP(hipMemcpyAsync(&h0, hdr, sizeof(h0), hipMemcpyDeviceToHost, s));
