@@ -378,11 +378,16 @@ __device__ __forceinline__ void side_dp(int lx, int ly, int steps, int ge, int g
     // lane above), but every lane loads them: the registers are then fresh
     // each block and the DPP shifts, whose lane 0 keeps the old value, write
     // into them without a copy.  They are loaded one block ahead.
+    // The last strip's rows sit in its first `lanes` lanes and no strip reads
+    // its last row, so it ends once lane lanes - 1 has passed column ly.
+    const bool last = s + 1 == strips;
+    const int lanes = last ? lx - s * 64 : 64;
+    const int steps_s = last ? min(steps, (ly + lanes + 7) & ~7) : steps;
     int4 n0, n1, n2, n3;
     feed_load(strip, 0, n0, n1, n2, n3);
-    for (int t8 = 0; t8 < steps; t8 += 8) {
+    for (int t8 = 0; t8 < steps_s; t8 += 8) {
       const int4 s0 = n0, s1 = n1, s2 = n2, s3 = n3;
-      if (t8 + 8 < steps) feed_load(strip, t8 + 8, n0, n1, n2, n3);
+      if (t8 + 8 < steps_s) feed_load(strip, t8 + 8, n0, n1, n2, n3);
       const int fh[8] = {s0.x, s0.z, s1.x, s1.z, s2.x, s2.z, s3.x, s3.z};
       const int ff[8] = {s0.y, s0.w, s1.y, s1.w, s2.y, s2.w, s3.y, s3.w};
       int sc[8];
@@ -425,7 +430,7 @@ __device__ __forceinline__ void side_dp(int lx, int ly, int steps, int ge, int g
         best = bmax;
         bpos = sbase + t8 + 1;
       }
-      if (lane == 63) {  // lane 63 finished columns t8 - 63 .. t8 - 56 of the strip's last row
+      if (!last && lane == 63) {  // lane 63 finished columns t8 - 63 .. t8 - 56 of the strip's last row
         if (t8 >= 63 && t8 - 56 <= ly) {
 #pragma unroll
           for (int k = 0; k < 8; ++k) strip[t8 + k - 63] = make_int2(oh[k], of[k]);
@@ -501,11 +506,16 @@ __device__ __forceinline__ void side_score8(int s0, int lx, int ly, int steps, i
   int hup = kANeg, flast = kANeg;
   const uint8_t* ycol = yo + 64 - lane;
   const uint32_t* pl = prof + lane;
+  // the last strip ends once its last lane with rows has passed column ly
+  // (see side_dp)
+  const bool last = s0 + 64 * R >= lx;
+  const int lanes = last ? (lx - s0 + R - 1) / R : 64;
+  const int steps_s = last ? min(steps, (ly + lanes + 7) & ~7) : steps;
   int4 n0, n1, n2, n3;  // the row above, one block ahead (see side_dp)
   feed_load(strip, 0, n0, n1, n2, n3);
-  for (int t8 = 0; t8 < steps; t8 += 8) {
+  for (int t8 = 0; t8 < steps_s; t8 += 8) {
     const int4 s0v = n0, s1v = n1, s2v = n2, s3v = n3;
-    if (t8 + 8 < steps) feed_load(strip, t8 + 8, n0, n1, n2, n3);
+    if (t8 + 8 < steps_s) feed_load(strip, t8 + 8, n0, n1, n2, n3);
     const int fh[8] = {s0v.x, s0v.z, s1v.x, s1v.z, s2v.x, s2v.z, s3v.x, s3v.z};
     const int ff[8] = {s0v.y, s0v.w, s1v.y, s1v.w, s2v.y, s2v.w, s3v.y, s3v.w};
     uint32_t yw[2];
@@ -547,7 +557,7 @@ __device__ __forceinline__ void side_score8(int s0, int lx, int ly, int steps, i
         rpos[q] = t8;
       }
     }
-    if (lane == 63) {  // the strip's last row, columns t8 - 63 .. t8 - 56
+    if (!last && lane == 63) {  // the strip's last row, columns t8 - 63 .. t8 - 56
       if (t8 >= 63 && t8 - 56 <= ly) {
 #pragma unroll
         for (int k = 0; k < 8; ++k) strip[t8 + k - 63] = make_int2(oh[k], of[k]);
