@@ -722,6 +722,16 @@ __device__ __forceinline__ SideStats align_side(const AlignArgs& A, const uint8_
     }
   };
   while (i > 0 || j > 0) {
+    // the walk's state is the same in every lane: keep it scalar
+    i = uni(i);
+    j = uni(j);
+    state = uni(state);
+    prev = uni(prev);
+    run_a = uni(run_a);
+    run_b = uni(run_b);
+    run_diag = uni(run_diag);
+    blk_s = uni(blk_s);
+    blk_g0 = uni(blk_g0);
     if (i == 0 || j == 0) {  // the rest is one gap along row 0 or column 0
       const int mv = i == 0 ? 2 : 3;
       close_run();
