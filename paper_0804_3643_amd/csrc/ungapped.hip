@@ -97,7 +97,8 @@ struct __align__(16) Smem {
   int32_t hit_seq[kHitSlots];
   int32_t hit_pos[kHitSlots];
   int32_t n_hit;                       // slots reserved so far in this item
-  int32_t n_fit;                       // end of the last reservation that fitted
+  int32_t n_fit;                       // start of the reservation that straddles the end of the staging
+                                       // area (kHitSlots if none)
   int32_t n_flush;                     // staged hits of the item being flushed
   int32_t item;
   unsigned long long hit_base;
@@ -146,18 +147,8 @@ __device__ __forceinline__ void smem_init(const UngappedArgs& A, Smem& S) {
   }
   if (threadIdx.x == 0) {
     S.n_hit = 0;
-    S.n_fit = 0;
+    S.n_fit = kHitSlots;
   }
-}
-
-__device__ __forceinline__ int wave_incl_scan(int v) {
-  const int lane = __lane_id();
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    int t = __shfl_up(v, o);
-    if (lane >= o) v += t;
-  }
-  return v;
 }
 
 // Rows of the tile (bank-a occurrences row0 .. row0+rows-1 of the key) and
@@ -305,22 +296,18 @@ __device__ __forceinline__ void for_each_hit(const vec2<F16> (&m)[kPairs], uint3
   }
 }
 
+// Each lane with hits reserves its slots with one LDS atomic (hits are rare:
+// a few lanes of a wavefront per column).  Reservations grow monotonically,
+// so the ones that fit form a prefix of the staging area; the one that
+// straddles its end (at most one) records where the prefix stops, and it and
+// every later one write their hits directly.
 template <bool F16>
 __device__ __forceinline__ void emit_hits(const UngappedArgs& A, Smem& S, const vec2<F16> (&m)[kPairs],
                                           uint32_t mask, int s2, int p2) {
-  const int lane = __lane_id();
-  if (!__ballot(mask != 0)) return;
+  if (!mask) return;
   const int cnt = __popc(mask);
-  const int incl = wave_incl_scan(cnt);
-  const int total = __shfl(incl, 63);
-  int base = 0;
-  if (lane == 63) {
-    base = atomicAdd(&S.n_hit, total);
-    if (base + total <= kHitSlots) atomicMax(&S.n_fit, base + total);
-  }
-  base = __shfl(base, 63);
-  if (base + total <= kHitSlots) {  // staged in LDS
-    int at = base + incl - cnt;
+  int at = atomicAdd(&S.n_hit, cnt);
+  if (at + cnt <= kHitSlots) {  // staged in LDS
     for_each_hit<F16>(m, mask, [&](int r, int score) {
       S.hit_rs[at] = (uint32_t)r | ((uint32_t)score << 5);
       S.hit_seq[at] = s2;
@@ -328,9 +315,8 @@ __device__ __forceinline__ void emit_hits(const UngappedArgs& A, Smem& S, const 
       ++at;
     });
   } else {  // staging area full: write directly
-    unsigned long long g = 0;
-    if (lane == 63) g = atomicAdd(A.n_hits, (unsigned long long)total);
-    g = __shfl(g, 63) + (unsigned long long)(incl - cnt);
+    if (at < kHitSlots) S.n_fit = at;
+    unsigned long long g = atomicAdd(A.n_hits, (unsigned long long)cnt);
     for_each_hit<F16>(m, mask, [&](int r, int score) {
       if (g < (unsigned long long)A.capacity) {
         plast_hit_t h;
@@ -355,7 +341,7 @@ __device__ __forceinline__ void flush_hits(const UngappedArgs& A, Smem& S) {
     S.n_flush = n;
     S.hit_base = n ? atomicAdd(A.n_hits, (unsigned long long)n) : 0ull;
     S.n_hit = 0;
-    S.n_fit = 0;
+    S.n_fit = kHitSlots;
   }
   __syncthreads();
   const int n = __builtin_amdgcn_readfirstlane(S.n_flush);
