@@ -284,16 +284,34 @@ __device__ __forceinline__ uint32_t hit_mask(uint32_t thr, const vec2<F16> (&m)[
 // Hit rows of this lane in register order (rows 2i and 2i+1 from register i);
 // every register index is a compile-time constant, and a block whose bits are
 // clear in every lane of the wavefront is skipped as a whole.
+// `any` is the OR of every lane's mask, so the test of a register is a
+// scalar branch and only the registers that hold a hit in some lane cost
+// vector instructions.
 template <bool F16, typename Put>
-__device__ __forceinline__ void for_each_hit(const vec2<F16> (&m)[kPairs], uint32_t mask, Put put) {
+__device__ __forceinline__ void for_each_hit(const vec2<F16> (&m)[kPairs], uint32_t mask, uint32_t any, Put put) {
 #pragma unroll
   for (int i = 0; i < kPairs; ++i) {
-    const uint32_t bits = mask & ((1u << i) | (1u << (16 + i)));
-    if (bits) {
+    const uint32_t sel = (1u << i) | (1u << (16 + i));
+    if (any & sel) {
+      const uint32_t bits = mask & sel;
       if (bits & (1u << i)) put(2 * i, to_int<F16>(m[i], 0));
       if (bits >> 16) put(2 * i + 1, to_int<F16>(m[i], 1));
     }
   }
+}
+
+// OR of v over the wavefront: an inclusive OR-scan of each row of 16 lanes
+// (wavefront DPP row shifts), then the row totals broadcast down (row_bcast
+// 15 and 31); lane 63 holds the result.
+__device__ __forceinline__ uint32_t wave_or(uint32_t v) {
+  int x = (int)v;
+  x |= __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);  // row_shr:1
+  x |= __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);  // row_shr:2
+  x |= __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);  // row_shr:4
+  x |= __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);  // row_shr:8
+  x |= __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  x |= __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  return (uint32_t)__builtin_amdgcn_readlane(x, 63);
 }
 
 // Each lane with hits reserves its slots with one LDS atomic (hits are rare:
@@ -304,11 +322,12 @@ __device__ __forceinline__ void for_each_hit(const vec2<F16> (&m)[kPairs], uint3
 template <bool F16>
 __device__ __forceinline__ void emit_hits(const UngappedArgs& A, Smem& S, const vec2<F16> (&m)[kPairs],
                                           uint32_t mask, int s2, int p2) {
-  if (!mask) return;
+  const uint32_t any = wave_or(mask);  // every lane of the wavefront takes part
+  if (!any || !mask) return;
   const int cnt = __popc(mask);
   int at = atomicAdd(&S.n_hit, cnt);
   if (at + cnt <= kHitSlots) {  // staged in LDS
-    for_each_hit<F16>(m, mask, [&](int r, int score) {
+    for_each_hit<F16>(m, mask, any, [&](int r, int score) {
       S.hit_rs[at] = (uint32_t)r | ((uint32_t)score << 5);
       S.hit_seq[at] = s2;
       S.hit_pos[at] = p2;
@@ -317,7 +336,7 @@ __device__ __forceinline__ void emit_hits(const UngappedArgs& A, Smem& S, const 
   } else {  // staging area full: write directly
     if (at < kHitSlots) S.n_fit = at;
     unsigned long long g = atomicAdd(A.n_hits, (unsigned long long)cnt);
-    for_each_hit<F16>(m, mask, [&](int r, int score) {
+    for_each_hit<F16>(m, mask, any, [&](int r, int score) {
       if (g < (unsigned long long)A.capacity) {
         plast_hit_t h;
         h.seq1 = S.rowseq[r];
