@@ -256,13 +256,16 @@ __device__ __forceinline__ void scan_window(const Smem& S, const uint32_t (&win)
   }
 }
 
-// Bit layout of the row mask: bit i (i < 16) is row 2i (low half of register
-// i), bit 16 + i is row 2i + 1 (high half).
+// Bit layout of the row mask: row r is bit 8 (r & 3) + (r >> 2), so that the
+// sign bits of four rows (two registers) land in one byte-permuted dword at
+// bits 7, 15, 23, 31 and one shift and one and-or place them (hit_mask).
+__host__ __device__ constexpr uint32_t row_bit(int r) { return 1u << (8 * (r & 3) + (r >> 2)); }
+
 __device__ __forceinline__ uint32_t valid_rows_mask(int rows) {
   uint32_t m = 0;
 #pragma unroll
   for (int r = 0; r < kTileRows; ++r)
-    if (r < rows) m |= 1u << ((r >> 1) + ((r & 1) << 4));
+    if (r < rows) m |= row_bit(r);
   return m;
 }
 
@@ -270,13 +273,16 @@ template <bool F16>
 __device__ __forceinline__ uint32_t hit_mask(uint32_t thr, const vec2<F16> (&m)[kPairs]) {
   typedef vec2<F16> V;
   const V th = as_vec<F16>(thr);
+  uint32_t d[kPairs];
+#pragma unroll
+  for (int i = 0; i < kPairs; ++i) d[i] = __builtin_bit_cast(uint32_t, th - m[i]);  // negative where best >= s1
   uint32_t mask = 0;
 #pragma unroll
-  for (int i = 0; i < kPairs; ++i) {
-    const V diff = th - m[i];                                       // negative where best >= s1
-    const uint32_t d = __builtin_bit_cast(uint32_t, diff);
-    const uint32_t rot = __builtin_amdgcn_alignbit(d, d, 15 - i);  // bit 15 -> i, bit 31 -> 16 + i
-    mask |= rot & ((1u << i) | (1u << (16 + i)));
+  for (int k = 0; k < kPairs / 2; ++k) {
+    // the high bytes of both halves of registers 2k and 2k + 1: the sign bits
+    // of rows 4k .. 4k + 3 at bits 7, 15, 23, 31
+    const uint32_t w = __builtin_amdgcn_perm(d[2 * k + 1], d[2 * k], 0x07050301u);
+    mask |= (w >> (7 - k)) & (0x01010101u << k);
   }
   return mask;
 }
@@ -291,11 +297,10 @@ template <bool F16, typename Put>
 __device__ __forceinline__ void for_each_hit(const vec2<F16> (&m)[kPairs], uint32_t mask, uint32_t any, Put put) {
 #pragma unroll
   for (int i = 0; i < kPairs; ++i) {
-    const uint32_t sel = (1u << i) | (1u << (16 + i));
-    if (any & sel) {
-      const uint32_t bits = mask & sel;
-      if (bits & (1u << i)) put(2 * i, to_int<F16>(m[i], 0));
-      if (bits >> 16) put(2 * i + 1, to_int<F16>(m[i], 1));
+    const uint32_t lo = row_bit(2 * i), hi = row_bit(2 * i + 1);
+    if (any & (lo | hi)) {
+      if (mask & lo) put(2 * i, to_int<F16>(m[i], 0));
+      if (mask & hi) put(2 * i + 1, to_int<F16>(m[i], 1));
     }
   }
 }
