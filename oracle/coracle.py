@@ -30,23 +30,28 @@ def build(force: bool = True) -> str:
     return LIB
 
 
+def declare(lib):
+    """Set the argument and result types of the library's entry points on a
+    ctypes handle (of liborc.so, or of another build of the same source)."""
+    P = ctypes.c_void_p
+    i32, i64 = ctypes.c_int32, ctypes.c_int64
+    lib.orc_build_index.restype = i64
+    lib.orc_build_index.argtypes = [P, P, i32, i32, P, P, P]
+    lib.orc_ungapped.restype = i64
+    lib.orc_ungapped.argtypes = [P, P, i32, P, P, P, P, P, i32, P, P, P, i32, P, i32, i32, i32, P, i32,
+                                 i32, P, i64, P]
+    lib.orc_gapped.restype = None
+    lib.orc_gapped.argtypes = [P, P, P, P, i32, P, i64, P, i32, i32, i32, i32, i32, P]
+    lib.orc_full_align.restype = i64
+    lib.orc_full_align.argtypes = [P, P, P, P, i32, P, P, P, i64, P, i32, i32, i32, P, P]
+    return lib
+
+
 def load():
     global _lib
     if _lib is None:
         build(force=False)
-        lib = ctypes.CDLL(LIB)
-        P = ctypes.c_void_p
-        i32, i64 = ctypes.c_int32, ctypes.c_int64
-        lib.orc_build_index.restype = i64
-        lib.orc_build_index.argtypes = [P, P, i32, i32, P, P, P]
-        lib.orc_ungapped.restype = i64
-        lib.orc_ungapped.argtypes = [P, P, i32, P, P, P, P, P, i32, P, P, P, i32, P, i32, i32, i32, P, i32,
-                                     i32, P, i64, P]
-        lib.orc_gapped.restype = None
-        lib.orc_gapped.argtypes = [P, P, P, P, i32, P, i64, P, i32, i32, i32, i32, i32, P]
-        lib.orc_full_align.restype = i64
-        lib.orc_full_align.argtypes = [P, P, P, P, i32, P, P, P, i64, P, i32, i32, i32, P, P]
-        _lib = lib
+        _lib = declare(ctypes.CDLL(LIB))
     return _lib
 
 

@@ -337,6 +337,25 @@ def test_gapped_poly_a_and_swap_symmetry():
         assert O.gapped_side(x, y, 5, 11, 1) == O.gapped_side(y, x, 5, 11, 1)
 
 
+def test_gapped_band_edge_closed_form():
+    """x = W^20, y = G^17 W^20, anchored at both starts (no left side).  Putting
+    all 20 W/W pairs (11 each) on one diagonal needs y's 17 Gs against a gap
+    (11 + 17): 220 - 28 = 192, which takes cells |i - j| = 17.  Within a band of
+    16 the best shift is 16 diagonals (27), after which x's first W meets y's
+    last G (-2) and 19 W/W pairs follow: 209 - 27 - 2 = 180.  Every form of the
+    filter (scalar, vectorised, C) must draw the band at exactly |i - j| <= band."""
+    W, G = O.ALPHABET.index("W"), O.ALPHABET.index("G")
+    x = np.full(20, W, np.int64)
+    y = np.concatenate([np.full(17, G, np.int64), np.full(20, W, np.int64)])
+    assert O.gapped_side(x, y, 16) == 180 and O.gapped_side(x, y, 17) == 192
+    b1 = synth.Bank.from_strings(["W" * 20])
+    b2 = synth.Bank.from_strings(["G" * 17 + "W" * 20])
+    hit = np.array([[0, 0, 0, 0, 0]])
+    for band, exp in ((16, 180), (17, 192)):
+        assert O.gapped_scores(b1, b2, hit, band=band).tolist() == [exp]
+        assert C.gapped_scores(b1, b2, hit, band=band, nthreads=1).tolist() == [exp]
+
+
 def test_gapped_vectorised_and_c_match_scalar(cfg0):
     h, _ = C.ungapped_hits(cfg0.bank1, cfg0.bank2, params.S1)
     sample = h[:: max(1, len(h) // 60)]
@@ -354,6 +373,55 @@ def test_gapped_dominates_ungapped_on_same_windows(cfg0):
     h, _ = C.ungapped_hits(cfg0.bank1, cfg0.bank2, params.S1)
     g = C.gapped_scores(cfg0.bank1, cfg0.bank2, h)
     assert (g >= h[:, 4]).all()
+
+
+# ----------------------------------------------------------------------------- matrix orientation
+
+def _asymmetric():
+    """BLOSUM62 with M[A, C] = +6 and M[C, A] = -6: the first index is the
+    bank-1 (x) letter, the second the bank-2 (y) letter."""
+    m = O.BLOSUM62.copy()
+    A, Cl = O.ALPHABET.index("A"), O.ALPHABET.index("C")
+    m[A, Cl], m[Cl, A] = 6, -6
+    return m
+
+
+def _orientation_banks():
+    # one pair of sequences whose only shared seed word is WWWW at position 20:
+    # every other word pair differs in its first or last letter
+    return (synth.Bank.from_strings(["A" * 20 + "WWWW" + "A" * 24]),
+            synth.Bank.from_strings(["C" * 20 + "WWWW" + "C" * 24]))
+
+
+def test_matrix_orientation_closed_forms():
+    """x = A..A against y = C..C scores +6 per pair with the matrix read as
+    M[x letter, y letter] and -6 read the other way round, so every stage's
+    score has a closed form that a transposed operand misses.  Ungapped:
+    4 W/W pairs (44) + 20 rightward and 20 leftward A/C pairs (6 each) = 284.
+    Gapped and full: the whole diagonal of both windows, 44 + 24 * 6 rightward
+    and 20 * 6 leftward = 308, with no gap and 4 identities."""
+    m = _asymmetric()
+    b1, b2 = _orientation_banks()
+    a, b = O.sequences(b1)[0], O.sequences(b2)[0]
+    assert O.ungapped_score(a, 20, b, 20, m) == 284
+    exp = np.array([[0, 20, 0, 20, 284]])
+    assert np.array_equal(O.ungapped_hits(b1, b2, 0, matrix=m), exp)
+    assert np.array_equal(C.ungapped_hits(b1, b2, 0, matrix=m, nthreads=1)[0], exp)
+    for n in range(6):
+        for k in range(6):
+            x, y = np.zeros(n, np.int64), np.ones(k, np.int64)
+            assert O.gapped_side(x, y, 2, 11, 1, m) == 6 * min(n, k)
+            assert O.full_side(x, y, 11, 1, m)[0] == 6 * min(n, k)
+    assert O.gapped_score(a, 20, b, 20, matrix=m) == 308
+    assert O.gapped_scores(b1, b2, exp, matrix=m).tolist() == [308]
+    assert C.gapped_scores(b1, b2, exp, matrix=m, nthreads=1).tolist() == [308]
+    F = {k: i for i, k in enumerate(O.ALIGN_FIELDS)}
+    for rec, cover in (O.full_alignments(b1, b2, exp, [308], [True], matrix=m),
+                       C.full_alignments(b1, b2, exp, [308], [True], matrix=m, nthreads=1)):
+        assert cover.tolist() == [0] and len(rec) == 1
+        r = rec[0]
+        assert (r[F["score"]], r[F["start1"]], r[F["end1"]], r[F["start2"]], r[F["end2"]]) == (308, 0, 48, 0, 48)
+        assert (r[F["length"]], r[F["identities"]], r[F["mismatches"]], r[F["gap_opens"]]) == (48, 4, 44, 0)
 
 
 # ----------------------------------------------------------------------------- generator

@@ -34,13 +34,59 @@ def _all_paths(x, y, go, ge):
     return out
 
 
+def _rule_path(paths, end, top, go):
+    """The trace-back rule applied to the enumerated paths.  Reading backward from
+    the end cell among the optimal paths into it, each step takes the first move
+    kind (in the order below) that one of them continues with: after a pair (or
+    at the end cell) a pair, then y against a gap (E), then x against a gap (F);
+    inside an E run, ending the run (a pair, then F) before extending it; inside
+    an F run, a pair, then E, then extending.  With no opening cost every run may
+    end at every cell, so inside a run the order after a pair applies."""
+    cands = [p for i, j, s, p in paths if (i, j) == end and s == top]
+    suffix = ""
+    while suffix not in cands:
+        live = [p for p in cands if p.endswith(suffix)]
+        nxt = {p[-len(suffix) - 1] for p in live if len(p) > len(suffix)}
+        order = "DFE" if suffix[:1] == "E" and go > 0 else "DEF"
+        suffix = next(c for c in order if c in nxt) + suffix
+    return suffix
+
+
+def _path_record(x, y, path):
+    """(end1, end2, length, identities, mismatches, gap openings) of a path read
+    from the anchor at the starts of x and y."""
+    i = j = ident = mism = opens = 0
+    prev = None
+    for m in path:
+        if m == "D":
+            ident += int(x[i] == y[j])
+            mism += int(x[i] != y[j])
+            i, j = i + 1, j + 1
+        else:
+            opens += int(m != prev)
+            i, j = i + (m == "F"), j + (m == "E")
+        prev = m
+    return i, j, len(path), ident, mism, opens
+
+
 def test_full_side_equals_exhaustive_enumeration():
+    """The Python full side, and the C one through a one-hit alignment anchored at
+    the starts of both sequences, against every path enumerated."""
     rng = np.random.default_rng(11)
-    for case in range(200):
+    by_cost = {}
+    # pairs where two optimal paths into the end cell differ in length and gap
+    # openings, so that the rule's choice shows in the record (gaps 3 + 2 k)
+    fixed = [("CAG", "WACG"), ("GGWC", "WGC"), ("AGCWG", "WCG")]
+    for case in range(300 + len(fixed)):
         lx, ly = int(rng.integers(0, 6)), int(rng.integers(0, 6))
         x = rng.integers(0, 20 if case % 3 else 3, lx)
         y = rng.integers(0, 20 if case % 3 else 3, ly)
+        if case % 5 == 4:  # W and P only: W/W 11, P/P 7, W/P -4, frequent ties between paths
+            x, y = 18 * (x % 2) + 12 * (1 - x % 2), 18 * (y % 2) + 12 * (1 - y % 2)
         go, ge = [(11, 1), (1, 1), (0, 2), (3, 0)][case % 4]
+        if case >= 300:
+            x, y = _enc(fixed[case - 300][0]), _enc(fixed[case - 300][1])
+            lx, ly, go, ge = len(x), len(y), 3, 2
         best, end, moves = O.full_side(x, y, go, ge)
         paths = _all_paths(x, y, go, ge)
         top = max(p[2] for p in paths)
@@ -48,9 +94,23 @@ def test_full_side_equals_exhaustive_enumeration():
         # end cell: first cell in row-major order reached by an optimal path
         first = min((i, j) for i, j, s, _ in paths if s == top)
         assert end == first
-        # the traced path is one of the optimal paths into the end cell
-        assert ("".join(moves)) in {p for i, j, s, p in paths if (i, j) == end and s == top}
+        # the traced path is the optimal path into the end cell that the rule picks
+        rule = _rule_path(paths, end, top, go)
+        assert "".join(moves) == rule, (x, y, go, ge)
         assert O.path_score(x, y, moves, go, ge) == best
+        if lx and ly:
+            by_cost.setdefault((go, ge), []).append((x, y, top, rule))
+    F = {k: i for i, k in enumerate(O.ALIGN_FIELDS)}
+    cols = [F[k] for k in ("end1", "end2", "length", "identities", "mismatches", "gap_opens")]
+    for (go, ge), cases in by_cost.items():
+        b1 = synth.Bank.from_flat(np.concatenate([c[0] for c in cases]), [len(c[0]) for c in cases])
+        b2 = synth.Bank.from_flat(np.concatenate([c[1] for c in cases]), [len(c[1]) for c in cases])
+        hits = np.array([(k, 0, k, 0, 0) for k in range(len(cases))], dtype=np.int64)
+        rec, cover = C.full_alignments(b1, b2, hits, np.zeros(len(cases)), np.ones(len(cases), bool), go, ge)
+        assert cover.tolist() == list(range(len(cases)))
+        rec = rec[np.argsort(rec[:, F["hit"]])]
+        for r, (x, y, top, rule) in zip(rec, cases):
+            assert r[F["score"]] == top and tuple(r[cols]) == _path_record(x, y, rule), (x, y, go, ge)
 
 
 def test_full_side_hand_example_one_gap():
@@ -62,6 +122,19 @@ def test_full_side_hand_example_one_gap():
     assert best == 10 * 11 - 12 == 98
     assert end == (10, 11)
     assert "".join(moves) == "DDDDDEDDDDD"
+
+
+def test_full_side_hand_example_gap_tie():
+    """x = PPW, y = WPW with gaps of 1 per letter and no opening cost.  The first
+    pair P/W scores -4, a gap on either side -1, so cell (1, 1) holds -2 both from
+    the left (E: y's W against a gap, after x's P against one) and from above
+    (F).  Then P/P (7) and W/W (11): best 16 at (3, 3), against 14 for the plain
+    diagonal.  Tracing back, cell (1, 1) is in state H, not on the diagonal, and
+    the rule takes E before F; read from the anchor the path is x's P against a
+    gap, y's W against a gap, then the two pairs."""
+    best, end, moves = O.full_side(_enc("PPW"), _enc("WPW"), 0, 1)
+    assert best == -1 - 1 + 7 + 11 == 16 and end == (3, 3)
+    assert "".join(moves) == "FEDD"
 
 
 def test_full_side_closed_forms():
@@ -222,3 +295,27 @@ def test_stage32_numpy_and_c_oracles_agree(cfg0_stage32):
     rc, cc = C.full_alignments(w.bank1, w.bank2, h, g, mask)
     assert len(rp) > 10
     assert np.array_equal(rp, rc) and np.array_equal(cp, cc)
+
+
+def test_stage32_c_matches_python_on_tiny_random_pairs():
+    """The C oracle against the pinned Python one on small random sequence pairs
+    over four letters (W, A, G, C: many equal-score paths, so the trace-back
+    rule decides the records), several hits per pair, all passing."""
+    rng = np.random.default_rng(21)
+    letters = [AL.index(c) for c in "WAGC"]
+    n = 400
+    seqs1 = [rng.choice(letters, int(rng.integers(1, 10))) for _ in range(n)]
+    seqs2 = [rng.choice(letters, int(rng.integers(1, 10))) for _ in range(n)]
+    bank1 = synth.Bank.from_flat(np.concatenate(seqs1), [len(s) for s in seqs1])
+    bank2 = synth.Bank.from_flat(np.concatenate(seqs2), [len(s) for s in seqs2])
+    hits = []
+    for s in range(n):
+        for _ in range(int(rng.integers(1, 4))):
+            hits.append((s, int(rng.integers(0, len(seqs1[s]))), s, int(rng.integers(0, len(seqs2[s]))), 0))
+    hits = np.array(hits, dtype=np.int64)
+    g = rng.integers(0, 50, len(hits))
+    ps = np.ones(len(hits), dtype=bool)
+    for go, ge in ((11, 1), (3, 2), (1, 1)):
+        rp, cp = O.full_alignments(bank1, bank2, hits, g, ps, go, ge)
+        rc, cc = C.full_alignments(bank1, bank2, hits, g, ps, go, ge, nthreads=2)
+        assert np.array_equal(rp, rc) and np.array_equal(cp, cc), (go, ge)
