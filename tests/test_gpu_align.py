@@ -92,6 +92,35 @@ def test_align_edge_cases(B):
     assert (rec[:, F["end1"]] - rec[:, F["start1"]] > 1000).any()  # the long pair aligned end to end
 
 
+def test_align_trace_back_ties(B):
+    """Pairs with several optimal paths into the end cell.  Three short pairs
+    whose optimal paths differ in length and gap openings (gaps of 3 + 2 k), so
+    the record shows which path the trace-back took, and 300 random short pairs
+    over W, A, G and C with hits at random positions (both sides), against the
+    C oracle under two gap costs."""
+    rng = np.random.default_rng(33)
+    enc = lambda t: np.array([O.ALPHABET.index(c) for c in t], dtype=np.uint8)
+    letters = np.array([O.ALPHABET.index(c) for c in "WAGC"], dtype=np.uint8)
+    xs = [enc("CAG"), enc("GGWC"), enc("AGCWG")] + [rng.choice(letters, int(rng.integers(1, 12))) for _ in range(300)]
+    ys = [enc("WACG"), enc("WGC"), enc("WCG")] + [rng.choice(letters, int(rng.integers(1, 12))) for _ in range(300)]
+    bank1, bank2 = _bank(xs), _bank(ys)
+    ia = B.build_index(*B.bank_to_device(bank1, "cuda"))
+    ib = B.build_index(*B.bank_to_device(bank2, "cuda"))
+    h = [(k, 0, k, 0, 0) for k in range(3)]
+    for k in range(3, len(xs)):
+        for _ in range(int(rng.integers(1, 3))):
+            h.append((k, int(rng.integers(0, len(xs[k]))), k, int(rng.integers(0, len(ys[k]))), 0))
+    hits = torch.tensor(h, dtype=torch.int32, device="cuda")
+    gs = torch.tensor(rng.integers(0, 60, len(h)), dtype=torch.int32, device="cuda")
+    ps = torch.ones(len(h), dtype=torch.uint8, device="cuda")
+    for go, ge in ((3, 2), (11, 1)):
+        _say("align trace-back ties: %d hits, gaps %d + %d k" % (len(h), go, ge))
+        rec, _ = _assert_parity(B, bank1, bank2, ia, ib, hits, gs, ps, gap_open=go, gap_extend=ge)
+    F = {k: i for i, k in enumerate(O.ALIGN_FIELDS)}
+    first = rec[rec[:, F["hit"]] == 0]
+    assert len(first) == 1 and first[0, F["length"]] > 0
+
+
 def test_align_other_gaps_and_matrix(B, cfg0):
     """Other gap costs and matrices, up to the largest table entries the kernel sees."""
     _say("align cfg0 with gap 5 + 2k and a modified matrix")
