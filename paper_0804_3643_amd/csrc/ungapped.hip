@@ -8,8 +8,9 @@
 // letters).  Each lane owns one bank-b occurrence at a time: its 44-letter
 // window sits in 11 registers as (letter * 8) bytes, so one bit-field extract
 // gives the LDS address of the entry and eight 8-byte LDS reads give the scores
-// of all 32 rows.  Running sums and running bests are packed pairs, two rows per
-// register.  At step 24 the running sum is reset to the running best, so the
+// of all 32 rows (an item with at most 8 or 16 rows, such as the last row tile
+// of a key, builds and scans only 2 or 4 of the 4-row groups).  Running sums
+// and running bests are packed pairs, two rows per register.  At step 24 the running sum is reset to the running best, so the
 // best leftward prefix is added to the best rightward prefix (the composition of
 // the GPU kernel of Annex 4).  Letters outside a sequence are separators scoring
 // kSepScore <= 0 against everything; the separator run after a sequence is at
@@ -63,7 +64,7 @@ constexpr int kProfBytes = kRowGroups * kProfRG;  // 59136
 constexpr int kPairs = 2 * kRowGroups;            // packed registers per lane (16)
 static_assert(kProfBytes + 4096 < 65536, "profile offsets must fit the LDS instruction offset field");
 static_assert(kPadCode * kScale < 256, "scaled codes must fit a byte");
-static_assert(kTileRows == 32 && kPairs == 16, "row mask layout assumes 32 rows");
+static_assert(kTileRows == 32 && kPairs == 16, "row mask layout assumes at most 32 rows");
 static_assert(kSpan * kF16MaxEntry < 1024, "f16 partial sums must stay exact");
 
 struct BankView {
@@ -152,9 +153,10 @@ __device__ __forceinline__ void smem_init(const UngappedArgs& A, Smem& S) {
 }
 
 // Rows of the tile (bank-a occurrences row0 .. row0+rows-1 of the key) and
-// their 44-step profile.  Called by all threads (contains barriers).
+// the 44-step profile of its first `groups` 4-row groups (rows past `rows`
+// hold separators).  Called by all threads (contains barriers).
 __device__ __forceinline__ void build_profile(const UngappedArgs& A, const WorkItem& it, int64_t a0, int rows,
-                                              Smem& S) {
+                                              int groups, Smem& S) {
   const int tid = threadIdx.x;
   if (tid < kTileRows) {
     int q = -1, sq = 0, ps = 0;
@@ -169,8 +171,9 @@ __device__ __forceinline__ void build_profile(const UngappedArgs& A, const WorkI
     S.rowpos[tid] = ps;
   }
   __syncthreads();
-  for (int idx = tid; idx < kSpan * kTileRows; idx += kThreads) {
-    int t = idx / kTileRows, r = idx - t * kTileRows;
+  const int nr = 4 * groups;
+  for (int idx = tid; idx < kSpan * nr; idx += kThreads) {
+    int t = idx / nr, r = idx - t * nr;
     int q = S.rowq[r];
     int letter = kPadCode;
     if (q >= 0) {
@@ -181,7 +184,7 @@ __device__ __forceinline__ void build_profile(const UngappedArgs& A, const WorkI
   }
   __syncthreads();
   // prof[rg][t][c] = scores of rows 4rg..4rg+3 at step t against bank-b letter c
-  for (int e = tid; e < kRowGroups * kSpan * kNLet; e += kThreads) {
+  for (int e = tid; e < groups * kSpan * kNLet; e += kThreads) {
     int rg = e / (kSpan * kNLet);
     int rem = e - rg * (kSpan * kNLet);
     int t = rem / kNLet;
@@ -199,41 +202,42 @@ __device__ __forceinline__ void build_profile(const UngappedArgs& A, const WorkI
   __syncthreads();
 }
 
-// The 44-step scan of one bank-b window against the 32 profile rows.
+// The 44-step scan of one bank-b window against the first 4 RG profile rows.
 // win: the window as (letter * 8) bytes, byte b = position q - 20 + b.
 // m receives best-right + best-left of every row (register i: rows 2i, 2i+1).
-template <bool F16>
-__device__ __forceinline__ void scan_window(const Smem& S, const uint32_t (&win)[11], vec2<F16> (&m)[kPairs]) {
+template <bool F16, int RG>
+__device__ __forceinline__ void scan_window(const Smem& S, const uint32_t (&win)[11], vec2<F16> (&m)[2 * RG]) {
   typedef vec2<F16> V;
-  V s[kPairs];
-  uint2 cur[kRowGroups], nxt[kRowGroups];
-  auto load = [&](int t, uint2(&dst)[kRowGroups]) {
+  constexpr int NP = 2 * RG;
+  V s[NP];
+  uint2 cur[RG], nxt[RG];
+  auto load = [&](int t, uint2(&dst)[RG]) {
     const int bidx = t < kRight ? kNbr + t : (kSpan - 1) - t;
     const uint32_t c8 = (win[bidx >> 2] >> (8 * (bidx & 3))) & 0xffu;
     const uint8_t* p = S.prof + c8 + t * kProfT;
 #pragma unroll
-    for (int rg = 0; rg < kRowGroups; ++rg) dst[rg] = *(const uint2*)(p + rg * kProfRG);
+    for (int rg = 0; rg < RG; ++rg) dst[rg] = *(const uint2*)(p + rg * kProfRG);
   };
-  auto val = [&](const uint2(&src)[kRowGroups], int i) {
+  auto val = [&](const uint2(&src)[RG], int i) {
     return as_vec<F16>((i & 1) ? src[i >> 1].y : src[i >> 1].x);
   };
   const V zero = {0, 0};
   load(0, cur);
   load(1, nxt);
 #pragma unroll
-  for (int i = 0; i < kPairs; ++i) s[i] = val(cur, i);
+  for (int i = 0; i < NP; ++i) s[i] = val(cur, i);
 #pragma unroll
-  for (int rg = 0; rg < kRowGroups; ++rg) cur[rg] = nxt[rg];
+  for (int rg = 0; rg < RG; ++rg) cur[rg] = nxt[rg];
   // Steps 1 .. 43; the scores of step t are in cur when step t is applied.
 #pragma unroll
   for (int t = 1; t < kSpan; ++t) {
     if (t + 1 < kSpan) load(t + 1, nxt);
     if (t == kRight) {
 #pragma unroll
-      for (int i = 0; i < kPairs; ++i) s[i] = m[i];  // best right prefix, then left
+      for (int i = 0; i < NP; ++i) s[i] = m[i];  // best right prefix, then left
     }
 #pragma unroll
-    for (int i = 0; i < kPairs; ++i) {
+    for (int i = 0; i < NP; ++i) {
       const V prev = s[i];
       s[i] = prev + val(cur, i);
       if constexpr (F16) {
@@ -251,7 +255,7 @@ __device__ __forceinline__ void scan_window(const Smem& S, const uint32_t (&win)
     }
     if (t + 1 < kSpan) {
 #pragma unroll
-      for (int rg = 0; rg < kRowGroups; ++rg) cur[rg] = nxt[rg];
+      for (int rg = 0; rg < RG; ++rg) cur[rg] = nxt[rg];
     }
   }
 }
@@ -269,16 +273,16 @@ __device__ __forceinline__ uint32_t valid_rows_mask(int rows) {
   return m;
 }
 
-template <bool F16>
-__device__ __forceinline__ uint32_t hit_mask(uint32_t thr, const vec2<F16> (&m)[kPairs]) {
+template <bool F16, int RG>
+__device__ __forceinline__ uint32_t hit_mask(uint32_t thr, const vec2<F16> (&m)[2 * RG]) {
   typedef vec2<F16> V;
   const V th = as_vec<F16>(thr);
-  uint32_t d[kPairs];
+  uint32_t d[2 * RG];
 #pragma unroll
-  for (int i = 0; i < kPairs; ++i) d[i] = __builtin_bit_cast(uint32_t, th - m[i]);  // negative where best >= s1
+  for (int i = 0; i < 2 * RG; ++i) d[i] = __builtin_bit_cast(uint32_t, th - m[i]);  // negative where best >= s1
   uint32_t mask = 0;
 #pragma unroll
-  for (int k = 0; k < kPairs / 2; ++k) {
+  for (int k = 0; k < RG; ++k) {
     // the high bytes of both halves of registers 2k and 2k + 1: the sign bits
     // of rows 4k .. 4k + 3 at bits 7, 15, 23, 31
     const uint32_t w = __builtin_amdgcn_perm(d[2 * k + 1], d[2 * k], 0x07050301u);
@@ -293,10 +297,10 @@ __device__ __forceinline__ uint32_t hit_mask(uint32_t thr, const vec2<F16> (&m)[
 // `any` is the OR of every lane's mask, so the test of a register is a
 // scalar branch and only the registers that hold a hit in some lane cost
 // vector instructions.
-template <bool F16, typename Put>
-__device__ __forceinline__ void for_each_hit(const vec2<F16> (&m)[kPairs], uint32_t mask, uint32_t any, Put put) {
+template <bool F16, int RG, typename Put>
+__device__ __forceinline__ void for_each_hit(const vec2<F16> (&m)[2 * RG], uint32_t mask, uint32_t any, Put put) {
 #pragma unroll
-  for (int i = 0; i < kPairs; ++i) {
+  for (int i = 0; i < 2 * RG; ++i) {
     const uint32_t lo = row_bit(2 * i), hi = row_bit(2 * i + 1);
     if (any & (lo | hi)) {
       if (mask & lo) put(2 * i, to_int<F16>(m[i], 0));
@@ -324,15 +328,15 @@ __device__ __forceinline__ uint32_t wave_or(uint32_t v) {
 // so the ones that fit form a prefix of the staging area; the one that
 // straddles its end (at most one) records where the prefix stops, and it and
 // every later one write their hits directly.
-template <bool F16>
-__device__ __forceinline__ void emit_hits(const UngappedArgs& A, Smem& S, const vec2<F16> (&m)[kPairs],
+template <bool F16, int RG>
+__device__ __forceinline__ void emit_hits(const UngappedArgs& A, Smem& S, const vec2<F16> (&m)[2 * RG],
                                           uint32_t mask, int s2, int p2) {
   const uint32_t any = wave_or(mask);  // every lane of the wavefront takes part
   if (!any || !mask) return;
   const int cnt = __popc(mask);
   int at = atomicAdd(&S.n_hit, cnt);
   if (at + cnt <= kHitSlots) {  // staged in LDS
-    for_each_hit<F16>(m, mask, any, [&](int r, int score) {
+    for_each_hit<F16, RG>(m, mask, any, [&](int r, int score) {
       S.hit_rs[at] = (uint32_t)r | ((uint32_t)score << 5);
       S.hit_seq[at] = s2;
       S.hit_pos[at] = p2;
@@ -341,7 +345,7 @@ __device__ __forceinline__ void emit_hits(const UngappedArgs& A, Smem& S, const 
   } else {  // staging area full: write directly
     if (at < kHitSlots) S.n_fit = at;
     unsigned long long g = atomicAdd(A.n_hits, (unsigned long long)cnt);
-    for_each_hit<F16>(m, mask, any, [&](int r, int score) {
+    for_each_hit<F16, RG>(m, mask, any, [&](int r, int score) {
       if (g < (unsigned long long)A.capacity) {
         plast_hit_t h;
         h.seq1 = S.rowseq[r];
@@ -391,18 +395,14 @@ __device__ __forceinline__ void load_window_raw(const UngappedArgs& A, int q2, u
   for (int i = 0; i < 12; ++i) raw[i] = src[i];
 }
 
-// All threads of the workgroup call run_item with the same item (it contains
-// barriers); every branch around a barrier depends only on wave-uniform values.
-template <bool F16>
-__device__ void run_item(const UngappedArgs& A, const WorkItem it, Smem& S) {
+// The item's columns against its first 4 RG rows (rows <= 4 RG), then the
+// flush of its hits.  Called by all threads (contains barriers).
+template <bool F16, int RG>
+__device__ void run_tile(const UngappedArgs& A, const WorkItem& it, int64_t a0, int64_t b0, int rows, Smem& S) {
   const int tid = threadIdx.x;
   const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int64_t a0 = A.a.key_off[it.key];
-  const int n1 = (int)(A.a.key_off[it.key + 1] - a0);
-  const int rows = min(kTileRows, n1 - it.row0);
-  const int64_t b0 = A.b.key_off[it.key];
   const uint32_t valid = valid_rows_mask(rows);
-  build_profile(A, it, a0, rows, S);
+  build_profile(A, it, a0, rows, RG, S);
 
   // Lane columns: col0 + tid + kThreads * k.  Column data is software-pipelined:
   // the occurrence two columns ahead and the window one column ahead are in
@@ -446,12 +446,30 @@ __device__ void run_item(const UngappedArgs& A, const WorkItem it, Smem& S) {
       s_nxt = A.b.occ_seq[o];
     }
     const int st2 = (int)A.b.seq_start[s2];
-    vec2<F16> m[kPairs];
-    scan_window<F16>(S, win, m);
-    const uint32_t mask = active ? (hit_mask<F16>(A.thr, m) & valid) : 0u;
-    emit_hits<F16>(A, S, m, mask, s2, q2 - st2);
+    vec2<F16> m[2 * RG];
+    scan_window<F16, RG>(S, win, m);
+    const uint32_t mask = active ? (hit_mask<F16, RG>(A.thr, m) & valid) : 0u;
+    emit_hits<F16, RG>(A, S, m, mask, s2, q2 - st2);
   }
   flush_hits(A, S);
+}
+
+// All threads of the workgroup call run_item with the same item (it contains
+// barriers); every branch around a barrier depends only on wave-uniform values.
+// A tile with at most 8 or 16 rows (the last row tile of a key, and most tiles
+// of a small query bank) scans only those rows: 2 or 4 row groups.
+template <bool F16>
+__device__ void run_item(const UngappedArgs& A, const WorkItem it, Smem& S) {
+  const int64_t a0 = A.a.key_off[it.key];
+  const int n1 = (int)(A.a.key_off[it.key + 1] - a0);
+  const int rows = __builtin_amdgcn_readfirstlane(min(kTileRows, n1 - it.row0));
+  const int64_t b0 = A.b.key_off[it.key];
+  if (rows <= 8)
+    run_tile<F16, 2>(A, it, a0, b0, rows, S);
+  else if (rows <= 16)
+    run_tile<F16, 4>(A, it, a0, b0, rows, S);
+  else
+    run_tile<F16, kRowGroups>(A, it, a0, b0, rows, S);
 }
 
 constexpr int kPlainCols = 4096;  // item width of the PLAIN schedule
