@@ -8,9 +8,9 @@
 // letters).  Each lane owns one bank-b occurrence at a time: its 44-letter
 // window sits in 11 registers as (letter * 8) bytes, so one bit-field extract
 // gives the LDS address of the entry and eight 8-byte LDS reads give the scores
-// of all 32 rows (an item with at most 8 or 16 rows, such as the last row tile
-// of a key, builds and scans only 2 or 4 of the 4-row groups).  Running sums
-// and running bests are packed pairs, two rows per register.  At step 24 the running sum is reset to the running best, so the
+// of all 32 rows (an item with at most 4, 8, 12 or 16 rows, such as the last
+// row tile of a key, builds and scans only that many rows, in 4-row groups).
+// Running sums and running bests are packed pairs, two rows per register.  At step 24 the running sum is reset to the running best, so the
 // best leftward prefix is added to the best rightward prefix (the composition of
 // the GPU kernel of Annex 4).  Letters outside a sequence are separators scoring
 // kSepScore <= 0 against everything; the separator run after a sequence is at
@@ -456,16 +456,20 @@ __device__ void run_tile(const UngappedArgs& A, const WorkItem& it, int64_t a0, 
 
 // All threads of the workgroup call run_item with the same item (it contains
 // barriers); every branch around a barrier depends only on wave-uniform values.
-// A tile with at most 8 or 16 rows (the last row tile of a key, and most tiles
-// of a small query bank) scans only those rows: 2 or 4 row groups.
+// A tile with at most 4, 8, 12 or 16 rows (the last row tile of a key, and
+// most tiles of a small query bank) scans only 1, 2, 3 or 4 row groups.
 template <bool F16>
 __device__ void run_item(const UngappedArgs& A, const WorkItem it, Smem& S) {
   const int64_t a0 = A.a.key_off[it.key];
   const int n1 = (int)(A.a.key_off[it.key + 1] - a0);
   const int rows = __builtin_amdgcn_readfirstlane(min(kTileRows, n1 - it.row0));
   const int64_t b0 = A.b.key_off[it.key];
-  if (rows <= 8)
+  if (rows <= 4)
+    run_tile<F16, 1>(A, it, a0, b0, rows, S);
+  else if (rows <= 8)
     run_tile<F16, 2>(A, it, a0, b0, rows, S);
+  else if (rows <= 12)
+    run_tile<F16, 3>(A, it, a0, b0, rows, S);
   else if (rows <= 16)
     run_tile<F16, 4>(A, it, a0, b0, rows, S);
   else
