@@ -362,7 +362,7 @@ __device__ __forceinline__ void gapped_hit_f16(const GappedArgs& G, const uint32
     // kAhead pairs before the pair is computed (they depend on letters only).
     constexpr int kPairs = (kGCells + 1) / 2;
     constexpr int kSeq = kFBlock * kPairs;
-    constexpr int kAhead = 3;
+    constexpr int kAhead = 5;
     uint32_t A[kSeq], B[kSeq];
     auto issue = [&](int q) {
       const int r = q / kPairs, p = q % kPairs;
