@@ -146,6 +146,36 @@ def test_ungapped_multi_tile_ragged(B, mode):
     assert np.array_equal(B.canonical_hits(hits), ref)
 
 
+def test_ungapped_row_tile_sizes(B):
+    """Keys with exactly 1, 4, 5, 8, 9, 12, 13, 16, 17, 31, 32, 33 and 64 bank-1
+    occurrences (each bank-1 sequence is one 4-letter word), so that every
+    size of row tile the kernel has (4, 8, 12, 16 and 32 rows) meets its full
+    and its one-past-full row count; with s1 = 4 every candidate pair is a hit,
+    so every row of every tile reports."""
+    _say("ungapped row-tile sizes")
+    rng = np.random.default_rng(17)
+    counts = [1, 4, 5, 8, 9, 12, 13, 16, 17, 31, 32, 33, 64]
+    words = []
+    while len(words) < len(counts):  # words of pairwise different keys
+        w = rng.integers(0, 20, 4)
+        if all(O.seed_key(*w) != O.seed_key(*v) for v in words):
+            words.append(w)
+    seqs1 = [w for w, n in zip(words, counts) for _ in range(n)]
+    seqs2 = [np.concatenate([rng.integers(0, 20, int(rng.integers(0, 30))), w, rng.integers(0, 20, int(rng.integers(0, 30)))])
+             for w in words for _ in range(7)]
+    b1 = synth.Bank.from_flat(np.concatenate(seqs1), [4] * len(seqs1))
+    b2 = synth.Bank.from_flat(np.concatenate(seqs2), [len(x) for x in seqs2])
+    ia, ib = _index(B, b1), _index(B, b2)
+    n1 = np.diff(ia.key_off().cpu().numpy())
+    assert sorted(n1[n1 > 0].tolist()) == counts
+    ref, ref_ext = C.ungapped_hits(b1, b2, 4)
+    assert len(ref) == ref_ext
+    for mode in ("plain", "batched"):
+        hits, n_ext = B.ungapped_extend(ia, ib, 4, mode=mode)
+        assert n_ext == ref_ext
+        assert np.array_equal(B.canonical_hits(hits), ref)
+
+
 def test_ungapped_threshold_4_is_every_candidate_pair(B):
     """Score >= 4 always, so s1 = 4 must return every candidate pair exactly once:
     the work decomposition covers each (key, i, j) once."""
