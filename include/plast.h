@@ -79,8 +79,9 @@ typedef struct {
  * Launch shapes (performance only: every valid tuning gives the same results).
  * Keys are put in size classes by n2, their number of bank-b occurrences: key
  * k is in class c iff class_min_n2[c] <= n2 < class_min_n2[c + 1] (the last
- * class is open above).  A BATCHED work item covers 32 bank-a occurrences and
- * up to item_cols[c] bank-b occurrences of one key.  xcd_queues = 8 splits the
+ * class is open above).  A BATCHED work item covers up to 32 bank-a
+ * occurrences (the last item of a key fewer) and up to item_cols[c] bank-b
+ * occurrences of one key.  xcd_queues = 8 splits the
  * work list into one contiguous queue per XCD (workgroup w starts on queue
  * w mod 8 and then steals from the others), so the items sharing bank-b
  * windows run under one L2; 1 keeps a single queue.  gapped_threads is the
