@@ -345,6 +345,10 @@ __device__ __forceinline__ void gapped_hit_f16(const GappedArgs& G, const uint32
 #pragma unroll
   for (int t = 0; t < kAcc; ++t) acc[t] = NEG;
   int i0 = 1;
+  // shift of anti-diagonal 2 i0 - 16 of the current block, (2 i0 - 16) * extend,
+  // stepped by extend per anti-diagonal (integers below 2048: exact in binary16)
+  const gh2 EX = {ex, ex};
+  gh2 sh = gh2{(_Float16)(2 - kGMaxBand), (_Float16)(2 - kGMaxBand)} * EX;
   const char* tb = (const char*)tbl;
   // One block of kFBlock rows starting at row i0.  BLK >= 0 names the block
   // (rows 4 BLK + 1 ..) at compile time: its cells outside every window are
@@ -409,11 +413,10 @@ __device__ __forceinline__ void gapped_hit_f16(const GappedArgs& G, const uint32
     }
     // anti-diagonals below 2 (i0 + 4) - 16 are complete: unshift and fold into best
     {
-      const _Float16 base = (_Float16)(2 * i0 - kGMaxBand);
 #pragma unroll
       for (int t = 0; t < kAccShift; ++t) {
-        const _Float16 o = (base + (_Float16)t) * ex;
-        best = gmax(best, acc[t] - gh2{o, o});
+        best = gmax(best, acc[t] - sh);
+        sh = sh + EX;  // after the block: the shift of the next block's first anti-diagonal
       }
 #pragma unroll
       for (int t = 0; t < kAcc; ++t) acc[t] = t + kAccShift < kAcc ? acc[t + kAccShift] : NEG;
@@ -456,13 +459,10 @@ __device__ __forceinline__ void gapped_hit_f16(const GappedArgs& G, const uint32
   if constexpr (kTailBlocks >= 3) peeled(std::integral_constant<int, kNBlocks - 3>{});
   if constexpr (kTailBlocks >= 2) peeled(std::integral_constant<int, kNBlocks - 2>{});
   if constexpr (kTailBlocks >= 1) peeled(std::integral_constant<int, kNBlocks - 1>{});
-  {
-    const _Float16 base = (_Float16)(2 * i0 - kGMaxBand);
 #pragma unroll
-    for (int t = 0; t < kAcc; ++t) {
-      const _Float16 o = (base + (_Float16)t) * ex;
-      best = gmax(best, acc[t] - gh2{o, o});
-    }
+  for (int t = 0; t < kAcc; ++t) {
+    best = gmax(best, acc[t] - sh);
+    sh = sh + EX;
   }
   if (live) {
     const int total = sane ? (int)best.x + (int)best.y : -1;
