@@ -77,14 +77,15 @@ def kernel_source_hash(src=KERNEL_SRC):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def recorded_traffic(path, src=KERNEL_SRC):
+def recorded_traffic(path, src=KERNEL_SRC, key="traffic_bytes_per_launch"):
     """HBM bytes per launch of a kernel from a committed rocprofv3 counter
-    summary, if it was taken on the current kernel source."""
+    summary, if it was taken on the current kernel source (``key`` names the
+    figure, e.g. the one for a given workgroup size)."""
     if not os.path.exists(path):
         return None
     txt = open(path).read()
     m = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", txt)
-    b = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    b = re.search(r"^%s:\s*([0-9.eE+]+)" % re.escape(key), txt, re.M)
     if not m or not b or m.group(1) != kernel_source_hash(src):
         return None
     return float(b.group(1))
@@ -964,6 +965,7 @@ def main():
 
     achieved = n_ext * OPS_PER_EXT / (batched_kernel_ms * 1e-3) / 1e12
     lds_achieved = n_ext * LDS_BYTES_PER_EXT / (batched_kernel_ms * 1e-3) / 1e12
+    gapped_threads = (tuning if tuning is not None else B.tuning_default()).as_dict()["gapped_threads"]
     gapped_kernel_ms = float(np.mean(stage_ms["gapped_ms"]))
     h_host = host_b[0].numpy()
     cells = gapped_cells(np, w.bank1, w.bank2, h_host)
@@ -1038,7 +1040,8 @@ def main():
                        "peak": PEAK_INT16_TOPS, "unit": "TOP/s", "frac": gapped_achieved / PEAK_INT16_TOPS,
                        "kernel_ms": gapped_kernel_ms, "dp_cells": cells, "ops_per_cell": GAPPED_OPS_PER_CELL,
                        "traffic": recorded_traffic(traffic_file("gapped", args.config),
-                                                   os.path.join(ROOT, "paper_0804_3643_amd", "csrc", "gapped.hip"))},
+                                                   os.path.join(ROOT, "paper_0804_3643_amd", "csrc", "gapped.hip"),
+                                                   "traffic_bytes_per_launch_threads_%d" % gapped_threads)},
         },
         "cpu_baseline": None,
         "stage32": stage32,
