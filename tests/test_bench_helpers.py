@@ -95,3 +95,23 @@ def test_golden_check_accepts_the_oracle_and_rejects_a_slip(cfg0, cfg0_hits):
     assert not bad["equal"] and "hits_gscore" in bad["mismatch"]
     assert not bench.golden_check("0", h, g, params.S2, n_ext + 1, cfg0.bank1, sha)["equal"]
     assert not bench.golden_check("0", h, g, params.S2, n_ext, cfg0.bank1, sha[::-1])["equal"]
+
+
+def test_recorded_traffic_reads_the_figure_of_the_current_source(tmp_path):
+    """A counter summary gives its figure only for the kernel source it was taken
+    on, and the gapped filter's only for the workgroup size asked for."""
+    src = tmp_path / "k.hip"
+    src.write_text("kernel text\n")
+    h = bench.kernel_source_hash(str(src))
+    f = tmp_path / "t.md"
+    f.write_text("# summary\n\nkernel_source_sha256_16: %s\ntraffic_bytes_per_launch: 1.5e+10\n"
+                 "traffic_bytes_per_launch_threads_256: 2.5e+10\n" % h)
+    assert bench.recorded_traffic(str(f), str(src)) == 1.5e10
+    assert bench.recorded_traffic(str(f), str(src), "traffic_bytes_per_launch_threads_256") == 2.5e10
+    assert bench.recorded_traffic(str(f), str(src), "traffic_bytes_per_launch_threads_512") is None
+    src.write_text("kernel text, changed\n")
+    assert bench.recorded_traffic(str(f), str(src)) is None
+    # the committed summaries carry one figure per gapped workgroup size
+    txt = open(bench.traffic_file("gapped", 2)).read()
+    for nt in (128, 256, 512):
+        assert "traffic_bytes_per_launch_threads_%d:" % nt in txt
