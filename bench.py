@@ -1023,6 +1023,11 @@ def main():
             "kernel_ms": batched_kernel_ms, "extensions_per_launch": n_ext,
             "measured_peak": peaks["valu_pk_f16"]["rate"] / 1e12,
             "frac_of_measured_peak": achieved / (peaks["valu_pk_f16"]["rate"] / 1e12),
+            "note": "88 algorithmic operations per extension (44 additions, 44 maxima) against 2 packed "
+                    "16-bit operations per lane per clock; the kernel's three-way maximum does two maxima "
+                    "per half in one instruction, so this fraction can pass 1 by a little: the instruction "
+                    "stream (about 41 lane instructions per extension, profiles/sq_counters_cfg1.md) uses "
+                    "about 0.9 of the VALU issue slots",
             "with_lookups_as_alu_ops": {
                 "ops_per_ext": OPS_PER_EXT_WITH_LOOKUPS,
                 "achieved": achieved * OPS_PER_EXT_WITH_LOOKUPS / OPS_PER_EXT,
